@@ -1,0 +1,168 @@
+/*
+ * gcb.h -- C ABI of the MI355X (gfx950) library for grouping-circular-based
+ * (GCB) greedy RBF mesh deformation (Fang, Zhang, Shan, Tie, Zhang, Sun,
+ * arXiv:2004.04817).
+ *
+ * The calls follow the paper's statement of the problem: Algorithm 1 takes
+ * the boundary nodes G with displacements dX, dY, dZ, the group count m, the
+ * allowable error E* and the support cap Nc^max, and returns the support set
+ * S with weights W^x, W^y, W^z; Eq. (6) then moves any set of volume points.
+ *
+ * Conventions for every call:
+ *  - Every function returns an int status (enum gcb_status) unless noted.
+ *  - Coordinates and displacements are row-major (x, y, z) triples, float64
+ *    unless a dtype argument says otherwise.
+ *  - `mem` says where a pointer lives: GCB_MEM_HOST (pageable or pinned host
+ *    memory) or GCB_MEM_DEVICE (device memory of the context's device).
+ *  - Inputs are copied; the caller keeps ownership of every buffer it passes.
+ *    Outputs go into caller-allocated buffers of the stated size.
+ *  - A context is not thread-safe; use one context per thread or stream.
+ *  - Device work is enqueued on the context's stream.  Calls with host
+ *    outputs synchronise that stream before returning; calls with device
+ *    outputs return once the work is enqueued.
+ *  - On error nothing is returned through output pointers, and
+ *    gcb_last_error() describes the failure.  No C++ exception crosses this
+ *    interface.  GCB_E_DEVICE means a HIP runtime call failed.
+ */
+#ifndef GCB_H
+#define GCB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gcb_ctx gcb_ctx;
+
+enum gcb_status {
+    GCB_OK = 0,
+    GCB_NOT_CONVERGED = 1, /* warning: |S| reached nc_max while the error exceeded E* */
+    GCB_E_INVALID = -1,    /* argument out of range, NULL pointer, non-finite input */
+    GCB_E_STATE = -2,      /* call out of order (e.g. deform before select) */
+    GCB_E_NOMEM = -3,      /* device or host allocation failed */
+    GCB_E_SINGULAR = -4,   /* the support matrix stopped being numerically SPD */
+    GCB_E_DEVICE = -5      /* a HIP runtime call failed */
+};
+
+enum gcb_mem { GCB_MEM_HOST = 0, GCB_MEM_DEVICE = 1 };
+enum gcb_dtype { GCB_F32 = 0, GCB_F64 = 1 };
+
+/* Evaluation precision of the interpolant sweeps (Eq. 1 / Eq. 6).  The
+ * support-system factor and the final all-node check are FP64 in both. */
+enum gcb_precision {
+    GCB_PREC_FP64 = 0,       /* every sweep in FP64 */
+    GCB_PREC_FP32_EVAL = 1   /* FP32 screening sweeps, FP64 re-check of candidates */
+};
+
+typedef struct {
+    double radius;       /* R, the Wendland C2 support radius (Eq. 2: eta = |r - r_i| / R); > 0 */
+    int32_t m;           /* group count of the stochastic partition, 1 <= m <= nb (m = 1: traditional greedy) */
+    uint64_t seed;       /* partition seed (splitmix64-driven Fisher-Yates shuffle) */
+    double tol_abs;      /* E*, absolute allowable interpolation error (Algorithm 1); >= 0 */
+    int64_t nc_max;      /* Nc^max, cap on |S|; 3 <= nc_max <= nb */
+    int32_t precision;   /* enum gcb_precision */
+    int32_t use_init;    /* 1: start from init_idx; 0: farthest-point rule */
+    int64_t init_idx[3]; /* three distinct boundary indices when use_init = 1 */
+} gcb_params;
+
+typedef struct {
+    int64_t nc;              /* |S| */
+    int64_t iterations;      /* greedy iterations k = 3, 4, ... that ran */
+    int32_t status;          /* GCB_OK or GCB_NOT_CONVERGED */
+    int32_t converged;       /* FP64 all-node max error <= E* */
+    double final_max_err;    /* FP64 certificate: max_j |F(r_j) - d_j|_2 over all nb nodes */
+    double final_rms_err;    /* sqrt(mean_j |F(r_j) - d_j|_2^2) */
+    uint64_t pairs_group;    /* pair evaluations in the group sweeps: sum_k |G_i \ S_k| |S_k| */
+    uint64_t pairs_append;   /* pair evaluations of the appended phi vectors: sum |S| */
+    uint64_t pairs_cert;     /* nb * nc */
+    double ms_select;        /* device wall time of the selection (hipEvents), ms */
+} gcb_select_info;
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue on (NULL: the library creates its own non-blocking stream).
+ * *out receives the context; release it with gcb_destroy. */
+int gcb_create(gcb_ctx **out, int device, void *hip_stream);
+
+/* Free every device and host buffer the context owns.  NULL-safe. */
+void gcb_destroy(gcb_ctx *ctx);
+
+/* Message of the last failed call on ctx (owned by ctx, valid until the next
+ * call).  With ctx = NULL: the message of the last failed gcb_create. */
+const char *gcb_last_error(const gcb_ctx *ctx);
+
+/* Switch the stream later calls enqueue on (NULL: the library's own stream). */
+int gcb_set_stream(gcb_ctx *ctx, void *hip_stream);
+
+/* Boundary nodes G and their prescribed displacements (Algorithm 1 input;
+ * Eq. 3).  xyz and disp are (nb, 3) float64.  nb >= 3; all values finite
+ * (checked).  Resets any previous selection. */
+int gcb_set_boundary(gcb_ctx *ctx, int64_t nb, const double *xyz, const double *disp, int mem);
+
+/* Replace the displacements of the same nodes, (nb, 3) float64.  The
+ * previous selection is dropped; the next gcb_select starts afresh. */
+int gcb_set_displacement(gcb_ctx *ctx, const double *disp, int mem);
+
+/* Algorithm 1 parameters plus R (Eq. 2).  Checked against the boundary when
+ * gcb_select runs. */
+int gcb_set_params(gcb_ctx *ctx, const gcb_params *p);
+
+/* Optional explicit partition: group_of[nb] in [0, m) for the current m.
+ * Pass NULL to return to the seeded partition. */
+int gcb_set_groups(gcb_ctx *ctx, const int32_t *group_of, int mem);
+
+/* Run the GCB greedy selection (Algorithm 1; m = 1 is the traditional
+ * greedy of Rendall and Allen).  Iteration k evaluates the interpolation
+ * error of group G_{k mod m} only, and appends its maximum-error node (ties
+ * to the lowest index, nodes already in S excluded) when that error exceeds
+ * E* and |S| < nc_max.  It stops after m consecutive iterations without an
+ * append, or when an append is refused at the cap (GCB_NOT_CONVERGED).  The
+ * support system Phi_S W = Delta_S (Eqs. 4-5 restricted to S) is kept
+ * factored in FP64 and extended by one row per appended node (the recurrence
+ * idea of Section 1), here as the inverse factor M = L^-1.  A final FP64
+ * sweep over all nb nodes fills final_max_err / final_rms_err.  info may be
+ * NULL.  Returns GCB_OK, GCB_NOT_CONVERGED or an error. */
+int gcb_select(gcb_ctx *ctx, gcb_select_info *info);
+
+/* Selected support nodes in selection order (original boundary indices,
+ * idx[nc] int64) and their weights (w[nc][3] float64); either may be NULL. */
+int gcb_get_support(gcb_ctx *ctx, int64_t *idx, double *w, int mem);
+
+/* Per-iteration record of the last selection into host arrays of length
+ * cap (any may be NULL): group i = k mod m, argmax node (original index, -1
+ * if the group had no candidate), its error E, appended flag.  Returns the
+ * number of iterations (may exceed cap: only cap entries are written), or a
+ * negative status. */
+int64_t gcb_get_log(gcb_ctx *ctx, int32_t *group, int64_t *node, double *err, int8_t *appended, int64_t cap);
+
+/* Eq. (6): displacements of nv arbitrary points from the selected supports:
+ * out[k] = sum_{s in S} w_s phi(|r_k - r_s| / R).  xyz (nv, 3) of in_dtype,
+ * out (nv, 3) of out_dtype (GCB_F32 or GCB_F64), both in `mem`.  Arithmetic
+ * is FP64; nv = 0 is a no-op.  Requires a finished gcb_select. */
+int gcb_deform(gcb_ctx *ctx, int64_t nv, const void *xyz, int in_dtype, void *out, int out_dtype, int mem);
+
+/* Multiple right-hand sides on one support set: k_modes displacement fields
+ * of the same boundary nodes, disp_modes (nb, 3*k_modes) float64 (columns
+ * x, y, z of mode 0, then mode 1, ...), are solved on the selected S (Eqs.
+ * 4-5 restricted to S, FP64 factor) and evaluated at nv points (Eq. 6):
+ * out (nv, 3*k_modes) of out_dtype.  Requires a finished gcb_select. */
+int gcb_deform_multi(gcb_ctx *ctx, int32_t k_modes, const double *disp_modes, int64_t nv, const void *xyz,
+                     int in_dtype, void *out, int out_dtype, int mem);
+
+/* FP64 interpolation error over all nb boundary nodes with the current
+ * support set (the convergence certificate): max and RMS of |F(r_j) - d_j|_2. */
+int gcb_certify(gcb_ctx *ctx, double *max_err, double *rms_err);
+
+/* Host-only: the seeded partition the library uses (Section 3: groups
+ * pairwise disjoint, sizes differ by at most one).  Fisher-Yates shuffle pi
+ * of 0..nb-1 driven by splitmix64(seed), node pi[t] to group t mod m.
+ * group_of[nb] host int32.  Makes no HIP call. */
+int gcb_partition(int64_t nb, int32_t m, uint64_t seed, int32_t *group_of);
+
+/* Host-only: library version string (static storage). */
+const char *gcb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GCB_H */

@@ -1,0 +1,291 @@
+"""Python binding of the MI355X GCB greedy RBF mesh-deformation library.
+
+A thin ctypes layer over ``libgcb.so`` (the C ABI declared in
+``include/gcb.h``): argument marshalling only.  Every step of the method runs
+in the library's HIP kernels.  PyTorch is used, when the caller passes
+tensors, for device memory and the current HIP stream.
+
+The library must be built (``__graft_entry__.build()`` or
+``python paper_2004_04817_amd/build.py``); importing :func:`lib` raises if it
+is missing -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgcb.so")
+
+GCB_OK, GCB_NOT_CONVERGED = 0, 1
+GCB_E_INVALID, GCB_E_STATE, GCB_E_NOMEM, GCB_E_SINGULAR, GCB_E_DEVICE = -1, -2, -3, -4, -5
+GCB_MEM_HOST, GCB_MEM_DEVICE = 0, 1
+GCB_F32, GCB_F64 = 0, 1
+GCB_PREC_FP64, GCB_PREC_FP32_EVAL = 0, 1
+
+EXPORTS = ["gcb_version", "gcb_partition", "gcb_create", "gcb_destroy", "gcb_last_error", "gcb_set_stream",
+           "gcb_set_boundary", "gcb_set_displacement", "gcb_set_params", "gcb_set_groups", "gcb_select",
+           "gcb_get_support", "gcb_get_log", "gcb_deform", "gcb_deform_multi", "gcb_certify"]
+
+
+class GcbError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gcb error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("radius", C.c_double), ("m", C.c_int32), ("seed", C.c_uint64), ("tol_abs", C.c_double),
+                ("nc_max", C.c_int64), ("precision", C.c_int32), ("use_init", C.c_int32),
+                ("init_idx", C.c_int64 * 3)]
+
+
+class SelectInfo(C.Structure):
+    _fields_ = [("nc", C.c_int64), ("iterations", C.c_int64), ("status", C.c_int32), ("converged", C.c_int32),
+                ("final_max_err", C.c_double), ("final_rms_err", C.c_double), ("pairs_group", C.c_uint64),
+                ("pairs_append", C.c_uint64), ("pairs_cert", C.c_uint64), ("ms_select", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_LIB = None
+
+
+def lib():
+    """Load libgcb.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        # PyTorch ships its own HIP runtime with the same soname as the system
+        # one; loading torch first makes libgcb.so bind to that same runtime,
+        # so device pointers and streams from torch are valid in the library
+        # and only one runtime owns the GPU.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        L = C.CDLL(LIB_PATH)
+        vp, i64, i32 = C.c_void_p, C.c_int64, C.c_int32
+        L.gcb_version.restype = C.c_char_p
+        L.gcb_partition.argtypes = [i64, i32, C.c_uint64, vp]
+        L.gcb_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+        L.gcb_destroy.argtypes = [vp]
+        L.gcb_destroy.restype = None
+        L.gcb_last_error.argtypes = [vp]
+        L.gcb_last_error.restype = C.c_char_p
+        L.gcb_set_stream.argtypes = [vp, vp]
+        L.gcb_set_boundary.argtypes = [vp, i64, vp, vp, C.c_int]
+        L.gcb_set_displacement.argtypes = [vp, vp, C.c_int]
+        L.gcb_set_params.argtypes = [vp, C.POINTER(Params)]
+        L.gcb_set_groups.argtypes = [vp, vp, C.c_int]
+        L.gcb_select.argtypes = [vp, C.POINTER(SelectInfo)]
+        L.gcb_get_support.argtypes = [vp, vp, vp, C.c_int]
+        L.gcb_get_log.argtypes = [vp, vp, vp, vp, vp, i64]
+        L.gcb_get_log.restype = i64
+        L.gcb_deform.argtypes = [vp, i64, vp, C.c_int, vp, C.c_int, C.c_int]
+        L.gcb_deform_multi.argtypes = [vp, i32, vp, i64, vp, C.c_int, vp, C.c_int, C.c_int]
+        L.gcb_certify.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        for name in EXPORTS:
+            getattr(L, name)
+        _LIB = L
+    return _LIB
+
+
+def version() -> str:
+    return lib().gcb_version().decode()
+
+
+def partition(nb: int, m: int, seed: int) -> np.ndarray:
+    """The library's seeded partition (host function of the C ABI)."""
+    g = np.empty(nb, dtype=np.int32)
+    rc = lib().gcb_partition(int(nb), int(m), int(seed) & 0xFFFFFFFFFFFFFFFF, g.ctypes.data)
+    if rc != GCB_OK:
+        raise GcbError(rc, "gcb_partition rejected its arguments")
+    return g
+
+
+def _is_tensor(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _arg(x, dtype):
+    """(pointer, mem kind, keep-alive) for a numpy array or a torch tensor."""
+    if _is_tensor(x):
+        import torch
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        want = {np.float64: torch.float64, np.float32: torch.float32, np.int32: torch.int32,
+                np.int64: torch.int64}[dtype]
+        if x.dtype != want:
+            raise ValueError(f"expected {want}, got {x.dtype}")
+        return x.data_ptr(), (GCB_MEM_DEVICE if x.is_cuda else GCB_MEM_HOST), x
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return a.ctypes.data, GCB_MEM_HOST, a
+
+
+def _stream_of(x):
+    if _is_tensor(x) and x.is_cuda:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
+    return None
+
+
+@dataclasses.dataclass
+class Log:
+    group: np.ndarray
+    node: np.ndarray
+    err: np.ndarray
+    appended: np.ndarray
+
+
+class Context:
+    """One GCB problem on one device (wraps a gcb_ctx)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        h = C.c_void_p()
+        rc = lib().gcb_create(C.byref(h), int(device), stream)
+        if rc != GCB_OK:
+            raise GcbError(rc, lib().gcb_last_error(None).decode())
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gcb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def _check(self, rc, ok=(GCB_OK,)):
+        if rc not in ok:
+            raise GcbError(rc, lib().gcb_last_error(self._h).decode())
+        return rc
+
+    def set_stream(self, stream):
+        self._check(lib().gcb_set_stream(self._h, stream))
+
+    def use_current_stream(self, tensor):
+        s = _stream_of(tensor)
+        if s is not None:
+            self.set_stream(s)
+
+    def set_boundary(self, xyz, disp):
+        px, mx, kx = _arg(xyz, np.float64)
+        pd, md, kd = _arg(disp, np.float64)
+        if mx != md:
+            raise ValueError("xyz and disp must live in the same memory")
+        nb = int(kx.shape[0])
+        if tuple(kx.shape) != (nb, 3) or tuple(kd.shape) != (nb, 3):
+            raise ValueError("xyz and disp must be (nb, 3)")
+        self.use_current_stream(kx)
+        self._check(lib().gcb_set_boundary(self._h, nb, px, pd, mx))
+        self.nb = nb
+
+    def set_displacement(self, disp):
+        pd, md, kd = _arg(disp, np.float64)
+        self.use_current_stream(kd)
+        self._check(lib().gcb_set_displacement(self._h, pd, md))
+
+    def set_params(self, radius: float, m: int, tol_abs: float, nc_max: int | None = None, seed: int = 0,
+                   precision: int = GCB_PREC_FP64, init_idx=None):
+        p = Params()
+        p.radius = float(radius)
+        p.m = int(m)
+        p.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        p.tol_abs = float(tol_abs)
+        p.nc_max = int(self.nb if nc_max is None else nc_max)
+        p.precision = int(precision)
+        p.use_init = 0 if init_idx is None else 1
+        if init_idx is not None:
+            for t in range(3):
+                p.init_idx[t] = int(init_idx[t])
+        self._check(lib().gcb_set_params(self._h, C.byref(p)))
+
+    def set_groups(self, group_of):
+        if group_of is None:
+            self._check(lib().gcb_set_groups(self._h, None, GCB_MEM_HOST))
+            return
+        pg, mg, kg = _arg(group_of, np.int32)
+        self._check(lib().gcb_set_groups(self._h, pg, mg))
+
+    def select(self) -> dict:
+        info = SelectInfo()
+        self._check(lib().gcb_select(self._h, C.byref(info)), ok=(GCB_OK, GCB_NOT_CONVERGED))
+        self.nc = info.nc
+        return info.as_dict()
+
+    def get_support(self):
+        idx = np.empty(self.nc, dtype=np.int64)
+        w = np.empty((self.nc, 3), dtype=np.float64)
+        self._check(lib().gcb_get_support(self._h, idx.ctypes.data, w.ctypes.data, GCB_MEM_HOST))
+        return idx, w
+
+    def get_log(self) -> Log:
+        n = lib().gcb_get_log(self._h, None, None, None, None, 0)
+        if n < 0:
+            self._check(int(n))
+        g = np.empty(n, np.int32)
+        nd = np.empty(n, np.int64)
+        e = np.empty(n, np.float64)
+        a = np.empty(n, np.int8)
+        lib().gcb_get_log(self._h, g.ctypes.data, nd.ctypes.data, e.ctypes.data, a.ctypes.data, n)
+        return Log(g, nd, e, a)
+
+    def deform(self, xyz, out=None, out_dtype=None):
+        """Eq. (6) at the points xyz (nv, 3): numpy (host) or torch (host/device)."""
+        if _is_tensor(xyz):
+            import torch
+            in_dt = GCB_F64 if xyz.dtype == torch.float64 else GCB_F32
+            if out is None:
+                odt = torch.float64 if out_dtype in (None, np.float64, torch.float64) else torch.float32
+                out = torch.empty(xyz.shape, dtype=odt, device=xyz.device)
+            px, mx, kx = _arg(xyz, np.float64 if in_dt == GCB_F64 else np.float32)
+            out_dt = GCB_F64 if out.dtype == torch.float64 else GCB_F32
+            po, mo, ko = _arg(out, np.float64 if out_dt == GCB_F64 else np.float32)
+        else:
+            a = np.ascontiguousarray(xyz)
+            in_dt = GCB_F32 if a.dtype == np.float32 else GCB_F64
+            px, mx, kx = _arg(a, np.float32 if in_dt == GCB_F32 else np.float64)
+            if out is None:
+                out = np.empty(a.shape, dtype=np.float32 if out_dtype == np.float32 else np.float64)
+            out_dt = GCB_F32 if out.dtype == np.float32 else GCB_F64
+            po, mo, ko = out.ctypes.data, GCB_MEM_HOST, out
+        if mx != mo:
+            raise ValueError("xyz and out must live in the same memory")
+        nv = int(kx.shape[0])
+        self.use_current_stream(kx)
+        self._check(lib().gcb_deform(self._h, nv, px, in_dt, po, out_dt, mx))
+        return out
+
+    def certify(self):
+        mx, rms = C.c_double(), C.c_double()
+        self._check(lib().gcb_certify(self._h, C.byref(mx), C.byref(rms)))
+        return mx.value, rms.value
+
+
+def select(xyz, disp, radius, m, tol_abs, nc_max=None, seed=0, precision=GCB_PREC_FP64, init_idx=None,
+           group_of=None, device=0):
+    """Convenience: run one selection and return (context, info)."""
+    ctx = Context(device)
+    ctx.set_boundary(xyz, disp)
+    ctx.set_params(radius, m, tol_abs, nc_max=nc_max, seed=seed, precision=precision, init_idx=init_idx)
+    if group_of is not None:
+        ctx.set_groups(group_of)
+    info = ctx.select()
+    return ctx, info

@@ -1,0 +1,107 @@
+// Internal declarations of the MI355X GCB greedy RBF library (not installed).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gcb.h"
+
+namespace gcb {
+
+constexpr int kBlock = 256;          // threads per workgroup of the sweep kernels (4 wave64)
+constexpr int kLdsTile = 256;        // supports staged in LDS per pass
+constexpr int kMaxChunks = 64;       // split-K depth of a group sweep
+constexpr double kSingularTol = 64.0 * 2.220446049250313e-16;  // phi0 - l.l below this: not SPD
+
+// Greedy state, resident in device memory and advanced by the kernels.
+struct GState {
+    int64_t k;            // iteration counter (Algorithm 1 starts at k = 3)
+    int32_t n;            // |S|
+    int32_t quiet;        // consecutive iterations without an append
+    int32_t done;         // 0 running, 1 converged, 2 cap reached, 3 singular, 4 factor capacity reached
+    int32_t app;          // this iteration appends `node`
+    int32_t node_pos;     // permuted position of the node to append (-1: none)
+    int32_t node_orig;    // its original index
+    int32_t pad0;
+    double E;             // this iteration's group maximum error
+    uint64_t pairs_group;
+    uint64_t pairs_append;
+    int64_t log_len;      // iterations written to the log
+    int32_t singular_node;
+    int32_t init_left;    // forced appends of the starting nodes still to do
+};
+
+// Per-block argmax record.
+struct ArgRec {
+    double e2;            // squared error (-1: none)
+    int32_t orig;         // original index
+    int32_t pos;          // permuted position
+    int32_t count;        // candidates (not in S) seen
+    int32_t pad;
+};
+
+struct Boundary {
+    int64_t nb = 0;
+    int32_t m = 0;
+    double radius = 0, inv_r = 0;
+    // permuted, group-contiguous (within a group ascending original index), coordinates scaled by 1/R
+    double *px = nullptr, *py = nullptr, *pz = nullptr;
+    double *pdx = nullptr, *pdy = nullptr, *pdz = nullptr;
+    float *fx = nullptr, *fy = nullptr, *fz = nullptr;   // FP32 copies (screening mode)
+    int32_t *perm = nullptr;     // pos -> original index
+    int32_t *pos_of = nullptr;   // original index -> pos
+    int32_t *goff = nullptr;     // m+1 group offsets
+    uint8_t *inS = nullptr;      // by pos
+    // original order (unscaled) for the starting-node rule
+    double *xyz0 = nullptr, *disp0 = nullptr;
+    int32_t gmax = 0;            // largest group size
+    std::vector<int32_t> goff_h;
+};
+
+struct Support {
+    int64_t cap = 0;             // capacity of the support arrays and of M
+    double *sx = nullptr, *sy = nullptr, *sz = nullptr;   // scaled coordinates, selection order
+    double *wx = nullptr, *wy = nullptr, *wz = nullptr;   // weights (FP64 master)
+    float *fsx = nullptr, *fsy = nullptr, *fsz = nullptr, *fwx = nullptr, *fwy = nullptr, *fwz = nullptr;
+    int32_t *orig = nullptr;     // original index of support s
+    double *M = nullptr;         // packed lower-triangular inverse factor, row i at i(i+1)/2
+    double *b = nullptr, *l = nullptr;   // append scratch (cap)
+    double *Pu = nullptr;        // (cap/kBlock + 1) x cap partial column sums
+    int64_t pu_rows = 0;
+};
+
+}  // namespace gcb
+
+struct gcb_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    std::string err;
+    gcb_params params{};
+    bool have_params = false;
+    bool have_groups = false;
+    std::vector<int32_t> groups_h;   // explicit partition
+    gcb::Boundary bd;
+    gcb::Support sp;
+    gcb::GState *state = nullptr;    // device
+    gcb::GState state_h{};
+    gcb::ArgRec *argrec = nullptr;   // device, per block
+    int64_t argrec_cap = 0;
+    double *P = nullptr;             // sweep partials
+    int64_t P_cap = 0;
+    // per-iteration log (device)
+    int32_t *log_group = nullptr;
+    int32_t *log_node = nullptr;
+    double *log_err = nullptr;
+    int8_t *log_app = nullptr;
+    int64_t log_cap = 0;
+    bool selected = false;
+    gcb_select_info info{};
+    // scratch for certificate / volume
+    double *red = nullptr;
+    int64_t red_cap = 0;
+    void *tmp = nullptr;
+    size_t tmp_cap = 0;
+};

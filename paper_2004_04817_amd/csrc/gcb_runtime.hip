@@ -1,0 +1,628 @@
+// Host runtime and C ABI of the MI355X GCB greedy RBF library.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "gcb_internal.h"
+#include "gcb_kernels.h"
+
+using namespace gcb;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+struct Fail {
+    int code;
+};
+
+#define HIPCHK(ctx, expr)                                                                         \
+    do {                                                                                          \
+        hipError_t _e = (expr);                                                                   \
+        if (_e != hipSuccess) {                                                                   \
+            (ctx)->err = std::string(#expr) + ": " + hipGetErrorString(_e);                       \
+            throw Fail{_e == hipErrorOutOfMemory ? GCB_E_NOMEM : GCB_E_DEVICE};                   \
+        }                                                                                         \
+    } while (0)
+
+[[noreturn]] void fail(gcb_ctx* ctx, int code, const std::string& msg) {
+    ctx->err = msg;
+    throw Fail{code};
+}
+
+template <typename T>
+void dalloc(gcb_ctx* ctx, T*& p, size_t count) {
+    if (p) {
+        (void)hipFree(p);
+        p = nullptr;
+    }
+    if (count == 0) count = 1;
+    void* q = nullptr;
+    hipError_t e = hipMalloc(&q, count * sizeof(T));
+    if (e != hipSuccess) {
+        ctx->err = "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes: " + hipGetErrorString(e);
+        throw Fail{GCB_E_NOMEM};
+    }
+    p = static_cast<T*>(q);
+}
+
+template <typename T>
+void dfree(T*& p) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+// splitmix64 (Steele, Lea, Flood 2014; 64-bit finaliser of the xoshiro reference)
+inline uint64_t splitmix64(uint64_t& state) {
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+void seeded_partition(int64_t nb, int32_t m, uint64_t seed, int32_t* group_of) {
+    std::vector<int64_t> order(static_cast<size_t>(nb));
+    for (int64_t i = 0; i < nb; ++i) order[i] = i;
+    uint64_t st = seed;
+    for (int64_t i = nb - 1; i > 0; --i) {
+        const uint64_t j = splitmix64(st) % static_cast<uint64_t>(i + 1);
+        std::swap(order[i], order[j]);
+    }
+    for (int64_t t = 0; t < nb; ++t) group_of[order[t]] = static_cast<int32_t>(t % m);
+}
+
+bool all_finite(const double* a, int64_t count) {
+    for (int64_t i = 0; i < count; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+void sync(gcb_ctx* ctx) { HIPCHK(ctx, hipStreamSynchronize(ctx->stream)); }
+
+void copy_in(gcb_ctx* ctx, void* dst, const void* src, size_t bytes, int mem) {
+    HIPCHK(ctx, hipMemcpyAsync(dst, src, bytes, mem == GCB_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                               ctx->stream));
+}
+
+void copy_out(gcb_ctx* ctx, void* dst, const void* src, size_t bytes, int mem) {
+    HIPCHK(ctx, hipMemcpyAsync(dst, src, bytes, mem == GCB_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                               ctx->stream));
+}
+
+void free_support(Support& sp) {
+    dfree(sp.sx); dfree(sp.sy); dfree(sp.sz); dfree(sp.wx); dfree(sp.wy); dfree(sp.wz);
+    dfree(sp.fsx); dfree(sp.fsy); dfree(sp.fsz); dfree(sp.fwx); dfree(sp.fwy); dfree(sp.fwz);
+    dfree(sp.orig); dfree(sp.M); dfree(sp.b); dfree(sp.l); dfree(sp.Pu);
+    sp.cap = 0;
+    sp.pu_rows = 0;
+}
+
+void free_boundary(Boundary& bd) {
+    dfree(bd.px); dfree(bd.py); dfree(bd.pz); dfree(bd.pdx); dfree(bd.pdy); dfree(bd.pdz);
+    dfree(bd.fx); dfree(bd.fy); dfree(bd.fz); dfree(bd.perm); dfree(bd.pos_of); dfree(bd.goff); dfree(bd.inS);
+    dfree(bd.xyz0); dfree(bd.disp0);
+    bd.nb = 0;
+    bd.m = 0;
+}
+
+// (Re)allocate the support arrays for capacity `cap`, keeping the first n
+// entries (and the first n rows of the packed factor).
+void grow_support(gcb_ctx* ctx, int64_t cap, int64_t n) {
+    Support& sp = ctx->sp;
+    Support nw;
+    nw.cap = cap;
+    dalloc(ctx, nw.sx, cap); dalloc(ctx, nw.sy, cap); dalloc(ctx, nw.sz, cap);
+    dalloc(ctx, nw.wx, cap); dalloc(ctx, nw.wy, cap); dalloc(ctx, nw.wz, cap);
+    dalloc(ctx, nw.orig, cap);
+    dalloc(ctx, nw.M, (size_t)cap * (size_t)(cap + 1) / 2);
+    dalloc(ctx, nw.b, cap);
+    dalloc(ctx, nw.l, cap);
+    nw.pu_rows = (cap + kBlock - 1) / kBlock;
+    dalloc(ctx, nw.Pu, (size_t)nw.pu_rows * (size_t)cap);
+    if (n > 0 && sp.cap > 0) {
+        const size_t b8 = sizeof(double) * (size_t)n;
+        HIPCHK(ctx, hipMemcpyAsync(nw.sx, sp.sx, b8, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(nw.sy, sp.sy, b8, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(nw.sz, sp.sz, b8, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(nw.wx, sp.wx, b8, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(nw.wy, sp.wy, b8, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(nw.wz, sp.wz, b8, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(nw.orig, sp.orig, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(nw.M, sp.M, sizeof(double) * (size_t)n * (size_t)(n + 1) / 2, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+        sync(ctx);
+    }
+    free_support(sp);
+    sp = nw;
+}
+
+template <typename T>
+void grow_log_array(gcb_ctx* ctx, T*& p, int64_t old_len, int64_t cap) {
+    T* q = nullptr;
+    dalloc(ctx, q, cap);
+    if (p && old_len > 0) HIPCHK(ctx, hipMemcpyAsync(q, p, sizeof(T) * old_len, hipMemcpyDeviceToDevice, ctx->stream));
+    sync(ctx);
+    dfree(p);
+    p = q;
+}
+
+void grow_log(gcb_ctx* ctx, int64_t used, int64_t cap) {
+    grow_log_array(ctx, ctx->log_group, used, cap);
+    grow_log_array(ctx, ctx->log_node, used, cap);
+    grow_log_array(ctx, ctx->log_err, used, cap);
+    grow_log_array(ctx, ctx->log_app, used, cap);
+    ctx->log_cap = cap;
+}
+
+void check_params(gcb_ctx* ctx) {
+    const gcb_params& p = ctx->params;
+    const int64_t nb = ctx->bd.nb;
+    if (!ctx->have_params) fail(ctx, GCB_E_STATE, "gcb_set_params has not been called");
+    if (nb < 3) fail(ctx, GCB_E_STATE, "gcb_set_boundary has not been called");
+    if (!(p.radius > 0.0) || !std::isfinite(p.radius)) fail(ctx, GCB_E_INVALID, "radius must be finite and > 0");
+    if (p.m < 1 || p.m > nb) fail(ctx, GCB_E_INVALID, "m must satisfy 1 <= m <= nb");
+    if (!(p.tol_abs >= 0.0) || !std::isfinite(p.tol_abs)) fail(ctx, GCB_E_INVALID, "tol_abs must be finite and >= 0");
+    if (p.nc_max < 3 || p.nc_max > nb) fail(ctx, GCB_E_INVALID, "nc_max must satisfy 3 <= nc_max <= nb");
+    if (p.nc_max > (int64_t)1 << 30) fail(ctx, GCB_E_INVALID, "nc_max too large");
+    if (p.precision != GCB_PREC_FP64 && p.precision != GCB_PREC_FP32_EVAL)
+        fail(ctx, GCB_E_INVALID, "unknown precision");
+    if (p.use_init) {
+        for (int t = 0; t < 3; ++t)
+            if (p.init_idx[t] < 0 || p.init_idx[t] >= nb) fail(ctx, GCB_E_INVALID, "init_idx out of range");
+        if (p.init_idx[0] == p.init_idx[1] || p.init_idx[0] == p.init_idx[2] || p.init_idx[1] == p.init_idx[2])
+            fail(ctx, GCB_E_INVALID, "init_idx must be distinct");
+    }
+    if (ctx->have_groups)
+        for (int64_t j = 0; j < nb; ++j)
+            if (ctx->groups_h[j] < 0 || ctx->groups_h[j] >= p.m) fail(ctx, GCB_E_INVALID, "group id out of [0, m)");
+}
+
+// Partition, permutation and staging of the boundary (a1).
+void stage_boundary(gcb_ctx* ctx) {
+    Boundary& bd = ctx->bd;
+    const gcb_params& p = ctx->params;
+    const int64_t nb = bd.nb;
+    std::vector<int32_t> grp(static_cast<size_t>(nb));
+    if (ctx->have_groups) grp = ctx->groups_h;
+    else seeded_partition(nb, p.m, p.seed, grp.data());
+    std::vector<int32_t> goff(static_cast<size_t>(p.m) + 1, 0);
+    for (int64_t j = 0; j < nb; ++j) goff[grp[j] + 1]++;
+    int32_t gmax = 0;
+    for (int32_t g = 0; g < p.m; ++g) {
+        gmax = std::max(gmax, goff[g + 1]);
+        goff[g + 1] += goff[g];
+    }
+    std::vector<int32_t> fill(goff.begin(), goff.end() - 1), perm(static_cast<size_t>(nb));
+    for (int64_t j = 0; j < nb; ++j) perm[fill[grp[j]]++] = static_cast<int32_t>(j);
+    bd.m = p.m;
+    bd.radius = p.radius;
+    bd.inv_r = 1.0 / p.radius;
+    bd.gmax = gmax;
+    bd.goff_h = goff;
+    dalloc(ctx, bd.px, nb); dalloc(ctx, bd.py, nb); dalloc(ctx, bd.pz, nb);
+    dalloc(ctx, bd.pdx, nb); dalloc(ctx, bd.pdy, nb); dalloc(ctx, bd.pdz, nb);
+    dalloc(ctx, bd.perm, nb); dalloc(ctx, bd.pos_of, nb); dalloc(ctx, bd.inS, nb);
+    dalloc(ctx, bd.goff, (size_t)p.m + 1);
+    HIPCHK(ctx, hipMemcpyAsync(bd.perm, perm.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(bd.goff, goff.data(), sizeof(int32_t) * (p.m + 1), hipMemcpyHostToDevice, ctx->stream));
+    launch_stage(ctx->stream, nb, bd.xyz0, bd.disp0, bd.perm, bd.inv_r, bd);
+    HIPCHK(ctx, hipGetLastError());
+    sync(ctx);   // host vectors above go out of scope
+}
+
+int64_t n_upper(const gcb_ctx* ctx, int64_t n, int64_t iters) {
+    return std::min<int64_t>(ctx->params.nc_max, n + iters);
+}
+
+void run_select(gcb_ctx* ctx, gcb_select_info* info) {
+    check_params(ctx);
+    ctx->selected = false;
+    stage_boundary(ctx);
+    const gcb_params& p = ctx->params;
+    Boundary& bd = ctx->bd;
+    const int64_t cap0 = std::min<int64_t>(p.nc_max, 1024);
+    free_support(ctx->sp);
+    grow_support(ctx, cap0, 0);
+    const int64_t nrec = std::max<int64_t>(1024, (bd.gmax + kBlock - 1) / kBlock);
+    if (ctx->argrec_cap < nrec + 1) {
+        ctx->argrec_cap = nrec + 1;   // the last record holds the three starting nodes
+        dalloc(ctx, ctx->argrec, ctx->argrec_cap);
+    }
+    const int64_t pneed = (int64_t)kMaxChunks * 3 * bd.gmax;
+    if (ctx->P_cap < pneed) {
+        ctx->P_cap = pneed;
+        dalloc(ctx, ctx->P, pneed);
+    }
+    if (!ctx->state) dalloc(ctx, ctx->state, 1);
+    if (ctx->log_cap == 0) grow_log(ctx, 0, 65536);
+    int32_t* init = reinterpret_cast<int32_t*>(ctx->argrec + ctx->argrec_cap - 1);   // 3 ints in a spare record
+    static_assert(sizeof(ArgRec) >= 3 * sizeof(int32_t), "record too small");
+
+    hipEvent_t ev0, ev1;
+    HIPCHK(ctx, hipEventCreate(&ev0));
+    HIPCHK(ctx, hipEventCreate(&ev1));
+    HIPCHK(ctx, hipEventRecord(ev0, ctx->stream));
+
+    GState st{};
+    st.k = 3;
+    st.init_left = 3;
+    st.node_pos = -1;
+    st.node_orig = -1;
+    st.singular_node = -1;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->state, &st, sizeof(st), hipMemcpyHostToDevice, ctx->stream));
+    if (p.use_init) {
+        int32_t h[3] = {(int32_t)p.init_idx[0], (int32_t)p.init_idx[1], (int32_t)p.init_idx[2]};
+        HIPCHK(ctx, hipMemcpyAsync(init, h, sizeof(h), hipMemcpyHostToDevice, ctx->stream));
+        sync(ctx);
+    } else {
+        launch_init_nodes(ctx->stream, bd, init, ctx->argrec);
+    }
+    for (int t = 0; t < 3; ++t) {
+        launch_init_stage(ctx->stream, ctx->state, init, t, bd.pos_of);
+        launch_append(ctx->stream, ctx->state, bd, ctx->sp, t);
+    }
+    HIPCHK(ctx, hipGetLastError());
+    const int chunk = 32;
+    for (;;) {
+        HIPCHK(ctx, hipMemcpyAsync(&ctx->state_h, ctx->state, sizeof(GState), hipMemcpyDeviceToHost, ctx->stream));
+        sync(ctx);
+        GState& h = ctx->state_h;
+        if (h.done == 4) {
+            h.done = 0;
+            HIPCHK(ctx, hipMemcpyAsync(ctx->state, &h, sizeof(GState), hipMemcpyHostToDevice, ctx->stream));
+        } else if (h.done != 0) {
+            break;
+        }
+        if (h.n + chunk > ctx->sp.cap && ctx->sp.cap < p.nc_max) {
+            const int64_t cap = std::min<int64_t>(p.nc_max, std::max<int64_t>(2 * ctx->sp.cap, h.n + chunk + 1));
+            grow_support(ctx, cap, h.n);
+        }
+        if (h.log_len + chunk > ctx->log_cap) grow_log(ctx, h.log_len, std::max<int64_t>(2 * ctx->log_cap, h.log_len + chunk));
+        for (int it = 0; it < chunk; ++it) {
+            const int n_ub = (int)n_upper(ctx, h.n, it + 1);
+            launch_iteration(ctx->stream, ctx->state, bd, ctx->sp, ctx->P, bd.gmax, ctx->argrec, p.tol_abs, p.nc_max,
+                             ctx->log_cap, ctx->log_group, ctx->log_node, ctx->log_err, ctx->log_app, n_ub);
+        }
+        HIPCHK(ctx, hipGetLastError());
+    }
+    HIPCHK(ctx, hipEventRecord(ev1, ctx->stream));
+    HIPCHK(ctx, hipEventSynchronize(ev1));
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ev0, ev1));
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    const GState& h = ctx->state_h;
+    if (h.done == 3) {
+        ctx->err = "support matrix not numerically SPD when appending node " + std::to_string(h.singular_node);
+        throw Fail{GCB_E_SINGULAR};
+    }
+    gcb_select_info inf{};
+    inf.nc = h.n;
+    inf.iterations = h.log_len;
+    inf.status = h.done == 2 ? GCB_NOT_CONVERGED : GCB_OK;
+    inf.pairs_group = h.pairs_group;
+    inf.pairs_append = h.pairs_append;
+    inf.ms_select = ms;
+    // FP64 certificate over all boundary nodes
+    if (ctx->red_cap < 2 * (bd.nb / kBlock + 2) + 2) {
+        ctx->red_cap = 2 * (bd.nb / kBlock + 2) + 2;
+        dalloc(ctx, ctx->red, ctx->red_cap);
+    }
+    launch_certify(ctx->stream, bd, ctx->sp, h.n, ctx->red, ctx->red + ctx->red_cap - 2);
+    HIPCHK(ctx, hipGetLastError());
+    double mr[2];
+    HIPCHK(ctx, hipMemcpyAsync(mr, ctx->red + ctx->red_cap - 2, sizeof(mr), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    inf.final_max_err = std::sqrt(mr[0]);
+    inf.final_rms_err = std::sqrt(mr[1] / (double)bd.nb);
+    inf.converged = inf.final_max_err <= p.tol_abs;
+    inf.pairs_cert = (uint64_t)bd.nb * (uint64_t)h.n;
+    ctx->info = inf;
+    ctx->selected = true;
+    if (info) *info = inf;
+}
+
+template <typename F>
+int guard(gcb_ctx* ctx, F&& f) {
+    if (!ctx) return GCB_E_INVALID;
+    try {
+        ctx->err.clear();
+        return f();
+    } catch (const Fail& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        ctx->err = "host allocation failed";
+        return GCB_E_NOMEM;
+    } catch (...) {
+        ctx->err = "unexpected internal error";
+        return GCB_E_DEVICE;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gcb_version(void) { return "gcb-mi355x 0.1 (gfx950, FP64 sweeps, inverse-factor append)"; }
+
+int gcb_partition(int64_t nb, int32_t m, uint64_t seed, int32_t* group_of) {
+    if (nb < 1 || m < 1 || m > nb || !group_of) return GCB_E_INVALID;
+    try {
+        seeded_partition(nb, m, seed, group_of);
+    } catch (...) {
+        return GCB_E_NOMEM;
+    }
+    return GCB_OK;
+}
+
+int gcb_create(gcb_ctx** out, int device, void* hip_stream) {
+    if (!out) return GCB_E_INVALID;
+    *out = nullptr;
+    gcb_ctx* ctx = new (std::nothrow) gcb_ctx();
+    if (!ctx) return GCB_E_NOMEM;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || device < 0 || device >= n) {
+        g_create_err = e != hipSuccess ? std::string("hipGetDeviceCount: ") + hipGetErrorString(e)
+                                       : "device index out of range";
+        delete ctx;
+        return e != hipSuccess ? GCB_E_DEVICE : GCB_E_INVALID;
+    }
+    ctx->device = device;
+    e = hipSetDevice(device);
+    if (e == hipSuccess && !hip_stream) e = hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        g_create_err = std::string("hip setup: ") + hipGetErrorString(e);
+        delete ctx;
+        return GCB_E_DEVICE;
+    }
+    ctx->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->own_stream;
+    *out = ctx;
+    return GCB_OK;
+}
+
+void gcb_destroy(gcb_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    free_boundary(ctx->bd);
+    free_support(ctx->sp);
+    dfree(ctx->state); dfree(ctx->argrec); dfree(ctx->P); dfree(ctx->red);
+    dfree(ctx->log_group); dfree(ctx->log_node); dfree(ctx->log_err); dfree(ctx->log_app);
+    if (ctx->tmp) (void)hipFree(ctx->tmp);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+    delete ctx;
+}
+
+const char* gcb_last_error(const gcb_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+int gcb_set_stream(gcb_ctx* ctx, void* hip_stream) {
+    return guard(ctx, [&] {
+        ctx->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->own_stream;
+        if (!ctx->stream) {
+            HIPCHK(ctx, hipSetDevice(ctx->device));
+            HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
+            ctx->stream = ctx->own_stream;
+        }
+        return GCB_OK;
+    });
+}
+
+int gcb_set_boundary(gcb_ctx* ctx, int64_t nb, const double* xyz, const double* disp, int mem) {
+    return guard(ctx, [&] {
+        if (nb < 3 || !xyz || !disp) fail(ctx, GCB_E_INVALID, "need nb >= 3 and non-NULL xyz, disp");
+        if (nb > ((int64_t)1 << 30)) fail(ctx, GCB_E_INVALID, "nb too large");
+        if (mem != GCB_MEM_HOST && mem != GCB_MEM_DEVICE) fail(ctx, GCB_E_INVALID, "bad mem kind");
+        if (mem == GCB_MEM_HOST && (!all_finite(xyz, 3 * nb) || !all_finite(disp, 3 * nb)))
+            fail(ctx, GCB_E_INVALID, "non-finite boundary coordinate or displacement");
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        ctx->selected = false;
+        free_boundary(ctx->bd);
+        ctx->bd.nb = nb;
+        dalloc(ctx, ctx->bd.xyz0, 3 * (size_t)nb);
+        dalloc(ctx, ctx->bd.disp0, 3 * (size_t)nb);
+        copy_in(ctx, ctx->bd.xyz0, xyz, sizeof(double) * 3 * nb, mem);
+        copy_in(ctx, ctx->bd.disp0, disp, sizeof(double) * 3 * nb, mem);
+        if (mem == GCB_MEM_DEVICE) {
+            int32_t* flag = nullptr;
+            dalloc(ctx, flag, 1);
+            HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
+            launch_check_finite(ctx->stream, 3 * nb, ctx->bd.xyz0, ctx->bd.disp0, flag);
+            int32_t h = 0;
+            HIPCHK(ctx, hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+            sync(ctx);
+            dfree(flag);
+            if (h) {
+                free_boundary(ctx->bd);
+                fail(ctx, GCB_E_INVALID, "non-finite boundary coordinate or displacement");
+            }
+        }
+        sync(ctx);
+        if (ctx->have_groups && (int64_t)ctx->groups_h.size() != nb) ctx->have_groups = false;
+        return GCB_OK;
+    });
+}
+
+int gcb_set_displacement(gcb_ctx* ctx, const double* disp, int mem) {
+    return guard(ctx, [&] {
+        if (ctx->bd.nb < 3) fail(ctx, GCB_E_STATE, "gcb_set_boundary has not been called");
+        if (!disp) fail(ctx, GCB_E_INVALID, "disp is NULL");
+        const int64_t nb = ctx->bd.nb;
+        if (mem == GCB_MEM_HOST && !all_finite(disp, 3 * nb)) fail(ctx, GCB_E_INVALID, "non-finite displacement");
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        copy_in(ctx, ctx->bd.disp0, disp, sizeof(double) * 3 * nb, mem);
+        if (mem == GCB_MEM_DEVICE) {
+            int32_t* flag = nullptr;
+            dalloc(ctx, flag, 1);
+            HIPCHK(ctx, hipMemsetAsync(flag, 0, sizeof(int32_t), ctx->stream));
+            launch_check_finite(ctx->stream, 3 * nb, ctx->bd.disp0, nullptr, flag);
+            int32_t h = 0;
+            HIPCHK(ctx, hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+            sync(ctx);
+            dfree(flag);
+            if (h) fail(ctx, GCB_E_INVALID, "non-finite displacement");
+        }
+        sync(ctx);
+        ctx->selected = false;
+        return GCB_OK;
+    });
+}
+
+int gcb_set_params(gcb_ctx* ctx, const gcb_params* p) {
+    return guard(ctx, [&] {
+        if (!p) fail(ctx, GCB_E_INVALID, "params is NULL");
+        ctx->params = *p;
+        ctx->have_params = true;
+        ctx->selected = false;
+        return GCB_OK;
+    });
+}
+
+int gcb_set_groups(gcb_ctx* ctx, const int32_t* group_of, int mem) {
+    return guard(ctx, [&] {
+        if (!group_of) {
+            ctx->have_groups = false;
+            ctx->groups_h.clear();
+            return GCB_OK;
+        }
+        if (ctx->bd.nb < 3) fail(ctx, GCB_E_STATE, "gcb_set_boundary has not been called");
+        ctx->groups_h.resize(static_cast<size_t>(ctx->bd.nb));
+        if (mem == GCB_MEM_DEVICE) {
+            HIPCHK(ctx, hipMemcpyAsync(ctx->groups_h.data(), group_of, sizeof(int32_t) * ctx->bd.nb, hipMemcpyDeviceToHost,
+                                       ctx->stream));
+            sync(ctx);
+        } else {
+            std::memcpy(ctx->groups_h.data(), group_of, sizeof(int32_t) * ctx->bd.nb);
+        }
+        ctx->have_groups = true;
+        ctx->selected = false;
+        return GCB_OK;
+    });
+}
+
+int gcb_select(gcb_ctx* ctx, gcb_select_info* info) {
+    return guard(ctx, [&] {
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        run_select(ctx, info);
+        return ctx->info.status;
+    });
+}
+
+int gcb_get_support(gcb_ctx* ctx, int64_t* idx, double* w, int mem) {
+    return guard(ctx, [&] {
+        if (!ctx->selected) fail(ctx, GCB_E_STATE, "no finished selection");
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        const int64_t n = ctx->info.nc;
+        std::vector<int32_t> o(static_cast<size_t>(n));
+        std::vector<double> wx(n), wy(n), wz(n);
+        HIPCHK(ctx, hipMemcpyAsync(o.data(), ctx->sp.orig, sizeof(int32_t) * n, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(wx.data(), ctx->sp.wx, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(wy.data(), ctx->sp.wy, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(wz.data(), ctx->sp.wz, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+        sync(ctx);
+        std::vector<int64_t> oi(o.begin(), o.end());
+        std::vector<double> wa(3 * (size_t)n);
+        for (int64_t s = 0; s < n; ++s) {
+            wa[3 * s] = wx[s];
+            wa[3 * s + 1] = wy[s];
+            wa[3 * s + 2] = wz[s];
+        }
+        if (mem == GCB_MEM_DEVICE) {
+            if (idx) HIPCHK(ctx, hipMemcpyAsync(idx, oi.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, ctx->stream));
+            if (w) HIPCHK(ctx, hipMemcpyAsync(w, wa.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, ctx->stream));
+            sync(ctx);
+        } else {
+            if (idx) std::memcpy(idx, oi.data(), sizeof(int64_t) * n);
+            if (w) std::memcpy(w, wa.data(), sizeof(double) * 3 * n);
+        }
+        return GCB_OK;
+    });
+}
+
+int64_t gcb_get_log(gcb_ctx* ctx, int32_t* group, int64_t* node, double* err, int8_t* appended, int64_t cap) {
+    if (!ctx) return GCB_E_INVALID;
+    int64_t total = 0;
+    int rc = guard(ctx, [&] {
+        if (!ctx->selected) fail(ctx, GCB_E_STATE, "no finished selection");
+        if (cap < 0) fail(ctx, GCB_E_INVALID, "cap < 0");
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        total = ctx->state_h.log_len;
+        const int64_t n = std::min(cap, std::min(total, ctx->log_cap));
+        if (n > 0) {
+            std::vector<int32_t> nd(static_cast<size_t>(n));
+            if (group) HIPCHK(ctx, hipMemcpyAsync(group, ctx->log_group, sizeof(int32_t) * n, hipMemcpyDeviceToHost, ctx->stream));
+            if (node) HIPCHK(ctx, hipMemcpyAsync(nd.data(), ctx->log_node, sizeof(int32_t) * n, hipMemcpyDeviceToHost, ctx->stream));
+            if (err) HIPCHK(ctx, hipMemcpyAsync(err, ctx->log_err, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+            if (appended) HIPCHK(ctx, hipMemcpyAsync(appended, ctx->log_app, n, hipMemcpyDeviceToHost, ctx->stream));
+            sync(ctx);
+            if (node)
+                for (int64_t i = 0; i < n; ++i) node[i] = nd[i];
+        }
+        return GCB_OK;
+    });
+    return rc < 0 ? rc : total;
+}
+
+int gcb_deform(gcb_ctx* ctx, int64_t nv, const void* xyz, int in_dtype, void* out, int out_dtype, int mem) {
+    return guard(ctx, [&] {
+        if (!ctx->selected) fail(ctx, GCB_E_STATE, "no finished selection");
+        if (nv < 0) fail(ctx, GCB_E_INVALID, "nv < 0");
+        if (nv == 0) return GCB_OK;
+        if (!xyz || !out) fail(ctx, GCB_E_INVALID, "NULL xyz or out");
+        if ((in_dtype != GCB_F32 && in_dtype != GCB_F64) || (out_dtype != GCB_F32 && out_dtype != GCB_F64))
+            fail(ctx, GCB_E_INVALID, "dtype must be GCB_F32 or GCB_F64");
+        if (mem != GCB_MEM_HOST && mem != GCB_MEM_DEVICE) fail(ctx, GCB_E_INVALID, "bad mem kind");
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        const size_t in_b = (size_t)nv * 3 * (in_dtype == GCB_F64 ? 8 : 4);
+        const size_t out_b = (size_t)nv * 3 * (out_dtype == GCB_F64 ? 8 : 4);
+        const void* din = xyz;
+        void* dout = out;
+        if (mem == GCB_MEM_HOST) {
+            if (ctx->tmp_cap < in_b + out_b) {
+                if (ctx->tmp) (void)hipFree(ctx->tmp);
+                ctx->tmp = nullptr;
+                ctx->tmp_cap = 0;
+                HIPCHK(ctx, hipMalloc(&ctx->tmp, in_b + out_b));
+                ctx->tmp_cap = in_b + out_b;
+            }
+            HIPCHK(ctx, hipMemcpyAsync(ctx->tmp, xyz, in_b, hipMemcpyHostToDevice, ctx->stream));
+            din = ctx->tmp;
+            dout = static_cast<char*>(ctx->tmp) + in_b;
+        }
+        launch_volume(ctx->stream, nv, din, in_dtype == GCB_F64, ctx->bd.inv_r, ctx->sp, (int)ctx->info.nc, dout,
+                      out_dtype == GCB_F64);
+        HIPCHK(ctx, hipGetLastError());
+        if (mem == GCB_MEM_HOST) {
+            HIPCHK(ctx, hipMemcpyAsync(out, dout, out_b, hipMemcpyDeviceToHost, ctx->stream));
+            sync(ctx);
+        }
+        return GCB_OK;
+    });
+}
+
+int gcb_deform_multi(gcb_ctx* ctx, int32_t, const double*, int64_t, const void*, int, void*, int, int) {
+    return guard(ctx, [&] {
+        fail(ctx, GCB_E_STATE, "gcb_deform_multi is not available in this build");
+        return GCB_E_STATE;
+    });
+}
+
+int gcb_certify(gcb_ctx* ctx, double* max_err, double* rms_err) {
+    return guard(ctx, [&] {
+        if (!ctx->selected) fail(ctx, GCB_E_STATE, "no finished selection");
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        launch_certify(ctx->stream, ctx->bd, ctx->sp, (int)ctx->info.nc, ctx->red, ctx->red + ctx->red_cap - 2);
+        HIPCHK(ctx, hipGetLastError());
+        double mr[2];
+        HIPCHK(ctx, hipMemcpyAsync(mr, ctx->red + ctx->red_cap - 2, sizeof(mr), hipMemcpyDeviceToHost, ctx->stream));
+        sync(ctx);
+        if (max_err) *max_err = std::sqrt(mr[0]);
+        if (rms_err) *rms_err = std::sqrt(mr[1] / (double)ctx->bd.nb);
+        return GCB_OK;
+    });
+}
+
+}  // extern "C"

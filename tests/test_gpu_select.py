@@ -1,0 +1,112 @@
+"""GPU parity of the greedy selection (Algorithm 1) against the FP64 oracle.
+
+Bar: the selected index sequence is bit-exact, except after an iteration
+whose top two errors differ by less than TAU_FP64 * max|d| (then the GPU run
+must be certified step by step by the oracle's follow-mode replay).
+Weights and errors agree to FP64 rounding of the different factor algorithm
+(inverse factor M = L^-1 on the GPU, forward/back substitution in the oracle).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import brute
+from tests.gpu_util import first_divergence, gpu_select, oracle_select
+
+pytestmark = pytest.mark.gpu
+
+TAU_FP64 = 1e-9   # near-tie tolerance, relative to max|d|
+
+
+def assert_same_run(p, g_info, g_S, g_W, g_log, r, tol_abs, m, tau=TAU_FP64, nc_max=None):
+    md = p.max_disp
+    div = first_divergence(g_S, r.S)
+    if div == -1:
+        assert g_info["iterations"] == r.iterations
+        assert np.array_equal(g_log.group, r.log_group)
+        assert np.array_equal(g_log.node, r.log_node)
+        assert np.array_equal(g_log.appended, r.log_appended)
+        assert np.abs(g_log.err - r.log_err).max() <= 1e-10 * md
+        Wscale = max(1.0, np.abs(r.W).max())
+        assert np.abs(g_W - r.W).max() <= 1e-7 * Wscale
+    else:
+        bad, reason, gap = oracle.validate(p.xyz, p.disp, p.radius, m, tol_abs, g_S, g_log.group, g_log.node,
+                                           g_log.appended, tau * md, nc_max=nc_max, seed=p.seed)
+        assert bad == -1, f"GPU sequence diverges at {div} and fails replay at {bad} (reason {reason})"
+    assert g_info["nc"] == len(g_S)
+    assert g_info["pairs_cert"] == p.nb * g_info["nc"]
+
+
+@pytest.mark.parametrize("nb", [8, 13, 16, 70])
+@pytest.mark.parametrize("mm", ["1", "2", "3", "nb"])
+def test_tiny_brute_force(nb, mm):
+    m = nb if mm == "nb" else int(mm)
+    p = synth.tiny_problem(nb=nb, seed=nb, m=m)
+    for tol_rel in (0.0, 0.05):
+        tol = tol_rel * p.max_disp
+        ctx, info, S, W, log = gpu_select(p, tol_abs=tol, m=m)
+        r = oracle_select(p, tol_abs=tol, m=m)
+        g = oracle.partition(p.nb, m, p.seed)
+        Sb, _ = brute.gcb_brute(p.xyz, p.disp, p.radius, g, m, tol)
+        assert list(S) == list(r.S) == Sb
+        assert_same_run(p, info, S, W, log, r, tol, m)
+        ctx.close()
+
+
+def test_small_ellipsoid_matches_oracle():
+    """Nb = 2,000 ellipsoid, m = 10, E* = 1e-4 max|d| (Nc of a few hundred)."""
+    p = synth.config_small_ellipsoid(with_volume=False)
+    ctx, info, S, W, log = gpu_select(p)
+    r = oracle_select(p)
+    assert info["status"] == 0 and info["converged"]
+    assert_same_run(p, info, S, W, log, r, p.tol_abs, p.m)
+    assert abs(info["final_max_err"] - r.final_max_err) <= 1e-10 * p.max_disp
+    assert abs(info["final_rms_err"] - r.final_rms_err) <= 1e-10 * p.max_disp
+    assert info["pairs_group"] == r.pairs_group and info["pairs_append"] == r.pairs_append
+    ctx.close()
+
+
+def test_traditional_greedy_m1():
+    """m = 1 is the traditional greedy: GPU sequence equals the oracle's and
+    the independent NumPy Rendall-Allen implementation."""
+    p = synth.config_small_ellipsoid(with_volume=False)
+    ctx, info, S, W, log = gpu_select(p, m=1)
+    r = oracle_select(p, m=1)
+    assert_same_run(p, info, S, W, log, r, p.tol_abs, 1)
+    assert list(S) == brute.traditional_greedy(p.xyz, p.disp, p.radius, p.tol_abs)
+    ctx.close()
+
+
+def test_capacity_growth_and_cap():
+    """E* = 0 with Nc^max = 1,100 forces |S| past the initial device capacity
+    (1,024) and ends at the cap with GCB_NOT_CONVERGED, like the oracle."""
+    p = synth.config_small_ellipsoid(with_volume=False)
+    ctx, info, S, W, log = gpu_select(p, tol_abs=0.0, nc_max=1100)
+    r = oracle_select(p, tol_abs=0.0, nc_max=1100)
+    assert info["status"] == 1 and r.status == oracle.ORC_NOT_CONVERGED
+    assert len(S) == 1100
+    assert_same_run(p, info, S, W, log, r, 0.0, p.m, nc_max=1100)
+    ctx.close()
+
+
+def test_explicit_partition_and_start():
+    p = synth.config_small_ellipsoid(nb=1500, with_volume=False)
+    g = np.random.default_rng(3).integers(0, 7, p.nb).astype(np.int32)
+    init = [5, 700, 1400]
+    ctx, info, S, W, log = gpu_select(p, m=7, group_of=g, init_idx=init)
+    r = oracle_select(p, m=7, group_of=g, init_idx=init)
+    assert list(S[:3]) == init
+    assert_same_run(p, info, S, W, log, r, p.tol_abs, 7)
+    ctx.close()
+
+
+def test_wing_full_size_selection():
+    """80,000-node wing at m = 107, E* = 1e-5 max|d|: the full workload."""
+    p = synth.config_wing(with_volume=False)
+    ctx, info, S, W, log = gpu_select(p)
+    r = oracle_select(p)
+    print("wing: nc", info["nc"], "iters", info["iterations"], "ms", info["ms_select"], "oracle nc", r.nc, flush=True)
+    assert info["converged"] and info["final_max_err"] <= p.tol_abs
+    assert_same_run(p, info, S, W, log, r, p.tol_abs, p.m)
+    ctx.close()
