@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Benchmark of the GCB greedy RBF hot path on one MI355X.
+
+One step = the whole hot path over one synthetic input: the GCB greedy
+selection (partition and staging, group sweeps, argmax, FP64 inverse-factor
+appends, FP64 all-node certificate) on the 80,000-node wing at m = 107, then
+the volume deformation (Eq. 6) of 3,000,000 graded volume points.  Inputs are
+resident in HBM before the timed region.
+
+Prints ONE JSON line: metric, value (pair-evals/s over greedy + volume), the
+roofline of the dominant kernel, and the FP64 CPU oracle timed on the host
+cores as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector (256 CU x 64 lanes x 2 flop x 2.4 GHz)
+FLOPS_PER_PAIR = 21            # canonical: 3 sub, 5 for r^2, 1 sqrt, 1 clamp, 5 for phi, 3 FMA (x2)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="wing", choices=["wing", "small", "wing-large"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-volume", type=int, default=3_000_000,
+                    help="volume points in the oracle's timed sample")
+    return ap.parse_args()
+
+
+def problem(name):
+    import synth
+    if name == "small":
+        return synth.config_small_ellipsoid()
+    if name == "wing-large":
+        return synth.config_wing_large()
+    return synth.config_wing()
+
+
+def cpu_baseline(p, nv_sample):
+    """The FP64 oracle as it stands, on all host cores: full greedy + a volume sample."""
+    import oracle
+    threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    r = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed, nthreads=threads)
+    t1 = time.perf_counter()
+    vol = p.volume[:nv_sample]
+    oracle.interpolate(p.xyz[r.S], r.W, p.radius, vol, nthreads=threads)
+    t2 = time.perf_counter()
+    pairs = r.pairs_group + r.pairs_append + vol.shape[0] * r.nc
+    return {"value": pairs / (t2 - t0), "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"full greedy (Nb={p.nb}, m={p.m}, Nc={r.nc}, {r.iterations} iterations, {t1 - t0:.2f} s) "
+                      f"+ Eq. 6 at {vol.shape[0]} volume points ({t2 - t1:.2f} s)",
+            "seconds": t2 - t0}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        sys.exit(2)
+    import torch
+    import paper_2004_04817_amd as gcb
+
+    p = problem(a.config)
+    dev = torch.device("cuda:0")
+    xyz = torch.from_numpy(p.xyz).to(dev)
+    disp = torch.from_numpy(p.disp).to(dev)
+    vol = torch.from_numpy(p.volume).to(dev)
+    out = torch.empty_like(vol)
+    nv = vol.shape[0]
+    ctx = gcb.Context(0)
+    ctx.set_boundary(xyz, disp)
+    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        info = ctx.select()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.deform(vol, out=out)
+        e1.record(stream)
+        return info, e0, e1
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    step_ms, vol_ms, infos = [], [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ts = time.perf_counter()
+        info, e0, e1 = step()
+        torch.cuda.synchronize()
+        step_ms.append(1e3 * (time.perf_counter() - ts))
+        vol_ms.append(e0.elapsed_time(e1))
+        infos.append(info)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    info = infos[-1]
+    nc = info["nc"]
+    pairs_greedy = info["pairs_group"] + info["pairs_append"]
+    pairs_volume = nv * nc
+    value = a.steps * (pairs_greedy + pairs_volume) / total
+    vol_avg_ms = float(np.mean(vol_ms))
+    achieved = FLOPS_PER_PAIR * pairs_volume / (vol_avg_ms * 1e-3) / 1e12
+    rec = {
+        "metric": "RBF pair-evals/s (greedy+volume); deform latency p50/p99 vs plain FP64 GPU",
+        "value": value,
+        "unit": "pair-evals/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": 1e3 * total / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": p.name + f"+volume{nv}", "nb": p.nb, "nv": nv, "m": p.m, "radius": p.radius,
+                   "tol_abs": p.tol_abs, "tol_rel": p.tol_rel, "nc": nc, "iterations": info["iterations"],
+                   "precision": "fp64", "parallelism": "single-gpu"},
+        "phases_ms": {"select": float(np.mean([i["ms_select"] for i in infos])), "volume": vol_avg_ms},
+        "pairs": {"group": info["pairs_group"], "append": info["pairs_append"], "volume": pairs_volume,
+                  "certificate": info["pairs_cert"]},
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
+        "accuracy": {"final_max_err": info["final_max_err"], "final_rms_err": info["final_rms_err"],
+                     "converged": bool(info["converged"])},
+        "roofline": {"kernel": "k_volume64<double,double>", "bound": "alu", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": None, "flops_per_pair": FLOPS_PER_PAIR},
+    }
+    if not a.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(p, min(a.cpu_sample_volume, nv))
+    print(json.dumps(rec), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

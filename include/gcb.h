@@ -91,7 +91,9 @@ void gcb_destroy(gcb_ctx *ctx);
  * call).  With ctx = NULL: the message of the last failed gcb_create. */
 const char *gcb_last_error(const gcb_ctx *ctx);
 
-/* Switch the stream later calls enqueue on (NULL: the library's own stream). */
+/* Switch the stream later calls enqueue on: a hipStream_t, used verbatim
+ * (NULL is the device's null stream, which is PyTorch's default stream).
+ * Work already enqueued on the previous stream is waited for first. */
 int gcb_set_stream(gcb_ctx *ctx, void *hip_stream);
 
 /* Boundary nodes G and their prescribed displacements (Algorithm 1 input;

@@ -129,9 +129,10 @@ def _arg(x, dtype):
 
 
 def _stream_of(x):
+    """The caller's current HIP stream for a device tensor (0 = null stream), else None."""
     if _is_tensor(x) and x.is_cuda:
         import torch
-        return C.c_void_p(torch.cuda.current_stream(x.device).cuda_stream)
+        return int(torch.cuda.current_stream(x.device).cuda_stream)
     return None
 
 
@@ -177,12 +178,14 @@ class Context:
             raise GcbError(rc, lib().gcb_last_error(self._h).decode())
         return rc
 
-    def set_stream(self, stream):
-        self._check(lib().gcb_set_stream(self._h, stream))
+    def set_stream(self, stream: int):
+        """Enqueue later calls on this hipStream_t handle (0: the null stream)."""
+        self._check(lib().gcb_set_stream(self._h, C.c_void_p(stream) if stream else None))
+        self._stream = stream
 
     def use_current_stream(self, tensor):
         s = _stream_of(tensor)
-        if s is not None:
+        if s is not None and s != getattr(self, "_stream", None):
             self.set_stream(s)
 
     def set_boundary(self, xyz, disp):

@@ -12,25 +12,43 @@ namespace gcb {
 
 constexpr int kBlock = 256;          // threads per workgroup of the sweep kernels (4 wave64)
 constexpr int kLdsTile = 256;        // supports staged in LDS per pass
-constexpr int kMaxChunks = 64;       // split-K depth of a group sweep
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kBigBlock = 1024;      // threads per workgroup of the factor kernels (16 wave64)
+constexpr int kRowsL = kBigBlock / 64;   // rows (columns) of M per factor block, one wave each
+constexpr int kBWindow = 4096;       // phi-vector entries staged in LDS at a time
 constexpr double kSingularTol = 64.0 * 2.220446049250313e-16;  // phi0 - l.l below this: not SPD
 
-// Greedy state, resident in device memory and advanced by the kernels.
+// Greedy state, resident in device memory.  Only the kernel that commits an
+// iteration writes k and n, so every block of the other kernels sees the
+// values the iteration started with.
 struct GState {
     int64_t k;            // iteration counter (Algorithm 1 starts at k = 3)
     int32_t n;            // |S|
     int32_t quiet;        // consecutive iterations without an append
     int32_t done;         // 0 running, 1 converged, 2 cap reached, 3 singular, 4 factor capacity reached
-    int32_t app;          // this iteration appends `node`
-    int32_t node_pos;     // permuted position of the node to append (-1: none)
-    int32_t node_orig;    // its original index
-    int32_t pad0;
-    double E;             // this iteration's group maximum error
+    int32_t init_left;    // forced appends of the starting nodes still to do
+    int64_t log_len;      // iterations written to the log
     uint64_t pairs_group;
     uint64_t pairs_append;
-    int64_t log_len;      // iterations written to the log
     int32_t singular_node;
-    int32_t init_left;    // forced appends of the starting nodes still to do
+    int32_t pad;
+};
+
+// What one iteration decided, written by the sweep kernel's last block and
+// read by the append kernels.
+struct IterRec {
+    int64_t k;            // the iteration's k
+    int32_t n;            // |S| before the append
+    int32_t app;          // 1: append node_pos
+    int32_t init;         // 1: a starting-node append (k does not advance)
+    int32_t ran;          // 1: the iteration ran (advance k)
+    int32_t node_pos;     // permuted position of the node to append
+    int32_t node_orig;    // its original index
+    int32_t singular;     // set by the factor kernel: phi0 - l.l <= tolerance
+    int32_t pad;
+    double E;             // group maximum error
+    double rs;            // 1 / sqrt(s), s = 1 - l.l
+    double cx, cy, cz;    // e / s, e = d_new - b.W
 };
 
 // Per-block argmax record.
@@ -67,9 +85,8 @@ struct Support {
     float *fsx = nullptr, *fsy = nullptr, *fsz = nullptr, *fwx = nullptr, *fwy = nullptr, *fwz = nullptr;
     int32_t *orig = nullptr;     // original index of support s
     double *M = nullptr;         // packed lower-triangular inverse factor, row i at i(i+1)/2
-    double *b = nullptr, *l = nullptr;   // append scratch (cap)
-    double *Pu = nullptr;        // (cap/kBlock + 1) x cap partial column sums
-    int64_t pu_rows = 0;
+    double *Mc = nullptr;        // the same factor by columns: column j (rows j..cap-1) at j*cap - j(j-1)/2
+    double *l = nullptr;         // append scratch: l = M b (cap)
 };
 
 }  // namespace gcb
@@ -87,10 +104,11 @@ struct gcb_ctx {
     gcb::Support sp;
     gcb::GState *state = nullptr;    // device
     gcb::GState state_h{};
-    gcb::ArgRec *argrec = nullptr;   // device, per block
+    gcb::IterRec *irec = nullptr;    // device, the current iteration's record
+    double *Pb = nullptr;            // block partials of the factor kernels
+    int64_t Pb_cap = 0;
+    gcb::ArgRec *argrec = nullptr;   // device, per-block records of the sweeps
     int64_t argrec_cap = 0;
-    double *P = nullptr;             // sweep partials
-    int64_t P_cap = 0;
     // per-iteration log (device)
     int32_t *log_group = nullptr;
     int32_t *log_node = nullptr;

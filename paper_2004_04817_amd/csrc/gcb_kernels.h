@@ -19,11 +19,28 @@ void launch_stage(hipStream_t s, int64_t nb, const double* xyz, const double* di
                   double inv_r, Boundary& bd);
 void launch_check_finite(hipStream_t s, int64_t count, const double* a, const double* b, int32_t* flag);
 void launch_init_nodes(hipStream_t s, const Boundary& bd, int32_t* init, ArgRec* rec);
-void launch_init_stage(hipStream_t s, GState* st, const int32_t* init, int t, const int32_t* pos_of);
-void launch_append(hipStream_t s, GState* st, const Boundary& bd, Support& sp, int n_ub);
-void launch_iteration(hipStream_t s, GState* st, const Boundary& bd, Support& sp, double* P, int32_t Tmax,
-                      ArgRec* rec, double tol_abs, int64_t nc_max, int64_t log_cap, int32_t* lg, int32_t* ln,
-                      double* le, int8_t* la, int n_ub);
+// Everything one greedy iteration's kernels touch.
+struct IterCtx {
+    GState* st;
+    IterRec* irec;
+    ArgRec* srec;          // per-block records of the group sweep
+    const int32_t* init;   // the three starting nodes
+    const Boundary* bd;
+    Support* sp;
+    double* Pb;
+    double tol_abs;
+    int64_t nc_max;
+    int64_t log_cap;
+    int32_t* log_group;
+    int32_t* log_node;
+    double* log_err;
+    int8_t* log_app;
+};
+
+int sweep_blocks(int gmax);
+void launch_init_append(hipStream_t s, const IterCtx& ic, int t);
+void launch_iteration(hipStream_t s, const IterCtx& ic, int n_ub);
+void launch_transpose_factor(hipStream_t s, const double* Mr, double* Mc, int n, int64_t cap);
 void launch_certify(hipStream_t s, const Boundary& bd, const Support& sp, int n, double* red, double* out);
 void launch_volume(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,
                    void* out, int out_f64);

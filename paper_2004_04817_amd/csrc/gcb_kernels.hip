@@ -6,6 +6,8 @@
 #include "gcb_internal.h"
 #include "gcb_kernels.h"
 
+#include <algorithm>
+
 namespace gcb {
 
 // ---------------------------------------------------------------- Eq. (2)
@@ -103,6 +105,21 @@ __device__ Best block_best(Best b) {
     return b;
 }
 
+template <int NT>
+__device__ Best block_best_n(Best b) {
+    __shared__ Best sh[NT / 64];
+    b = wave_best(b);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = b;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < NT / 64; ++i)
+            if (better(sh[i].v, sh[i].idx, b.v, b.idx)) b = sh[i];
+    }
+    __syncthreads();
+    return b;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -128,272 +145,406 @@ __device__ __forceinline__ int32_t wave_isum(int32_t v) {
     return v;
 }
 
-// ---------------------------------------------------------------- sweep chunking
-// Split-K layout of a group sweep: T targets in wave tiles of 64, n supports
-// in `nch` chunks of `cs` supports.  A function of (T, n) only, so the
-// summation order never depends on scheduling.
-__host__ __device__ inline void sweep_split(int T, int n, int& ntile, int& nch, int& cs) {
-    ntile = (T + 63) / 64;
-    int want = (2048 + ntile - 1) / (ntile > 0 ? ntile : 1);
-    int lim = (n + 7) / 8;
-    nch = want < kMaxChunks ? want : kMaxChunks;
-    if (nch > lim) nch = lim;
-    if (nch < 1) nch = 1;
-    cs = (n + nch - 1) / nch;
-    if (cs < 1) cs = 1;
-    nch = (n + cs - 1) / cs;
-    if (nch < 1) nch = 1;
+__device__ Best big_block_best(Best b) { return block_best_n<kBigBlock>(b); }
+
+// Integer sum over a kBigBlock block, valid in thread 0.
+__device__ int32_t big_block_isum(int32_t v) {
+    __shared__ int32_t sh[kBigBlock / 64];
+    v = wave_isum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int32_t r = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBigBlock / 64; ++i) r += sh[i];
+    __syncthreads();
+    return r;
 }
 
-// ---------------------------------------------------------------- group sweep (a3)
-// Wave w of the grid takes (target tile w % ntile, support chunk w / ntile)
-// and writes its partial sums to P[chunk][c][t] (c = x, y, z; stride Tmax).
-__global__ __launch_bounds__(kBlock) void k_group_sweep64(const GState* __restrict__ st, int32_t m,
-                                                          const int32_t* __restrict__ goff,
-                                                          const double* __restrict__ px,
-                                                          const double* __restrict__ py,
-                                                          const double* __restrict__ pz, SupportView sv,
-                                                          double* __restrict__ P, int32_t Tmax) {
-    if (st->done) return;
-    const int g = (int)(st->k % m);
-    const int t0 = goff[g];
-    const int T = goff[g + 1] - t0;
-    const int n = st->n;
-    if (T <= 0 || n <= 0) return;   // empty group (possible with an explicit partition)
-    int ntile, nch, cs;
-    sweep_split(T, n, ntile, nch, cs);
-    const int gw = (int)((blockIdx.x * (size_t)kBlock + threadIdx.x) >> 6);
-    const int tile = gw % ntile;
-    const int ch = gw / ntile;
-    if (ch >= nch) return;
-    const int lane = threadIdx.x & 63;
-    const int t = tile * 64 + lane;
-    const bool live = t < T;
-    const int tt = live ? t : T - 1;
-    const double tx = px[t0 + tt], ty = py[t0 + tt], tz = pz[t0 + tt];
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    const int s0 = ch * cs;
-    const int s1 = min(n, s0 + cs);
-    accumulate64(tx, ty, tz, s0, s1, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
-    if (live) {
-        double* Pc = P + (size_t)ch * 3 * Tmax;
-        Pc[t] = ax;
-        Pc[Tmax + t] = ay;
-        Pc[2 * (size_t)Tmax + t] = az;
-    }
-}
+// ---------------------------------------------------------------- iteration kernels
+// One greedy iteration is three kernels; kernel boundaries are the only
+// grid-wide synchronisation (no atomics, no spin waits), and every reduction
+// runs in a fixed order, so results never depend on scheduling.
+//   k_sweep   group sweep (a3): a wave owns `tw` targets of the active group
+//             and its 64 lanes split the n supports; per-block best record.
+//   k_factor_l decision (a4) from the block records, then b and l = M b (a5).
+//   k_factor_u u = M^T l, new row of M, W update, commit of the iteration.
 
-// Sum the chunk partials in chunk order, form e^2 = |F - d|^2 for the
-// targets not in S, and reduce each block to its best (e^2, lowest index).
-__global__ __launch_bounds__(kBlock) void k_group_reduce(const GState* __restrict__ st, int32_t m,
-                                                         const int32_t* __restrict__ goff,
-                                                         const double* __restrict__ pdx,
-                                                         const double* __restrict__ pdy,
-                                                         const double* __restrict__ pdz,
-                                                         const uint8_t* __restrict__ inS,
-                                                         const int32_t* __restrict__ perm,
-                                                         const double* __restrict__ P, int32_t Tmax,
-                                                         ArgRec* __restrict__ rec) {
-    if (st->done) return;
-    const int g = (int)(st->k % m);
-    const int t0 = goff[g];
-    const int T = goff[g + 1] - t0;
-    const int n = st->n;
-    int ntile, nch, cs;
-    sweep_split(T, n, ntile, nch, cs);
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    Best b{-1.0, 0x7fffffff, -1};
-    int32_t cnt = 0;
-    if (t < T && !inS[t0 + t]) {
-        double fx = 0.0, fy = 0.0, fz = 0.0;
-        for (int c = 0; c < nch; ++c) {
-            const double* Pc = P + (size_t)c * 3 * Tmax;
-            fx += Pc[t];
-            fy += Pc[Tmax + t];
-            fz += Pc[2 * (size_t)Tmax + t];
-        }
-        const double ex = fx - pdx[t0 + t], ey = fy - pdy[t0 + t], ez = fz - pdz[t0 + t];
-        b.v = fma(ez, ez, fma(ey, ey, ex * ex));
-        b.idx = perm[t0 + t];
-        b.aux = t0 + t;
-        cnt = 1;
-    }
-    cnt = wave_isum(cnt);
-    __shared__ int32_t scnt[kBlock / 64];
-    if ((threadIdx.x & 63) == 0) scnt[threadIdx.x >> 6] = cnt;
-    b = block_best(b);
-    if (threadIdx.x == 0) {
-        int32_t c = 0;
-        for (int i = 0; i < kBlock / 64; ++i) c += scnt[i];
-        rec[blockIdx.x] = ArgRec{b.v, b.idx, b.aux, c, 0};
-    }
-}
+__host__ __device__ inline int sweep_tw(int T) { return T >= 4096 ? 4 : (T >= 1024 ? 2 : 1); }
 
-// One block: reduce the per-block records in block order, log the
-// iteration and take Algorithm 1's decision (append iff E > E* and |S| < cap).
-__global__ __launch_bounds__(kBlock) void k_group_decide(GState* __restrict__ st, int32_t m,
-                                                         const int32_t* __restrict__ goff,
-                                                         const ArgRec* __restrict__ rec, double tol_abs,
-                                                         int64_t nc_max, int64_t cap, int32_t* __restrict__ log_group,
-                                                         int32_t* __restrict__ log_node, double* __restrict__ log_err,
-                                                         int8_t* __restrict__ log_app, int64_t log_cap) {
-    if (st->done) return;
-    const int g = (int)(st->k % m);
-    const int T = goff[g + 1] - goff[g];
-    const int nrec = (T + kBlock - 1) / kBlock;
-    Best b{-1.0, 0x7fffffff, -1};
-    int32_t cnt = 0;
-    for (int i = threadIdx.x; i < nrec; i += kBlock) {
-        const ArgRec r = rec[i];
-        if (better(r.e2, r.orig, b.v, b.idx)) { b.v = r.e2; b.idx = r.orig; b.aux = r.pos; }
-        cnt += r.count;
-    }
-    __shared__ int32_t scnt[kBlock / 64];
-    cnt = wave_isum(cnt);
-    if ((threadIdx.x & 63) == 0) scnt[threadIdx.x >> 6] = cnt;
-    b = block_best(b);
-    if (threadIdx.x != 0) return;
-    int32_t total = 0;
-    for (int i = 0; i < kBlock / 64; ++i) total += scnt[i];
-    const bool have = b.v >= 0.0;
-    const double E = have ? sqrt(b.v) : 0.0;
-    const int n = st->n;
-    st->pairs_group += (uint64_t)total * (uint64_t)n;
-    int32_t app = 0;
-    if (have && E > tol_abs) {
+// Algorithm 1's decision for iteration k from the group's best candidate.
+// Computed identically by every block of k_factor_l; only block 0 stores it.
+struct Decision {
+    int32_t app, done, quiet;
+    double E;
+};
+
+__device__ __forceinline__ Decision decide_local(const GState& st, int n, int32_t m, double e2, double tol_abs,
+                                                 int64_t nc_max, int64_t cap) {
+    Decision d;
+    const bool have = e2 >= 0.0;
+    d.E = have ? sqrt(e2) : 0.0;
+    d.app = 0;
+    d.done = st.done;
+    d.quiet = st.quiet;
+    if (have && d.E > tol_abs) {
         if (n < nc_max && n < cap) {
-            app = 1;
-            st->quiet = 0;
+            d.app = 1;
+            d.quiet = 0;
         } else if (n >= nc_max) {
-            st->done = 2;
+            d.done = 2;
         } else {
-            st->done = 4;   // factor capacity: the host grows the arrays and resumes
+            d.done = 4;   // factor capacity: the host grows the arrays and this iteration runs again
         }
     } else {
-        st->quiet += 1;
+        d.quiet += 1;
     }
-    if (st->done != 4) {
-        const int64_t it = st->log_len;
-        if (it < log_cap) {
-            log_group[it] = g;
-            log_node[it] = have ? b.idx : -1;
-            log_err[it] = E;
-            log_app[it] = (int8_t)app;
-        }
-        st->log_len = it + 1;
-    }
-    st->E = E;
-    st->app = app;
-    st->node_pos = app ? b.aux : -1;
-    st->node_orig = app ? b.idx : -1;
-    if (st->done == 0 && !app && st->quiet >= m) st->done = 1;
-    if (st->done != 4) st->k += 1;   // the append kernels that follow do not read k
+    if (d.done == 0 && !d.app && d.quiet >= m) d.done = 1;
+    return d;
 }
 
-// ---------------------------------------------------------------- append (a5)
-// b_j = phi(|r_new - s_j| / R), j < n, in FP64.
-__global__ __launch_bounds__(kBlock) void k_append_b(const GState* __restrict__ st, const double* __restrict__ px,
-                                                     const double* __restrict__ py, const double* __restrict__ pz,
-                                                     SupportView sv, double* __restrict__ b) {
-    if (!st->app) return;
+__global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st, int32_t m,
+                                                  const int32_t* __restrict__ goff, const double* __restrict__ px,
+                                                  const double* __restrict__ py, const double* __restrict__ pz,
+                                                  const double* __restrict__ pdx, const double* __restrict__ pdy,
+                                                  const double* __restrict__ pdz, const uint8_t* __restrict__ inS,
+                                                  const int32_t* __restrict__ perm, SupportView sv,
+                                                  ArgRec* __restrict__ rec) {
+    __shared__ Best sb[kWavesPerBlock];
+    __shared__ int32_t sc[kWavesPerBlock];
+    if (st->done) return;
     const int n = st->n;
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
-    const int p = st->node_pos;
-    b[j] = wendland_r2(dist2(px[p], py[p], pz[p], sv.sx[j], sv.sy[j], sv.sz[j]));
-}
-
-// l = M b over the packed lower triangle: one wave per row i < n.
-__global__ __launch_bounds__(kBlock) void k_append_l(const GState* __restrict__ st, const double* __restrict__ M,
-                                                     const double* __restrict__ b, double* __restrict__ l) {
-    if (!st->app) return;
-    const int n = st->n;
-    const int i = (int)((blockIdx.x * (size_t)kBlock + threadIdx.x) >> 6);
-    if (i >= n) return;
+    const int g = (int)(st->k % m);
+    const int t0 = goff[g];
+    const int T = goff[g + 1] - t0;
+    const int tw = sweep_tw(T);
+    const int per_block = kWavesPerBlock * tw;
+    if ((int)blockIdx.x * per_block >= T) return;
+    const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const double* Mi = M + (size_t)i * (i + 1) / 2;
-    double acc = 0.0;
-    for (int j = lane; j <= i; j += 64) acc = fma(Mi[j], b[j], acc);
-    acc = wave_sum(acc);
-    if (lane == 0) l[i] = acc;
-}
-
-// Partial column sums of u = M^T l: block (column tile x, row chunk y)
-// covers columns [x*kBlock, +kBlock) and rows [y*kBlock, +kBlock).
-__global__ __launch_bounds__(kBlock) void k_append_u(const GState* __restrict__ st, const double* __restrict__ M,
-                                                     const double* __restrict__ l, double* __restrict__ Pu,
-                                                     int64_t pu_stride) {
-    if (!st->app) return;
-    const int n = st->n;
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    const int r0 = blockIdx.y * kBlock;
-    if (r0 >= n || (int)(blockIdx.x * kBlock) >= n) return;
-    if (r0 + kBlock - 1 < (int)(blockIdx.x * kBlock)) return;   // block entirely above the diagonal
-    const int r1 = min(n, r0 + kBlock);
-    double acc = 0.0;
-    if (j < n) {
-        for (int i = max(r0, j); i < r1; ++i) acc = fma(M[(size_t)i * (i + 1) / 2 + j], l[i], acc);
-        Pu[(size_t)blockIdx.y * pu_stride + j] = acc;
+    const int tbase = blockIdx.x * per_block + wave * tw;
+    double tx[4], ty[4], tz[4], ax[4], ay[4], az[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int t = min(tbase + q, T - 1);
+        tx[q] = px[t0 + t];
+        ty[q] = py[t0 + t];
+        tz[q] = pz[t0 + t];
+        ax[q] = ay[q] = az[q] = 0.0;
     }
-}
-
-// Finish the append in one block: s = 1 - l.l, residual e = d_new - b.W,
-// new row of M = [-u^T / sqrt(s), 1 / sqrt(s)], W <- [W - u e / s; e / s].
-__global__ __launch_bounds__(1024) void k_append_finish(GState* __restrict__ st, const double* __restrict__ px,
-                                                        const double* __restrict__ py, const double* __restrict__ pz,
-                                                        const double* __restrict__ pdx, const double* __restrict__ pdy,
-                                                        const double* __restrict__ pdz, const int32_t* __restrict__ perm,
-                                                        uint8_t* __restrict__ inS, SupportMut sm,
-                                                        const double* __restrict__ b, const double* __restrict__ l,
-                                                        const double* __restrict__ Pu, int64_t pu_stride) {
-    if (!st->app) return;
-    const int n = st->n;
-    const int p = st->node_pos;
-    double ll = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int j = threadIdx.x; j < n; j += 1024) {
-        ll = fma(l[j], l[j], ll);
-        fx = fma(b[j], sm.wx[j], fx);
-        fy = fma(b[j], sm.wy[j], fy);
-        fz = fma(b[j], sm.wz[j], fz);
+    // lane handles supports lane, lane+64, ...; four supports' loads are issued before their use
+    int j = lane;
+    for (; j + 192 < n; j += 256) {
+        double sx[4], sy[4], sz[4], wx[4], wy[4], wz[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            sx[u] = sv.sx[j + 64 * u];
+            sy[u] = sv.sy[j + 64 * u];
+            sz[u] = sv.sz[j + 64 * u];
+            wx[u] = sv.wx[j + 64 * u];
+            wy[u] = sv.wy[j + 64 * u];
+            wz[u] = sv.wz[j + 64 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (q < tw) {
+                    const double phi = wendland_r2(dist2(tx[q], ty[q], tz[q], sx[u], sy[u], sz[u]));
+                    ax[q] = fma(wx[u], phi, ax[q]);
+                    ay[q] = fma(wy[u], phi, ay[q]);
+                    az[q] = fma(wz[u], phi, az[q]);
+                }
+            }
+        }
     }
-    ll = block_sum<1024>(ll);
-    fx = block_sum<1024>(fx);
-    fy = block_sum<1024>(fy);
-    fz = block_sum<1024>(fz);
-    __shared__ double sh[5];
-    __shared__ int bad;
-    if (threadIdx.x == 0) {
-        const double s = 1.0 - ll;
-        bad = !(s > kSingularTol);
-        sh[0] = s;
-        sh[1] = pdx[p] - fx;
-        sh[2] = pdy[p] - fy;
-        sh[3] = pdz[p] - fz;
-        sh[4] = 1.0 / sqrt(s);
+    for (; j < n; j += 64) {
+        const double sx = sv.sx[j], sy = sv.sy[j], sz = sv.sz[j];
+        const double wx = sv.wx[j], wy = sv.wy[j], wz = sv.wz[j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q < tw) {
+                const double phi = wendland_r2(dist2(tx[q], ty[q], tz[q], sx, sy, sz));
+                ax[q] = fma(wx, phi, ax[q]);
+                ay[q] = fma(wy, phi, ay[q]);
+                az[q] = fma(wz, phi, az[q]);
+            }
+        }
+    }
+    Best b{-1.0, 0x7fffffff, -1};
+    int32_t cnt = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (q < tw) {
+            const double fx = wave_sum(ax[q]), fy = wave_sum(ay[q]), fz = wave_sum(az[q]);
+            const int t = tbase + q;
+            if (t < T && !inS[t0 + t]) {
+                const double ex = fx - pdx[t0 + t], ey = fy - pdy[t0 + t], ez = fz - pdz[t0 + t];
+                const double e2 = fma(ez, ez, fma(ey, ey, ex * ex));
+                const int32_t o = perm[t0 + t];
+                if (better(e2, o, b.v, b.idx)) { b.v = e2; b.idx = o; b.aux = t0 + t; }
+                cnt += 1;
+            }
+        }
+    }
+    if (lane == 0) {
+        sb[wave] = b;
+        sc[wave] = cnt;
     }
     __syncthreads();
-    if (bad) {
+    if (threadIdx.x == 0) {
+        Best r = sb[0];
+        int32_t c = sc[0];
+        for (int w = 1; w < kWavesPerBlock; ++w) {
+            if (better(sb[w].v, sb[w].idx, r.v, r.idx)) r = sb[w];
+            c += sc[w];
+        }
+        rec[blockIdx.x] = ArgRec{r.v, r.idx, r.aux, c, 0};
+    }
+}
+
+// l = M b, one wave per row of M (16 rows per block).  b_j = phi(|r_new -
+// s_j| / R) is staged in LDS windows.  Block partials Pb[blk] = (b.W over
+// columns [i0, i0+16), l.l over rows [i0, i0+16)).  Before that, every block
+// reduces the sweep's block records to the group maximum and takes the
+// decision; block 0 stores it (log, state, iteration record).  With
+// init_t >= 0 the node is the starting node init[init_t] instead.
+__global__ __launch_bounds__(kBigBlock) void k_factor_l(
+    GState* __restrict__ st, IterRec* __restrict__ irec, const ArgRec* __restrict__ srec, int32_t m,
+    const int32_t* __restrict__ goff, int init_t, const int32_t* __restrict__ init, const int32_t* __restrict__ pos_of,
+    const double* __restrict__ px, const double* __restrict__ py, const double* __restrict__ pz, SupportView sv,
+    const double* __restrict__ Mr, double* __restrict__ l, double* __restrict__ Pb, double tol_abs, int64_t nc_max,
+    int64_t cap, int32_t* __restrict__ log_group, int32_t* __restrict__ log_node, double* __restrict__ log_err,
+    int8_t* __restrict__ log_app, int64_t log_cap) {
+    __shared__ double bw[kBWindow];
+    __shared__ double sl[kRowsL];
+    __shared__ int32_t s_app, s_pos, s_orig, s_n;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    if (init_t >= 0) {
         if (threadIdx.x == 0) {
+            s_app = 1;
+            s_orig = init[init_t];
+            s_pos = pos_of[s_orig];
+            s_n = init_t;
+            if (blockIdx.x == 0) {
+                irec->k = 0;
+                irec->n = init_t;
+                irec->app = 1;
+                irec->init = 1;
+                irec->ran = 0;
+                irec->node_pos = s_pos;
+                irec->node_orig = s_orig;
+                irec->singular = 0;
+                irec->E = 0.0;
+            }
+        }
+    } else {
+        // one snapshot of the state per block: block 0 updates it below, and
+        // every thread of a block must take the same branches
+        __shared__ GState s_st;
+        if (threadIdx.x == 0) s_st = *st;
+        __syncthreads();
+        const GState sg = s_st;
+        if (sg.done) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                irec->app = 0;
+                irec->ran = 0;
+            }
+            return;
+        }
+        const int n = sg.n;
+        const int g = (int)(sg.k % m);
+        const int T = goff[g + 1] - goff[g];
+        const int per_block = kWavesPerBlock * sweep_tw(T);
+        const int nrec = (T + per_block - 1) / per_block;
+        Best b{-1.0, 0x7fffffff, -1};
+        int32_t c = 0;
+        for (int i = threadIdx.x; i < nrec; i += kBigBlock) {
+            const ArgRec r = srec[i];
+            if (better(r.e2, r.orig, b.v, b.idx)) { b.v = r.e2; b.idx = r.orig; b.aux = r.pos; }
+            c += r.count;
+        }
+        b = big_block_best(b);
+        c = big_block_isum(c);
+        if (threadIdx.x == 0) {
+            const Decision d = decide_local(sg, n, m, b.v, tol_abs, nc_max, cap);
+            s_app = d.app;
+            s_pos = b.aux;
+            s_orig = b.idx;
+            s_n = n;
+            if (blockIdx.x == 0) {
+                if (d.done != 4) {
+                    const int64_t it = sg.log_len;
+                    if (it < log_cap) {
+                        log_group[it] = g;
+                        log_node[it] = b.v >= 0.0 ? b.idx : -1;
+                        log_err[it] = d.E;
+                        log_app[it] = (int8_t)d.app;
+                    }
+                    st->log_len = it + 1;
+                    st->pairs_group = sg.pairs_group + (uint64_t)c * (uint64_t)n;
+                }
+                st->quiet = d.quiet;
+                st->done = d.done;
+                irec->k = sg.k;
+                irec->n = n;
+                irec->app = d.app;
+                irec->init = 0;
+                irec->ran = d.done != 4;
+                irec->node_pos = d.app ? b.aux : -1;
+                irec->node_orig = d.app ? b.idx : -1;
+                irec->singular = 0;
+                irec->E = d.E;
+            }
+        }
+    }
+    __syncthreads();
+    if (!s_app) return;
+    const int n = s_n;
+    const int p = s_pos;
+    const int nblk = max(1, (n + kRowsL - 1) / kRowsL);
+    if ((int)blockIdx.x >= nblk) return;
+    const int i0 = blockIdx.x * kRowsL;
+    const int i1 = min(n, i0 + kRowsL);
+    const int i = i0 + wave;
+    const double qx = px[p], qy = py[p], qz = pz[p];
+    double acc = 0.0;
+    for (int w0 = 0; w0 < i1; w0 += kBWindow) {
+        const int w1 = min(i1, w0 + kBWindow);
+        __syncthreads();
+        for (int j = w0 + threadIdx.x; j < w1; j += kBigBlock)
+            bw[j - w0] = wendland_r2(dist2(qx, qy, qz, sv.sx[j], sv.sy[j], sv.sz[j]));
+        __syncthreads();
+        if (i < i1) {
+            const double* Mi = Mr + (size_t)i * (i + 1) / 2;
+            const int je = min(w1, i + 1);
+            double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int j = w0 + lane;
+            for (; j + 192 < je; j += 256) {
+                const double m0 = Mi[j], m1 = Mi[j + 64], m2 = Mi[j + 128], m3 = Mi[j + 192];
+                acc = fma(m0, bw[j - w0], acc);
+                a1 = fma(m1, bw[j + 64 - w0], a1);
+                a2 = fma(m2, bw[j + 128 - w0], a2);
+                a3 = fma(m3, bw[j + 192 - w0], a3);
+            }
+            for (; j < je; j += 64) acc = fma(Mi[j], bw[j - w0], acc);
+            acc = (acc + a1) + (a2 + a3);
+        }
+    }
+    const double li = wave_sum(acc);
+    if (lane == 0 && i < i1) {
+        l[i] = li;
+        sl[wave] = li;
+    }
+    __syncthreads();
+    if (wave == 0) {
+        // this block's share of b.W (columns i0..i1-1) and of l.l (rows i0..i1-1), xor-tree order
+        double fx = 0.0, fy = 0.0, fz = 0.0, ll = 0.0;
+        const int j = i0 + lane;
+        if (lane < kRowsL && j < i1) {
+            const double bj = wendland_r2(dist2(qx, qy, qz, sv.sx[j], sv.sy[j], sv.sz[j]));
+            fx = bj * sv.wx[j];
+            fy = bj * sv.wy[j];
+            fz = bj * sv.wz[j];
+            ll = sl[lane] * sl[lane];
+        }
+        fx = wave_sum(fx);
+        fy = wave_sum(fy);
+        fz = wave_sum(fz);
+        ll = wave_sum(ll);
+        if (lane == 0) {
+            Pb[4 * blockIdx.x + 0] = fx;
+            Pb[4 * blockIdx.x + 1] = fy;
+            Pb[4 * blockIdx.x + 2] = fz;
+            Pb[4 * blockIdx.x + 3] = ll;
+        }
+    }
+}
+
+// u = M^T l, one wave per column j of M read from the column-major copy Mc
+// (column j holds rows j.. at offset j*cap - j(j-1)/2).  Every block first
+// sums the k_factor_l partials in block order to s = 1 - l.l and
+// e = d_new - b.W.  Writes the new row [-u^T/sqrt(s), 1/sqrt(s)] into both
+// copies of M and W <- [W - u e/s; e/s]; block 0 commits the iteration.
+__global__ __launch_bounds__(kBigBlock) void k_factor_u(
+    GState* __restrict__ st, IterRec* __restrict__ irec, const double* __restrict__ px, const double* __restrict__ py,
+    const double* __restrict__ pz, const double* __restrict__ pdx, const double* __restrict__ pdy,
+    const double* __restrict__ pdz, const int32_t* __restrict__ perm, uint8_t* __restrict__ inS, SupportMut sm,
+    double* __restrict__ Mc, int64_t cap, const double* __restrict__ l, const double* __restrict__ Pb) {
+    __shared__ double part[4][kBigBlock / 64];
+    __shared__ double sh[5];
+    __shared__ int32_t s_bad;
+    // the iteration record is only read here (k_factor_l wrote it), so every
+    // block sees the same values
+    const IterRec r = *irec;
+    if (!r.app) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && r.ran) st->k = r.k + 1;
+        return;
+    }
+    const int n = r.n;
+    const int p = r.node_pos;
+    const int nbl = max(1, (n + kRowsL - 1) / kRowsL);
+    const int ncb = max(1, (n + kRowsL - 1) / kRowsL);
+    if ((int)blockIdx.x >= ncb) return;
+    {
+        // fixed-order reduction: per thread in block order, xor tree per wave, waves in order
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b = threadIdx.x; b < nbl; b += kBigBlock)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] += Pb[4 * b + c];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            v[c] = wave_sum(v[c]);
+            if ((threadIdx.x & 63) == 0) part[c][threadIdx.x >> 6] = v[c];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double f[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int t = 0; t < kBigBlock / 64; ++t)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) f[c] += part[c][t];
+            const double s = 1.0 - f[3];
+            s_bad = !(s > kSingularTol);
+            sh[0] = 1.0 / sqrt(s);
+            sh[1] = (pdx[p] - f[0]) / s;
+            sh[2] = (pdy[p] - f[1]) / s;
+            sh[3] = (pdz[p] - f[2]) / s;
+        }
+        __syncthreads();
+    }
+    if (s_bad) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
             st->done = 3;
-            st->singular_node = st->node_orig;
-            st->app = 0;
+            st->singular_node = r.node_orig;
         }
         return;
     }
-    const double s = sh[0], ex = sh[1], ey = sh[2], ez = sh[3], rs = sh[4];
-    const double cx = ex / s, cy = ey / s, cz = ez / s;
-    double* Mn = sm.M + (size_t)n * (n + 1) / 2;
-    const int nrow = (n + kBlock - 1) / kBlock;
-    for (int j = threadIdx.x; j < n; j += 1024) {
-        double u = 0.0;
-        for (int r = j / kBlock; r < nrow; ++r) u += Pu[(size_t)r * pu_stride + j];
-        Mn[j] = -u * rs;
-        sm.wx[j] = fma(-u, cx, sm.wx[j]);
-        sm.wy[j] = fma(-u, cy, sm.wy[j]);
-        sm.wz[j] = fma(-u, cz, sm.wz[j]);
+    const double rs = sh[0], cx = sh[1], cy = sh[2], cz = sh[3];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * kRowsL + wave;
+    if (j < n) {
+        const double* col = Mc + (size_t)j * cap - (size_t)j * (j - 1) / 2;   // rows j.. of column j
+        double a0 = 0.0, a1 = 0.0;
+        int i = j + lane;
+        for (; i + 64 < n; i += 128) {
+            a0 = fma(col[i - j], l[i], a0);
+            a1 = fma(col[i + 64 - j], l[i + 64], a1);
+        }
+        if (i < n) a0 = fma(col[i - j], l[i], a0);
+        const double u = wave_sum(a0 + a1);
+        if (lane == 0) {
+            const double v = -u * rs;
+            sm.M[(size_t)n * (n + 1) / 2 + j] = v;
+            Mc[(size_t)j * cap - (size_t)j * (j - 1) / 2 + (n - j)] = v;
+            sm.wx[j] = fma(-u, cx, sm.wx[j]);
+            sm.wy[j] = fma(-u, cy, sm.wy[j]);
+            sm.wz[j] = fma(-u, cz, sm.wz[j]);
+        }
     }
-    if (threadIdx.x == 0) {
-        Mn[n] = rs;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sm.M[(size_t)n * (n + 1) / 2 + n] = rs;
+        Mc[(size_t)n * cap - (size_t)n * (n - 1) / 2] = rs;
         sm.wx[n] = cx;
         sm.wy[n] = cy;
         sm.wz[n] = cz;
@@ -403,10 +554,26 @@ __global__ __launch_bounds__(1024) void k_append_finish(GState* __restrict__ st,
         sm.orig[n] = perm[p];
         inS[p] = 1;
         st->n = n + 1;
-        st->app = 0;
-        if (st->init_left > 0) st->init_left -= 1;   // starting nodes are not loop appends
-        else st->pairs_append += (uint64_t)n;
+        if (r.init) {
+            st->init_left -= 1;   // starting nodes are not loop appends
+        } else {
+            st->pairs_append += (uint64_t)n;
+            st->k = r.k + 1;
+        }
     }
+}
+
+// Column-major copy of the first n rows of the packed row-major factor for
+// capacity cap (after the support arrays grow).
+__global__ __launch_bounds__(kBlock) void k_transpose_factor(const double* __restrict__ Mr, double* __restrict__ Mc,
+                                                             int n, int64_t cap) {
+    const int64_t x = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (x >= (int64_t)n * (n + 1) / 2) return;
+    int i = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(i + 1) * (i + 2) / 2 <= x) ++i;
+    while ((int64_t)i * (i + 1) / 2 > x) --i;
+    const int j = (int)(x - (int64_t)i * (i + 1) / 2);
+    Mc[(size_t)j * cap - (size_t)j * (j - 1) / 2 + (i - j)] = Mr[x];
 }
 
 // ---------------------------------------------------------------- starting nodes
@@ -443,16 +610,6 @@ __global__ __launch_bounds__(kBlock) void k_init_final(int mode, int nrec, const
         if (better(rec[i].e2, rec[i].orig, b.v, b.idx)) { b.v = rec[i].e2; b.idx = rec[i].orig; }
     b = block_best(b);
     if (threadIdx.x == 0) init[mode] = b.idx;
-}
-
-// Stage the t-th starting node as the node to append.
-__global__ void k_init_stage(GState* __restrict__ st, const int32_t* __restrict__ init, int t,
-                             const int32_t* __restrict__ pos_of) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int o = init[t];
-    st->app = 1;
-    st->node_orig = o;
-    st->node_pos = pos_of[o];
 }
 
 // ---------------------------------------------------------------- certificate (a6)
@@ -580,37 +737,42 @@ void launch_init_nodes(hipStream_t s, const Boundary& bd, int32_t* init, ArgRec*
     }
 }
 
-void launch_append(hipStream_t s, GState* st, const Boundary& bd, Support& sp, int n_ub) {
-    SupportView sv = view(sp);
-    SupportMut sm = mut(sp);
-    const unsigned nb_b = (unsigned)((n_ub + kBlock - 1) / kBlock);
-    GCB_LAUNCH(k_append_b, dim3(nb_b > 0 ? nb_b : 1), dim3(kBlock), s, st, bd.px, bd.py, bd.pz, sv, sp.b);
-    const unsigned nw = (unsigned)((n_ub + 3) / 4);
-    GCB_LAUNCH(k_append_l, dim3(nw > 0 ? nw : 1), dim3(kBlock), s, st, sp.M, sp.b, sp.l);
-    GCB_LAUNCH(k_append_u, dim3(nb_b > 0 ? nb_b : 1, nb_b > 0 ? nb_b : 1), dim3(kBlock), s, st, sp.M, sp.l, sp.Pu,
-               (int64_t)sp.cap);
-    GCB_LAUNCH(k_append_finish, dim3(1), dim3(1024), s, st, bd.px, bd.py, bd.pz, bd.pdx, bd.pdy, bd.pdz, bd.perm,
-               bd.inS, sm, sp.b, sp.l, sp.Pu, (int64_t)sp.cap);
+static void launch_factor(hipStream_t s, const IterCtx& ic, int n_ub, int init_t) {
+    const Boundary& bd = *ic.bd;
+    Support& sp = *ic.sp;
+    const unsigned g = (unsigned)std::max(1, (n_ub + kRowsL - 1) / kRowsL);
+    GCB_LAUNCH(k_factor_l, dim3(g), dim3(kBigBlock), s, ic.st, ic.irec, ic.srec, bd.m, bd.goff, init_t, ic.init,
+               bd.pos_of, bd.px, bd.py, bd.pz, view(sp), sp.M, sp.l, ic.Pb, ic.tol_abs, ic.nc_max, sp.cap,
+               ic.log_group, ic.log_node, ic.log_err, ic.log_app, ic.log_cap);
+    GCB_LAUNCH(k_factor_u, dim3(g), dim3(kBigBlock), s, ic.st, ic.irec, bd.px, bd.py, bd.pz, bd.pdx, bd.pdy, bd.pdz,
+               bd.perm, bd.inS, mut(sp), sp.Mc, sp.cap, sp.l, ic.Pb);
 }
 
-void launch_init_stage(hipStream_t s, GState* st, const int32_t* init, int t, const int32_t* pos_of) {
-    GCB_LAUNCH(k_init_stage, dim3(1), dim3(64), s, st, init, t, pos_of);
+void launch_init_append(hipStream_t s, const IterCtx& ic, int t) { launch_factor(s, ic, t, t); }
+
+// Blocks of k_sweep that cover every group size T <= gmax (the targets per
+// wave, and so the targets per block, grow with T).
+int sweep_blocks(int gmax) {
+    int best = 1;
+    for (int T : {std::min(gmax, 1023), std::min(gmax, 4095), gmax}) {
+        const int per_block = kWavesPerBlock * sweep_tw(T);
+        best = std::max(best, (T + per_block - 1) / per_block);
+    }
+    return best;
 }
 
-void launch_iteration(hipStream_t s, GState* st, const Boundary& bd, Support& sp, double* P, int32_t Tmax,
-                      ArgRec* rec, double tol_abs, int64_t nc_max, int64_t log_cap, int32_t* lg, int32_t* ln,
-                      double* le, int8_t* la, int n_ub) {
-    SupportView sv = view(sp);
-    // upper bound of waves over any group and any n <= n_ub: tiles of the largest group x kMaxChunks
-    const int64_t waves = (int64_t)((bd.gmax + 63) / 64) * kMaxChunks;
-    const unsigned gs = (unsigned)((waves * 64 + kBlock - 1) / kBlock);
-    GCB_LAUNCH(k_group_sweep64, dim3(gs), dim3(kBlock), s, st, bd.m, bd.goff, bd.px, bd.py, bd.pz, sv, P, Tmax);
-    const unsigned gr = (unsigned)((bd.gmax + kBlock - 1) / kBlock);
-    GCB_LAUNCH(k_group_reduce, dim3(gr), dim3(kBlock), s, st, bd.m, bd.goff, bd.pdx, bd.pdy, bd.pdz, bd.inS, bd.perm,
-               P, Tmax, rec);
-    GCB_LAUNCH(k_group_decide, dim3(1), dim3(kBlock), s, st, bd.m, bd.goff, rec, tol_abs, nc_max, sp.cap, lg, ln, le, la,
-               log_cap);
-    launch_append(s, st, bd, sp, n_ub);
+void launch_iteration(hipStream_t s, const IterCtx& ic, int n_ub) {
+    const Boundary& bd = *ic.bd;
+    const unsigned gs = (unsigned)sweep_blocks(bd.gmax);
+    GCB_LAUNCH(k_sweep, dim3(gs), dim3(kBlock), s, ic.st, bd.m, bd.goff, bd.px, bd.py, bd.pz, bd.pdx, bd.pdy, bd.pdz,
+               bd.inS, bd.perm, view(*ic.sp), ic.srec);
+    launch_factor(s, ic, n_ub, -1);
+}
+
+void launch_transpose_factor(hipStream_t s, const double* Mr, double* Mc, int n, int64_t cap) {
+    const int64_t cnt = (int64_t)n * (n + 1) / 2;
+    if (cnt == 0) return;
+    GCB_LAUNCH(k_transpose_factor, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock), s, Mr, Mc, n, cap);
 }
 
 void launch_certify(hipStream_t s, const Boundary& bd, const Support& sp, int n, double* red, double* out) {

@@ -95,9 +95,8 @@ void copy_out(gcb_ctx* ctx, void* dst, const void* src, size_t bytes, int mem) {
 void free_support(Support& sp) {
     dfree(sp.sx); dfree(sp.sy); dfree(sp.sz); dfree(sp.wx); dfree(sp.wy); dfree(sp.wz);
     dfree(sp.fsx); dfree(sp.fsy); dfree(sp.fsz); dfree(sp.fwx); dfree(sp.fwy); dfree(sp.fwz);
-    dfree(sp.orig); dfree(sp.M); dfree(sp.b); dfree(sp.l); dfree(sp.Pu);
+    dfree(sp.orig); dfree(sp.M); dfree(sp.Mc); dfree(sp.l);
     sp.cap = 0;
-    sp.pu_rows = 0;
 }
 
 void free_boundary(Boundary& bd) {
@@ -109,19 +108,18 @@ void free_boundary(Boundary& bd) {
 }
 
 // (Re)allocate the support arrays for capacity `cap`, keeping the first n
-// entries (and the first n rows of the packed factor).
+// supports and the first n rows of the factor (both copies).
 void grow_support(gcb_ctx* ctx, int64_t cap, int64_t n) {
     Support& sp = ctx->sp;
     Support nw;
     nw.cap = cap;
+    const size_t tri = (size_t)cap * (size_t)(cap + 1) / 2;
     dalloc(ctx, nw.sx, cap); dalloc(ctx, nw.sy, cap); dalloc(ctx, nw.sz, cap);
     dalloc(ctx, nw.wx, cap); dalloc(ctx, nw.wy, cap); dalloc(ctx, nw.wz, cap);
     dalloc(ctx, nw.orig, cap);
-    dalloc(ctx, nw.M, (size_t)cap * (size_t)(cap + 1) / 2);
-    dalloc(ctx, nw.b, cap);
+    dalloc(ctx, nw.M, tri);
+    dalloc(ctx, nw.Mc, tri);
     dalloc(ctx, nw.l, cap);
-    nw.pu_rows = (cap + kBlock - 1) / kBlock;
-    dalloc(ctx, nw.Pu, (size_t)nw.pu_rows * (size_t)cap);
     if (n > 0 && sp.cap > 0) {
         const size_t b8 = sizeof(double) * (size_t)n;
         HIPCHK(ctx, hipMemcpyAsync(nw.sx, sp.sx, b8, hipMemcpyDeviceToDevice, ctx->stream));
@@ -133,10 +131,17 @@ void grow_support(gcb_ctx* ctx, int64_t cap, int64_t n) {
         HIPCHK(ctx, hipMemcpyAsync(nw.orig, sp.orig, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, ctx->stream));
         HIPCHK(ctx, hipMemcpyAsync(nw.M, sp.M, sizeof(double) * (size_t)n * (size_t)(n + 1) / 2, hipMemcpyDeviceToDevice,
                                    ctx->stream));
+        launch_transpose_factor(ctx->stream, nw.M, nw.Mc, (int)n, cap);
+        HIPCHK(ctx, hipGetLastError());
         sync(ctx);
     }
     free_support(sp);
     sp = nw;
+    const int64_t nbl = (cap + kRowsL - 1) / kRowsL + 1;
+    if (ctx->Pb_cap < 4 * nbl) {
+        ctx->Pb_cap = 4 * nbl;
+        dalloc(ctx, ctx->Pb, ctx->Pb_cap);
+    }
 }
 
 template <typename T>
@@ -224,21 +229,20 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     const gcb_params& p = ctx->params;
     Boundary& bd = ctx->bd;
     const int64_t cap0 = std::min<int64_t>(p.nc_max, 1024);
-    free_support(ctx->sp);
-    grow_support(ctx, cap0, 0);
-    const int64_t nrec = std::max<int64_t>(1024, (bd.gmax + kBlock - 1) / kBlock);
+    if (ctx->sp.cap < cap0 || ctx->sp.cap > p.nc_max) {
+        free_support(ctx->sp);
+        grow_support(ctx, cap0, 0);
+    }
+    const int64_t nrec = std::max<int64_t>(512, sweep_blocks(bd.gmax));
     if (ctx->argrec_cap < nrec + 1) {
         ctx->argrec_cap = nrec + 1;   // the last record holds the three starting nodes
         dalloc(ctx, ctx->argrec, ctx->argrec_cap);
     }
-    const int64_t pneed = (int64_t)kMaxChunks * 3 * bd.gmax;
-    if (ctx->P_cap < pneed) {
-        ctx->P_cap = pneed;
-        dalloc(ctx, ctx->P, pneed);
-    }
     if (!ctx->state) dalloc(ctx, ctx->state, 1);
+    if (!ctx->irec) dalloc(ctx, ctx->irec, 1);
+    HIPCHK(ctx, hipMemsetAsync(ctx->irec, 0, sizeof(IterRec), ctx->stream));
     if (ctx->log_cap == 0) grow_log(ctx, 0, 65536);
-    int32_t* init = reinterpret_cast<int32_t*>(ctx->argrec + ctx->argrec_cap - 1);   // 3 ints in a spare record
+    int32_t* init = reinterpret_cast<int32_t*>(ctx->argrec + ctx->argrec_cap - 1);
     static_assert(sizeof(ArgRec) >= 3 * sizeof(int32_t), "record too small");
 
     hipEvent_t ev0, ev1;
@@ -249,8 +253,6 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     GState st{};
     st.k = 3;
     st.init_left = 3;
-    st.node_pos = -1;
-    st.node_orig = -1;
     st.singular_node = -1;
     HIPCHK(ctx, hipMemcpyAsync(ctx->state, &st, sizeof(st), hipMemcpyHostToDevice, ctx->stream));
     if (p.use_init) {
@@ -260,12 +262,30 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     } else {
         launch_init_nodes(ctx->stream, bd, init, ctx->argrec);
     }
-    for (int t = 0; t < 3; ++t) {
-        launch_init_stage(ctx->stream, ctx->state, init, t, bd.pos_of);
-        launch_append(ctx->stream, ctx->state, bd, ctx->sp, t);
+    auto make_ic = [&]() {
+        IterCtx ic;
+        ic.st = ctx->state;
+        ic.irec = ctx->irec;
+        ic.srec = ctx->argrec;
+        ic.init = init;
+        ic.bd = &ctx->bd;
+        ic.sp = &ctx->sp;
+        ic.Pb = ctx->Pb;
+        ic.tol_abs = p.tol_abs;
+        ic.nc_max = p.nc_max;
+        ic.log_cap = ctx->log_cap;
+        ic.log_group = ctx->log_group;
+        ic.log_node = ctx->log_node;
+        ic.log_err = ctx->log_err;
+        ic.log_app = ctx->log_app;
+        return ic;
+    };
+    {
+        IterCtx ic = make_ic();
+        for (int t = 0; t < 3; ++t) launch_init_append(ctx->stream, ic, t);
     }
     HIPCHK(ctx, hipGetLastError());
-    const int chunk = 32;
+    const int chunk = 64;
     for (;;) {
         HIPCHK(ctx, hipMemcpyAsync(&ctx->state_h, ctx->state, sizeof(GState), hipMemcpyDeviceToHost, ctx->stream));
         sync(ctx);
@@ -281,10 +301,10 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
             grow_support(ctx, cap, h.n);
         }
         if (h.log_len + chunk > ctx->log_cap) grow_log(ctx, h.log_len, std::max<int64_t>(2 * ctx->log_cap, h.log_len + chunk));
+        IterCtx ic = make_ic();
         for (int it = 0; it < chunk; ++it) {
             const int n_ub = (int)n_upper(ctx, h.n, it + 1);
-            launch_iteration(ctx->stream, ctx->state, bd, ctx->sp, ctx->P, bd.gmax, ctx->argrec, p.tol_abs, p.nc_max,
-                             ctx->log_cap, ctx->log_group, ctx->log_node, ctx->log_err, ctx->log_app, n_ub);
+            launch_iteration(ctx->stream, ic, n_ub);
         }
         HIPCHK(ctx, hipGetLastError());
     }
@@ -390,7 +410,7 @@ void gcb_destroy(gcb_ctx* ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     free_boundary(ctx->bd);
     free_support(ctx->sp);
-    dfree(ctx->state); dfree(ctx->argrec); dfree(ctx->P); dfree(ctx->red);
+    dfree(ctx->state); dfree(ctx->argrec); dfree(ctx->red); dfree(ctx->irec); dfree(ctx->Pb);
     dfree(ctx->log_group); dfree(ctx->log_node); dfree(ctx->log_err); dfree(ctx->log_app);
     if (ctx->tmp) (void)hipFree(ctx->tmp);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
@@ -401,12 +421,9 @@ const char* gcb_last_error(const gcb_ctx* ctx) { return ctx ? ctx->err.c_str() :
 
 int gcb_set_stream(gcb_ctx* ctx, void* hip_stream) {
     return guard(ctx, [&] {
-        ctx->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->own_stream;
-        if (!ctx->stream) {
-            HIPCHK(ctx, hipSetDevice(ctx->device));
-            HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking));
-            ctx->stream = ctx->own_stream;
-        }
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));   // work already enqueued finishes first
+        ctx->stream = static_cast<hipStream_t>(hip_stream);
         return GCB_OK;
     });
 }
