@@ -47,8 +47,8 @@ struct IterRec {
     int32_t singular;     // set by the factor kernel: phi0 - l.l <= tolerance
     int32_t pad;
     double E;             // group maximum error
-    double rs;            // 1 / sqrt(s), s = 1 - l.l
-    double cx, cy, cz;    // e / s, e = d_new - b.W
+    double x, y, z;       // the node's scaled coordinates
+    double dx, dy, dz;    // its prescribed displacement
 };
 
 // Per-block argmax record.
@@ -58,6 +58,8 @@ struct ArgRec {
     int32_t pos;          // permuted position
     int32_t count;        // candidates (not in S) seen
     int32_t pad;
+    double x, y, z;       // the candidate's scaled coordinates
+    double dx, dy, dz;    // and its prescribed displacement
 };
 
 struct Boundary {
@@ -75,6 +77,8 @@ struct Boundary {
     // original order (unscaled) for the starting-node rule
     double *xyz0 = nullptr, *disp0 = nullptr;
     int32_t gmax = 0;            // largest group size
+    int64_t alloc_nb = 0;        // size the permuted arrays were allocated for
+    int32_t alloc_m = 0;         // groups goff was allocated for
     std::vector<int32_t> goff_h;
 };
 
@@ -88,6 +92,14 @@ struct Support {
     double *Mc = nullptr;        // the same factor by columns: column j (rows j..cap-1) at j*cap - j(j-1)/2
     double *l = nullptr;         // append scratch: l = M b (cap)
 };
+
+// Launch-shape choices (process-wide; read from GCB_SWEEP_LPT and GCB_GRAPH
+// when the first context is created).
+struct Tuning {
+    int sweep_lpt_max = 256;   // 64, 128 or 256 lanes sharing one target in the group sweep
+    bool use_graph = true;     // replay chunks of iterations as captured hipGraphs
+};
+extern Tuning g_tuning;
 
 }  // namespace gcb
 
@@ -117,6 +129,12 @@ struct gcb_ctx {
     int64_t log_cap = 0;
     bool selected = false;
     gcb_select_info info{};
+    // captured chunk of greedy iterations (replayed while its key is unchanged)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t chunk_exec = nullptr;
+    std::vector<int64_t> chunk_key;
+    uint64_t alloc_gen = 0;            // bumped by every device allocation
+    gcb::GState *state_pin = nullptr;   // pinned host copy of the state
     // scratch for certificate / volume
     double *red = nullptr;
     int64_t red_cap = 0;

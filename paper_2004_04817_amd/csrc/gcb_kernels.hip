@@ -164,15 +164,38 @@ __device__ int32_t big_block_isum(int32_t v) {
 // One greedy iteration is three kernels; kernel boundaries are the only
 // grid-wide synchronisation (no atomics, no spin waits), and every reduction
 // runs in a fixed order, so results never depend on scheduling.
-//   k_sweep   group sweep (a3): a wave owns `tw` targets of the active group
-//             and its 64 lanes split the n supports; per-block best record.
-//   k_factor_l decision (a4) from the block records, then b and l = M b (a5).
+//   k_sweep    group sweep (a3): lanes of a block split the supports of a
+//              few targets of the active group; one best record per block.
+//   k_factor_l decision (a4) from the block records, b and l = M b (a5).
 //   k_factor_u u = M^T l, new row of M, W update, commit of the iteration.
+// The active group (g, its first permuted position t0, its size T) is a
+// kernel argument: k advances by one every iteration, so the host knows it.
+// Loads that do not depend on the decision are issued before it.
 
-__host__ __device__ inline int sweep_tw(int T) { return T >= 4096 ? 4 : (T >= 1024 ? 2 : 1); }
+// Layout of a group sweep of T targets: `lpt` lanes share one target,
+// each lane holds `tpl` targets; a block of kBlock threads holds
+// (kBlock / lpt) * tpl targets.
+Tuning g_tuning;
 
-// Algorithm 1's decision for iteration k from the group's best candidate.
-// Computed identically by every block of k_factor_l; only block 0 stores it.
+// lanes per target (lpt <= the tuning cap) and targets per lane for a group of T targets
+inline void sweep_layout(int T, int& lpt, int& tpl) {
+    // one wave per target measured fastest for groups of ~10^3 (each target reads every support
+    // once, so wider layouts only add reduction work); bigger groups hold 2-4 targets per lane
+    if (T <= 512) { lpt = 128; tpl = 1; }
+    else if (T <= 4096) { lpt = 64; tpl = 1; }
+    else if (T <= 8192) { lpt = 64; tpl = 2; }
+    else { lpt = 64; tpl = 4; }
+    if (lpt > g_tuning.sweep_lpt_max) lpt = g_tuning.sweep_lpt_max;
+}
+
+inline int sweep_nblocks(int T) {
+    int lpt, tpl;
+    sweep_layout(T, lpt, tpl);
+    const int per = (kBlock / lpt) * tpl;
+    return T > 0 ? (T + per - 1) / per : 1;
+}
+
+// Algorithm 1's decision for the iteration from the group's best candidate.
 struct Decision {
     int32_t app, done, quiet;
     double E;
@@ -193,7 +216,7 @@ __device__ __forceinline__ Decision decide_local(const GState& st, int n, int32_
         } else if (n >= nc_max) {
             d.done = 2;
         } else {
-            d.done = 4;   // factor capacity: the host grows the arrays and this iteration runs again
+            d.done = 4;   // factor capacity exhausted: the host reports an internal error
         }
     } else {
         d.quiet += 1;
@@ -202,53 +225,73 @@ __device__ __forceinline__ Decision decide_local(const GState& st, int n, int32_
     return d;
 }
 
-__global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st, int32_t m,
-                                                  const int32_t* __restrict__ goff, const double* __restrict__ px,
-                                                  const double* __restrict__ py, const double* __restrict__ pz,
-                                                  const double* __restrict__ pdx, const double* __restrict__ pdy,
-                                                  const double* __restrict__ pdz, const uint8_t* __restrict__ inS,
-                                                  const int32_t* __restrict__ perm, SupportView sv,
-                                                  ArgRec* __restrict__ rec) {
-    __shared__ Best sb[kWavesPerBlock];
-    __shared__ int32_t sc[kWavesPerBlock];
-    if (st->done) return;
-    const int n = st->n;
-    const int g = (int)(st->k % m);
-    const int t0 = goff[g];
-    const int T = goff[g + 1] - t0;
-    const int tw = sweep_tw(T);
-    const int per_block = kWavesPerBlock * tw;
-    if ((int)blockIdx.x * per_block >= T) return;
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int tbase = blockIdx.x * per_block + wave * tw;
-    double tx[4], ty[4], tz[4], ax[4], ay[4], az[4];
+__device__ __forceinline__ bool better_rec(const ArgRec& a, const ArgRec& b) { return better(a.e2, a.orig, b.e2, b.orig); }
+
+constexpr int kPre = 4;   // supports per lane loaded before |S| is known
+
+__global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st, int t0, int T, int lpt, int tpl,
+                                                  const double* __restrict__ px, const double* __restrict__ py,
+                                                  const double* __restrict__ pz, const double* __restrict__ pdx,
+                                                  const double* __restrict__ pdy, const double* __restrict__ pdz,
+                                                  const uint8_t* __restrict__ inS, const int32_t* __restrict__ perm,
+                                                  SupportView sv, int64_t cap, ArgRec* __restrict__ rec) {
+    __shared__ double red[3][4][kBlock / 64];
+    __shared__ int32_t s_n, s_done;
+    const int groups = kBlock / lpt;                // target groups per block
+    const int grp = threadIdx.x / lpt;
+    const int gl = threadIdx.x % lpt;               // lane within the group
+    const int tbase = (blockIdx.x * groups + grp) * tpl;
+    if (threadIdx.x == 0) {
+        s_n = st->n;
+        s_done = st->done;
+    }
+    // the group's targets and the first supports, loaded while |S| is in flight
+    double tx[4], ty[4], tz[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int t = min(tbase + q, T - 1);
         tx[q] = px[t0 + t];
         ty[q] = py[t0 + t];
         tz[q] = pz[t0 + t];
-        ax[q] = ay[q] = az[q] = 0.0;
     }
-    // lane handles supports lane, lane+64, ...; four supports' loads are issued before their use
-    int j = lane;
-    for (; j + 192 < n; j += 256) {
-        double sx[4], sy[4], sz[4], wx[4], wy[4], wz[4];
+    // what the candidate threads (one per (group, q)) need at the end
+    const int ncand = groups * 4;
+    double cdx = 0.0, cdy = 0.0, cdz = 0.0;
+    int32_t corig = 0x7fffffff;
+    bool clive = false;
+    int ct = 0;
+    if ((int)threadIdx.x < ncand) {
+        const int gq = threadIdx.x / 4, q = threadIdx.x % 4;
+        ct = (blockIdx.x * groups + gq) * tpl + q;
+        clive = q < tpl && ct < T;
+        const int tc = min(ct, T - 1);
+        clive = clive && !inS[t0 + tc];
+        cdx = pdx[t0 + tc];
+        cdy = pdy[t0 + tc];
+        cdz = pdz[t0 + tc];
+        corig = perm[t0 + tc];
+    }
+    double sx[kPre], sy[kPre], sz[kPre], wx[kPre], wy[kPre], wz[kPre];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            sx[u] = sv.sx[j + 64 * u];
-            sy[u] = sv.sy[j + 64 * u];
-            sz[u] = sv.sz[j + 64 * u];
-            wx[u] = sv.wx[j + 64 * u];
-            wy[u] = sv.wy[j + 64 * u];
-            wz[u] = sv.wz[j + 64 * u];
-        }
+    for (int u = 0; u < kPre; ++u) {
+        const int j = min(gl + lpt * u, (int)cap - 1);
+        sx[u] = sv.sx[j];
+        sy[u] = sv.sy[j];
+        sz[u] = sv.sz[j];
+        wx[u] = sv.wx[j];
+        wy[u] = sv.wy[j];
+        wz[u] = sv.wz[j];
+    }
+    __syncthreads();
+    if (s_done) return;
+    const int n = s_n;
+    double ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0}, az[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < kPre; ++u) {
+        if (gl + lpt * u < n) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                if (q < tw) {
+                if (q < tpl) {
                     const double phi = wendland_r2(dist2(tx[q], ty[q], tz[q], sx[u], sy[u], sz[u]));
                     ax[q] = fma(wx[u], phi, ax[q]);
                     ay[q] = fma(wy[u], phi, ay[q]);
@@ -257,178 +300,326 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st,
             }
         }
     }
-    for (; j < n; j += 64) {
-        const double sx = sv.sx[j], sy = sv.sy[j], sz = sv.sz[j];
-        const double wx = sv.wx[j], wy = sv.wy[j], wz = sv.wz[j];
+    for (int j0 = gl + lpt * kPre; j0 < n; j0 += lpt * kPre) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (q < tw) {
-                const double phi = wendland_r2(dist2(tx[q], ty[q], tz[q], sx, sy, sz));
-                ax[q] = fma(wx, phi, ax[q]);
-                ay[q] = fma(wy, phi, ay[q]);
-                az[q] = fma(wz, phi, az[q]);
+        for (int u = 0; u < kPre; ++u) {
+            const int j = min(j0 + lpt * u, (int)cap - 1);
+            sx[u] = sv.sx[j];
+            sy[u] = sv.sy[j];
+            sz[u] = sv.sz[j];
+            wx[u] = sv.wx[j];
+            wy[u] = sv.wy[j];
+            wz[u] = sv.wz[j];
+        }
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            if (j0 + lpt * u < n) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q < tpl) {
+                        const double phi = wendland_r2(dist2(tx[q], ty[q], tz[q], sx[u], sy[u], sz[u]));
+                        ax[q] = fma(wx[u], phi, ax[q]);
+                        ay[q] = fma(wy[u], phi, ay[q]);
+                        az[q] = fma(wz[u], phi, az[q]);
+                    }
+                }
             }
         }
     }
-    Best b{-1.0, 0x7fffffff, -1};
-    int32_t cnt = 0;
+    // sum over the lpt lanes of each target: xor tree per wave, then the waves of a group in order
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        if (q < tw) {
-            const double fx = wave_sum(ax[q]), fy = wave_sum(ay[q]), fz = wave_sum(az[q]);
-            const int t = tbase + q;
-            if (t < T && !inS[t0 + t]) {
-                const double ex = fx - pdx[t0 + t], ey = fy - pdy[t0 + t], ez = fz - pdz[t0 + t];
-                const double e2 = fma(ez, ez, fma(ey, ey, ex * ex));
-                const int32_t o = perm[t0 + t];
-                if (better(e2, o, b.v, b.idx)) { b.v = e2; b.idx = o; b.aux = t0 + t; }
-                cnt += 1;
+        if (q < tpl) {
+            ax[q] = wave_sum(ax[q]);
+            ay[q] = wave_sum(ay[q]);
+            az[q] = wave_sum(az[q]);
+            if (lane == 0) {
+                red[0][q][wave] = ax[q];
+                red[1][q][wave] = ay[q];
+                red[2][q][wave] = az[q];
             }
         }
     }
-    if (lane == 0) {
-        sb[wave] = b;
-        sc[wave] = cnt;
+    __syncthreads();
+    // one thread per (group, q): error of target tbase + q; the best is chosen on
+    // (e^2, original index) only, then its owner writes the full record
+    __shared__ double s_e2[kBlock / 64 * 4];
+    __shared__ int32_t s_or[kBlock / 64 * 4], s_cnt[kBlock / 64 * 4];
+    __shared__ int32_t s_win, s_tot;
+    double e2 = -1.0;
+    if ((int)threadIdx.x < ncand) {
+        const int gq = threadIdx.x / 4, q = threadIdx.x % 4;
+        if (clive) {
+            const int wpg = lpt / 64;   // waves per group
+            double fx = 0.0, fy = 0.0, fz = 0.0;
+            for (int w = 0; w < wpg; ++w) {
+                fx += red[0][q][gq * wpg + w];
+                fy += red[1][q][gq * wpg + w];
+                fz += red[2][q][gq * wpg + w];
+            }
+            const double ex = fx - cdx, ey = fy - cdy, ez = fz - cdz;
+            e2 = fma(ez, ez, fma(ey, ey, ex * ex));
+        }
+        s_e2[threadIdx.x] = e2;
+        s_or[threadIdx.x] = clive ? corig : 0x7fffffff;
+        s_cnt[threadIdx.x] = clive ? 1 : 0;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        Best r = sb[0];
-        int32_t c = sc[0];
-        for (int w = 1; w < kWavesPerBlock; ++w) {
-            if (better(sb[w].v, sb[w].idx, r.v, r.idx)) r = sb[w];
-            c += sc[w];
+        int bi = 0, c = s_cnt[0];
+        for (int i = 1; i < ncand; ++i) {
+            if (better(s_e2[i], s_or[i], s_e2[bi], s_or[bi])) bi = i;
+            c += s_cnt[i];
         }
-        rec[blockIdx.x] = ArgRec{r.v, r.idx, r.aux, c, 0};
+        s_win = bi;
+        s_tot = c;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x == s_win) {
+        ArgRec& o = rec[blockIdx.x];
+        o.e2 = e2;
+        o.orig = clive ? corig : 0x7fffffff;
+        o.pos = t0 + ct;
+        o.count = s_tot;
+        // the winner is one of the block's targets: its coordinates are in registers of some lane;
+        // re-read them here (one thread, off the critical path of the other blocks)
+        const int tc = min(ct, T - 1);
+        o.x = px[t0 + tc];
+        o.y = py[t0 + tc];
+        o.z = pz[t0 + tc];
+        o.dx = cdx;
+        o.dy = cdy;
+        o.dz = cdz;
     }
 }
 
-// l = M b, one wave per row of M (16 rows per block).  b_j = phi(|r_new -
-// s_j| / R) is staged in LDS windows.  Block partials Pb[blk] = (b.W over
-// columns [i0, i0+16), l.l over rows [i0, i0+16)).  Before that, every block
-// reduces the sweep's block records to the group maximum and takes the
-// decision; block 0 stores it (log, state, iteration record).  With
-// init_t >= 0 the node is the starting node init[init_t] instead.
+// l = M b, one wave per row of M (kRowsL rows per block); b_j = phi(|r_new -
+// s_j| / R) staged in LDS windows.  Block partials Pb[blk] = (b.W over
+// columns [i0, i0 + kRowsL), l.l over rows [i0, i0 + kRowsL)).  Before that,
+// every block reduces the sweep records (nrec of them) to the group maximum
+// and takes the decision; block 0 stores it.  With init_t >= 0 the node is
+// the starting node init[init_t] instead.
 __global__ __launch_bounds__(kBigBlock) void k_factor_l(
-    GState* __restrict__ st, IterRec* __restrict__ irec, const ArgRec* __restrict__ srec, int32_t m,
-    const int32_t* __restrict__ goff, int init_t, const int32_t* __restrict__ init, const int32_t* __restrict__ pos_of,
-    const double* __restrict__ px, const double* __restrict__ py, const double* __restrict__ pz, SupportView sv,
-    const double* __restrict__ Mr, double* __restrict__ l, double* __restrict__ Pb, double tol_abs, int64_t nc_max,
-    int64_t cap, int32_t* __restrict__ log_group, int32_t* __restrict__ log_node, double* __restrict__ log_err,
+    GState* __restrict__ st, IterRec* __restrict__ irec, const ArgRec* __restrict__ srec, int nrec, int32_t m, int g,
+    int init_t, const int32_t* __restrict__ init, const int32_t* __restrict__ pos_of, const double* __restrict__ px,
+    const double* __restrict__ py, const double* __restrict__ pz, const double* __restrict__ pdx,
+    const double* __restrict__ pdy, const double* __restrict__ pdz, SupportView sv, const double* __restrict__ Mr,
+    double* __restrict__ l, double* __restrict__ Pb, double tol_abs, int64_t nc_max, int64_t cap,
+    int32_t* __restrict__ log_group, int32_t* __restrict__ log_node, double* __restrict__ log_err,
     int8_t* __restrict__ log_app, int64_t log_cap) {
     __shared__ double bw[kBWindow];
     __shared__ double sl[kRowsL];
-    __shared__ int32_t s_app, s_pos, s_orig, s_n;
+    __shared__ GState s_st;
+    __shared__ double s_we2[kBigBlock / 64];
+    __shared__ int32_t s_wor[kBigBlock / 64], s_wri[kBigBlock / 64], s_cnt[kBigBlock / 64];
+    __shared__ double s_win[6];
+    __shared__ int32_t s_winpos;
+    __shared__ int32_t s_app, s_n;
+    __shared__ double s_q[3];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) s_st = *st;
+    // each thread keeps the best of its records on (e^2, original index), with its fields
+    double be2 = -1.0, bx = 0.0, by = 0.0, bz = 0.0, bdx = 0.0, bdy = 0.0, bdz = 0.0;
+    int32_t bor = 0x7fffffff, bpos = -1, c = 0;
+    if (init_t < 0) {
+        for (int i = threadIdx.x; i < nrec; i += kBigBlock) {
+            const ArgRec x = srec[i];
+            if (better(x.e2, x.orig, be2, bor)) {
+                be2 = x.e2; bor = x.orig; bpos = x.pos;
+                bx = x.x; by = x.y; bz = x.z; bdx = x.dx; bdy = x.dy; bdz = x.dz;
+            }
+            c += x.count;
+        }
+    }
+    // support coordinates of the first b window and of this block's b.W slice, loaded early
+    constexpr int kBPre = 2;
+    double pbx[kBPre], pby[kBPre], pbz[kBPre];
+#pragma unroll
+    for (int u = 0; u < kBPre; ++u) {
+        const int j = min((int)threadIdx.x + kBigBlock * u, (int)cap - 1);
+        pbx[u] = sv.sx[j];
+        pby[u] = sv.sy[j];
+        pbz[u] = sv.sz[j];
+    }
+    double wsx = 0.0, wsy = 0.0, wsz = 0.0, wwx = 0.0, wwy = 0.0, wwz = 0.0;
+    if (wave == 0 && lane < kRowsL) {
+        const int j = min((int)blockIdx.x * kRowsL + lane, (int)cap - 1);
+        wsx = sv.sx[j]; wsy = sv.sy[j]; wsz = sv.sz[j];
+        wwx = sv.wx[j]; wwy = sv.wy[j]; wwz = sv.wz[j];
+    }
+    __syncthreads();
+    const GState sg = s_st;
+    if (init_t < 0 && sg.done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            irec->app = 0;
+            irec->ran = 0;
+        }
+        return;
+    }
+    const int n = init_t >= 0 ? init_t : sg.n;
+    const int i0 = blockIdx.x * kRowsL;
+    const int i = i0 + wave;
+    // this wave's row of M, loaded while the decision is taken
+    constexpr int kRowPre = 16;
+    double mrow[kRowPre];
+    const double* Mi = Mr + (size_t)i * (i + 1) / 2;
+#pragma unroll
+    for (int u = 0; u < kRowPre; ++u) {
+        const int j = lane + 64 * u;
+        mrow[u] = (i < n && j <= i) ? Mi[j] : 0.0;
+    }
     if (init_t >= 0) {
         if (threadIdx.x == 0) {
+            const int o = init[init_t];
+            const int p = pos_of[o];
             s_app = 1;
-            s_orig = init[init_t];
-            s_pos = pos_of[s_orig];
             s_n = init_t;
+            s_q[0] = px[p];
+            s_q[1] = py[p];
+            s_q[2] = pz[p];
             if (blockIdx.x == 0) {
-                irec->k = 0;
                 irec->n = init_t;
                 irec->app = 1;
                 irec->init = 1;
                 irec->ran = 0;
-                irec->node_pos = s_pos;
-                irec->node_orig = s_orig;
-                irec->singular = 0;
+                irec->node_pos = p;
+                irec->node_orig = o;
                 irec->E = 0.0;
+                irec->x = px[p];
+                irec->y = py[p];
+                irec->z = pz[p];
+                irec->dx = pdx[p];
+                irec->dy = pdy[p];
+                irec->dz = pdz[p];
             }
         }
     } else {
-        // one snapshot of the state per block: block 0 updates it below, and
-        // every thread of a block must take the same branches
-        __shared__ GState s_st;
-        if (threadIdx.x == 0) s_st = *st;
+        // block-wide best: xor tree per wave, then waves in order (a total order, so the result is unique)
+        double we2 = be2;
+        int32_t wor = bor;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double oe = __shfl_xor(we2, off, 64);
+            const int32_t oo = __shfl_xor(wor, off, 64);
+            if (better(oe, oo, we2, wor)) { we2 = oe; wor = oo; }
+        }
+        c = wave_isum(c);
+        if (lane == 0) {
+            s_we2[wave] = we2;
+            s_wor[wave] = wor;
+            s_cnt[wave] = c;
+        }
         __syncthreads();
-        const GState sg = s_st;
-        if (sg.done) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                irec->app = 0;
-                irec->ran = 0;
-            }
-            return;
-        }
-        const int n = sg.n;
-        const int g = (int)(sg.k % m);
-        const int T = goff[g + 1] - goff[g];
-        const int per_block = kWavesPerBlock * sweep_tw(T);
-        const int nrec = (T + per_block - 1) / per_block;
-        Best b{-1.0, 0x7fffffff, -1};
-        int32_t c = 0;
-        for (int i = threadIdx.x; i < nrec; i += kBigBlock) {
-            const ArgRec r = srec[i];
-            if (better(r.e2, r.orig, b.v, b.idx)) { b.v = r.e2; b.idx = r.orig; b.aux = r.pos; }
-            c += r.count;
-        }
-        b = big_block_best(b);
-        c = big_block_isum(c);
         if (threadIdx.x == 0) {
-            const Decision d = decide_local(sg, n, m, b.v, tol_abs, nc_max, cap);
+            int bw_ = 0;
+            int32_t total = s_cnt[0];
+            for (int w = 1; w < kBigBlock / 64; ++w) {
+                if (better(s_we2[w], s_wor[w], s_we2[bw_], s_wor[bw_])) bw_ = w;
+                total += s_cnt[w];
+            }
+            s_wri[0] = s_wor[bw_];
+            s_wri[1] = total;
+            s_we2[0] = s_we2[bw_];
+        }
+        __syncthreads();
+        // the thread holding the winning record publishes its fields (original indices are unique)
+        if (be2 >= 0.0 && bor == s_wri[0]) {
+            s_win[0] = bx; s_win[1] = by; s_win[2] = bz; s_win[3] = bdx; s_win[4] = bdy; s_win[5] = bdz;
+            s_winpos = bpos;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const int32_t total = s_wri[1];
+            ArgRec b;
+            b.e2 = s_we2[0];
+            b.orig = s_wri[0];
+            if (b.e2 >= 0.0) {
+                b.pos = s_winpos;
+                b.x = s_win[0]; b.y = s_win[1]; b.z = s_win[2];
+                b.dx = s_win[3]; b.dy = s_win[4]; b.dz = s_win[5];
+            } else {
+                b.pos = -1;
+                b.x = b.y = b.z = b.dx = b.dy = b.dz = 0.0;
+            }
+            const Decision d = decide_local(sg, n, m, b.e2, tol_abs, nc_max, cap);
             s_app = d.app;
-            s_pos = b.aux;
-            s_orig = b.idx;
             s_n = n;
+            s_q[0] = b.x;
+            s_q[1] = b.y;
+            s_q[2] = b.z;
             if (blockIdx.x == 0) {
                 if (d.done != 4) {
                     const int64_t it = sg.log_len;
                     if (it < log_cap) {
                         log_group[it] = g;
-                        log_node[it] = b.v >= 0.0 ? b.idx : -1;
+                        log_node[it] = b.e2 >= 0.0 ? b.orig : -1;
                         log_err[it] = d.E;
                         log_app[it] = (int8_t)d.app;
                     }
                     st->log_len = it + 1;
-                    st->pairs_group = sg.pairs_group + (uint64_t)c * (uint64_t)n;
+                    st->pairs_group = sg.pairs_group + (uint64_t)total * (uint64_t)n;
                 }
                 st->quiet = d.quiet;
                 st->done = d.done;
-                irec->k = sg.k;
                 irec->n = n;
                 irec->app = d.app;
                 irec->init = 0;
                 irec->ran = d.done != 4;
-                irec->node_pos = d.app ? b.aux : -1;
-                irec->node_orig = d.app ? b.idx : -1;
-                irec->singular = 0;
+                irec->node_pos = d.app ? b.pos : -1;
+                irec->node_orig = d.app ? b.orig : -1;
                 irec->E = d.E;
+                irec->x = b.x;
+                irec->y = b.y;
+                irec->z = b.z;
+                irec->dx = b.dx;
+                irec->dy = b.dy;
+                irec->dz = b.dz;
             }
         }
     }
     __syncthreads();
     if (!s_app) return;
-    const int n = s_n;
-    const int p = s_pos;
     const int nblk = max(1, (n + kRowsL - 1) / kRowsL);
     if ((int)blockIdx.x >= nblk) return;
-    const int i0 = blockIdx.x * kRowsL;
     const int i1 = min(n, i0 + kRowsL);
-    const int i = i0 + wave;
-    const double qx = px[p], qy = py[p], qz = pz[p];
+    const double qx = s_q[0], qy = s_q[1], qz = s_q[2];
     double acc = 0.0;
     for (int w0 = 0; w0 < i1; w0 += kBWindow) {
         const int w1 = min(i1, w0 + kBWindow);
         __syncthreads();
-        for (int j = w0 + threadIdx.x; j < w1; j += kBigBlock)
-            bw[j - w0] = wendland_r2(dist2(qx, qy, qz, sv.sx[j], sv.sy[j], sv.sz[j]));
+        if (w0 == 0) {
+#pragma unroll
+            for (int u = 0; u < kBPre; ++u) {
+                const int j = threadIdx.x + kBigBlock * u;
+                if (j < w1) bw[j] = wendland_r2(dist2(qx, qy, qz, pbx[u], pby[u], pbz[u]));
+            }
+            for (int j = threadIdx.x + kBigBlock * kBPre; j < w1; j += kBigBlock)
+                bw[j] = wendland_r2(dist2(qx, qy, qz, sv.sx[j], sv.sy[j], sv.sz[j]));
+        } else {
+            for (int j = w0 + threadIdx.x; j < w1; j += kBigBlock)
+                bw[j - w0] = wendland_r2(dist2(qx, qy, qz, sv.sx[j], sv.sy[j], sv.sz[j]));
+        }
         __syncthreads();
         if (i < i1) {
-            const double* Mi = Mr + (size_t)i * (i + 1) / 2;
             const int je = min(w1, i + 1);
-            double a1 = 0.0, a2 = 0.0, a3 = 0.0;
             int j = w0 + lane;
-            for (; j + 192 < je; j += 256) {
-                const double m0 = Mi[j], m1 = Mi[j + 64], m2 = Mi[j + 128], m3 = Mi[j + 192];
+            if (w0 == 0) {
+#pragma unroll
+                for (int u = 0; u < kRowPre; ++u)
+                    if (lane + 64 * u < je) acc = fma(mrow[u], bw[lane + 64 * u], acc);
+                j = lane + 64 * kRowPre;
+            }
+            double a1 = 0.0;
+            for (; j + 64 < je; j += 128) {
+                const double m0 = Mi[j], m1 = Mi[j + 64];
                 acc = fma(m0, bw[j - w0], acc);
                 a1 = fma(m1, bw[j + 64 - w0], a1);
-                a2 = fma(m2, bw[j + 128 - w0], a2);
-                a3 = fma(m3, bw[j + 192 - w0], a3);
             }
-            for (; j < je; j += 64) acc = fma(Mi[j], bw[j - w0], acc);
-            acc = (acc + a1) + (a2 + a3);
+            if (j < je) acc = fma(Mi[j], bw[j - w0], acc);
+            acc += a1;
         }
     }
     const double li = wave_sum(acc);
@@ -442,10 +633,10 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_l(
         double fx = 0.0, fy = 0.0, fz = 0.0, ll = 0.0;
         const int j = i0 + lane;
         if (lane < kRowsL && j < i1) {
-            const double bj = wendland_r2(dist2(qx, qy, qz, sv.sx[j], sv.sy[j], sv.sz[j]));
-            fx = bj * sv.wx[j];
-            fy = bj * sv.wy[j];
-            fz = bj * sv.wz[j];
+            const double bj = wendland_r2(dist2(qx, qy, qz, wsx, wsy, wsz));
+            fx = bj * wwx;
+            fy = bj * wwy;
+            fz = bj * wwz;
             ll = sl[lane] * sl[lane];
         }
         fx = wave_sum(fx);
@@ -466,36 +657,54 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_l(
 // sums the k_factor_l partials in block order to s = 1 - l.l and
 // e = d_new - b.W.  Writes the new row [-u^T/sqrt(s), 1/sqrt(s)] into both
 // copies of M and W <- [W - u e/s; e/s]; block 0 commits the iteration.
-__global__ __launch_bounds__(kBigBlock) void k_factor_u(
-    GState* __restrict__ st, IterRec* __restrict__ irec, const double* __restrict__ px, const double* __restrict__ py,
-    const double* __restrict__ pz, const double* __restrict__ pdx, const double* __restrict__ pdy,
-    const double* __restrict__ pdz, const int32_t* __restrict__ perm, uint8_t* __restrict__ inS, SupportMut sm,
-    double* __restrict__ Mc, int64_t cap, const double* __restrict__ l, const double* __restrict__ Pb) {
+__global__ __launch_bounds__(kBigBlock) void k_factor_u(GState* __restrict__ st, const IterRec* __restrict__ irec,
+                                                        uint8_t* __restrict__ inS, SupportMut sm,
+                                                        double* __restrict__ Mc, int64_t cap,
+                                                        const double* __restrict__ l, const double* __restrict__ Pb) {
     __shared__ double part[4][kBigBlock / 64];
-    __shared__ double sh[5];
+    __shared__ double sh[4];
     __shared__ int32_t s_bad;
-    // the iteration record is only read here (k_factor_l wrote it), so every
-    // block sees the same values
+    // the iteration record is only read here (k_factor_l wrote it), so every block sees the same values
     const IterRec r = *irec;
-    if (!r.app) {
-        if (blockIdx.x == 0 && threadIdx.x == 0 && r.ran) st->k = r.k + 1;
-        return;
+    // this thread's share of the k_factor_l partials, loaded with the record (masked once n is known)
+    double pv[4] = {0.0, 0.0, 0.0, 0.0};
+    const int nbl_cap = (int)((cap + kRowsL - 1) / kRowsL);
+    if ((int)threadIdx.x < nbl_cap) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pv[c] = Pb[4 * threadIdx.x + c];
     }
+    if (!r.app) return;
     const int n = r.n;
-    const int p = r.node_pos;
-    const int nbl = max(1, (n + kRowsL - 1) / kRowsL);
     const int ncb = max(1, (n + kRowsL - 1) / kRowsL);
     if ((int)blockIdx.x >= ncb) return;
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * kRowsL + wave;
+    // column j of M and the matching entries of l, loaded before s is known
+    constexpr int kColPre = 16;
+    double mc[kColPre], lv[kColPre];
+    const double* col = Mc + (size_t)j * cap - (size_t)j * (j - 1) / 2;   // rows j.. of column j
+#pragma unroll
+    for (int u = 0; u < kColPre; ++u) {
+        const int ii = j + lane + 64 * u;
+        const bool ok = j < n && ii < n;
+        mc[u] = ok ? col[ii - j] : 0.0;
+        lv[u] = ok ? l[ii] : 0.0;
+    }
     {
         // fixed-order reduction: per thread in block order, xor tree per wave, waves in order
         double v[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int b = threadIdx.x; b < nbl; b += kBigBlock)
+        if ((int)threadIdx.x < ncb) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] = pv[c];
+        }
+        for (int b = threadIdx.x + kBigBlock; b < ncb; b += kBigBlock)
 #pragma unroll
             for (int c = 0; c < 4; ++c) v[c] += Pb[4 * b + c];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             v[c] = wave_sum(v[c]);
-            if ((threadIdx.x & 63) == 0) part[c][threadIdx.x >> 6] = v[c];
+            if (lane == 0) part[c][wave] = v[c];
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -506,9 +715,9 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_u(
             const double s = 1.0 - f[3];
             s_bad = !(s > kSingularTol);
             sh[0] = 1.0 / sqrt(s);
-            sh[1] = (pdx[p] - f[0]) / s;
-            sh[2] = (pdy[p] - f[1]) / s;
-            sh[3] = (pdz[p] - f[2]) / s;
+            sh[1] = (r.dx - f[0]) / s;
+            sh[2] = (r.dy - f[1]) / s;
+            sh[3] = (r.dz - f[2]) / s;
         }
         __syncthreads();
     }
@@ -520,18 +729,16 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_u(
         return;
     }
     const double rs = sh[0], cx = sh[1], cy = sh[2], cz = sh[3];
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int j = blockIdx.x * kRowsL + wave;
     if (j < n) {
-        const double* col = Mc + (size_t)j * cap - (size_t)j * (j - 1) / 2;   // rows j.. of column j
         double a0 = 0.0, a1 = 0.0;
-        int i = j + lane;
-        for (; i + 64 < n; i += 128) {
-            a0 = fma(col[i - j], l[i], a0);
-            a1 = fma(col[i + 64 - j], l[i + 64], a1);
+#pragma unroll
+        for (int u = 0; u < kColPre; ++u) a0 = fma(mc[u], lv[u], a0);
+        int ii = j + lane + 64 * kColPre;
+        for (; ii + 64 < n; ii += 128) {
+            a0 = fma(col[ii - j], l[ii], a0);
+            a1 = fma(col[ii + 64 - j], l[ii + 64], a1);
         }
-        if (i < n) a0 = fma(col[i - j], l[i], a0);
+        if (ii < n) a0 = fma(col[ii - j], l[ii], a0);
         const double u = wave_sum(a0 + a1);
         if (lane == 0) {
             const double v = -u * rs;
@@ -543,23 +750,20 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_u(
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int p = r.node_pos;
         sm.M[(size_t)n * (n + 1) / 2 + n] = rs;
         Mc[(size_t)n * cap - (size_t)n * (n - 1) / 2] = rs;
         sm.wx[n] = cx;
         sm.wy[n] = cy;
         sm.wz[n] = cz;
-        sm.sx[n] = px[p];
-        sm.sy[n] = py[p];
-        sm.sz[n] = pz[p];
-        sm.orig[n] = perm[p];
+        sm.sx[n] = r.x;
+        sm.sy[n] = r.y;
+        sm.sz[n] = r.z;
+        sm.orig[n] = r.node_orig;
         inS[p] = 1;
         st->n = n + 1;
-        if (r.init) {
-            st->init_left -= 1;   // starting nodes are not loop appends
-        } else {
-            st->pairs_append += (uint64_t)n;
-            st->k = r.k + 1;
-        }
+        if (r.init) st->init_left -= 1;   // starting nodes are not loop appends
+        else st->pairs_append += (uint64_t)n;
     }
 }
 
@@ -737,36 +941,39 @@ void launch_init_nodes(hipStream_t s, const Boundary& bd, int32_t* init, ArgRec*
     }
 }
 
-static void launch_factor(hipStream_t s, const IterCtx& ic, int n_ub, int init_t) {
+static void launch_factor(hipStream_t s, const IterCtx& ic, int grid, int init_t, int g, int nrec) {
     const Boundary& bd = *ic.bd;
     Support& sp = *ic.sp;
-    const unsigned g = (unsigned)std::max(1, (n_ub + kRowsL - 1) / kRowsL);
-    GCB_LAUNCH(k_factor_l, dim3(g), dim3(kBigBlock), s, ic.st, ic.irec, ic.srec, bd.m, bd.goff, init_t, ic.init,
-               bd.pos_of, bd.px, bd.py, bd.pz, view(sp), sp.M, sp.l, ic.Pb, ic.tol_abs, ic.nc_max, sp.cap,
-               ic.log_group, ic.log_node, ic.log_err, ic.log_app, ic.log_cap);
-    GCB_LAUNCH(k_factor_u, dim3(g), dim3(kBigBlock), s, ic.st, ic.irec, bd.px, bd.py, bd.pz, bd.pdx, bd.pdy, bd.pdz,
-               bd.perm, bd.inS, mut(sp), sp.Mc, sp.cap, sp.l, ic.Pb);
+    GCB_LAUNCH(k_factor_l, dim3(grid), dim3(kBigBlock), s, ic.st, ic.irec, ic.srec, nrec, bd.m, g, init_t, ic.init,
+               bd.pos_of, bd.px, bd.py, bd.pz, bd.pdx, bd.pdy, bd.pdz, view(sp), sp.M, sp.l, ic.Pb, ic.tol_abs,
+               ic.nc_max, sp.cap, ic.log_group, ic.log_node, ic.log_err, ic.log_app, ic.log_cap);
+    GCB_LAUNCH(k_factor_u, dim3(grid), dim3(kBigBlock), s, ic.st, ic.irec, bd.inS, mut(sp), sp.Mc, sp.cap, sp.l, ic.Pb);
 }
 
-void launch_init_append(hipStream_t s, const IterCtx& ic, int t) { launch_factor(s, ic, t, t); }
+void launch_init_append(hipStream_t s, const IterCtx& ic, int t) { launch_factor(s, ic, 1, t, 0, 0); }
 
-// Blocks of k_sweep that cover every group size T <= gmax (the targets per
-// wave, and so the targets per block, grow with T).
 int sweep_blocks(int gmax) {
     int best = 1;
-    for (int T : {std::min(gmax, 1023), std::min(gmax, 4095), gmax}) {
-        const int per_block = kWavesPerBlock * sweep_tw(T);
-        best = std::max(best, (T + per_block - 1) / per_block);
-    }
+    for (int T = 1; T <= gmax; T = (T < gmax && T * 2 > gmax) ? gmax : T * 2)
+        best = std::max(best, sweep_nblocks(T));
+    for (int T : {std::min(gmax, 512), std::min(gmax, 1024), std::min(gmax, 2048), std::min(gmax, 8192), gmax})
+        best = std::max(best, sweep_nblocks(T));
     return best;
 }
 
-void launch_iteration(hipStream_t s, const IterCtx& ic, int n_ub) {
+void launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub) {
     const Boundary& bd = *ic.bd;
-    const unsigned gs = (unsigned)sweep_blocks(bd.gmax);
-    GCB_LAUNCH(k_sweep, dim3(gs), dim3(kBlock), s, ic.st, bd.m, bd.goff, bd.px, bd.py, bd.pz, bd.pdx, bd.pdy, bd.pdz,
-               bd.inS, bd.perm, view(*ic.sp), ic.srec);
-    launch_factor(s, ic, n_ub, -1);
+    const int t0 = bd.goff_h[g];
+    const int T = bd.goff_h[g + 1] - t0;
+    const int nrec = sweep_nblocks(T);
+    if (T > 0) {
+        int lpt, tpl;
+        sweep_layout(T, lpt, tpl);
+        GCB_LAUNCH(k_sweep, dim3(nrec), dim3(kBlock), s, ic.st, t0, T, lpt, tpl, bd.px, bd.py, bd.pz, bd.pdx, bd.pdy, bd.pdz,
+                   bd.inS, bd.perm, view(*ic.sp), ic.sp->cap, ic.srec);
+    }
+    const int grid = std::max(1, (n_ub + kRowsL - 1) / kRowsL);
+    launch_factor(s, ic, grid, -1, g, T > 0 ? nrec : 0);
 }
 
 void launch_transpose_factor(hipStream_t s, const double* Mr, double* Mc, int n, int64_t cap) {

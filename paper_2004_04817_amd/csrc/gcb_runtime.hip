@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <new>
 
 #include "gcb_internal.h"
@@ -46,6 +47,7 @@ void dalloc(gcb_ctx* ctx, T*& p, size_t count) {
         throw Fail{GCB_E_NOMEM};
     }
     p = static_cast<T*>(q);
+    ctx->alloc_gen++;   // captured graphs bake in buffer addresses
 }
 
 template <typename T>
@@ -105,6 +107,8 @@ void free_boundary(Boundary& bd) {
     dfree(bd.xyz0); dfree(bd.disp0);
     bd.nb = 0;
     bd.m = 0;
+    bd.alloc_nb = 0;
+    bd.alloc_m = 0;
 }
 
 // (Re)allocate the support arrays for capacity `cap`, keeping the first n
@@ -207,10 +211,16 @@ void stage_boundary(gcb_ctx* ctx) {
     bd.inv_r = 1.0 / p.radius;
     bd.gmax = gmax;
     bd.goff_h = goff;
-    dalloc(ctx, bd.px, nb); dalloc(ctx, bd.py, nb); dalloc(ctx, bd.pz, nb);
-    dalloc(ctx, bd.pdx, nb); dalloc(ctx, bd.pdy, nb); dalloc(ctx, bd.pdz, nb);
-    dalloc(ctx, bd.perm, nb); dalloc(ctx, bd.pos_of, nb); dalloc(ctx, bd.inS, nb);
-    dalloc(ctx, bd.goff, (size_t)p.m + 1);
+    if (bd.alloc_nb != nb) {   // keep the buffers (and any captured graph) when the size is unchanged
+        dalloc(ctx, bd.px, nb); dalloc(ctx, bd.py, nb); dalloc(ctx, bd.pz, nb);
+        dalloc(ctx, bd.pdx, nb); dalloc(ctx, bd.pdy, nb); dalloc(ctx, bd.pdz, nb);
+        dalloc(ctx, bd.perm, nb); dalloc(ctx, bd.pos_of, nb); dalloc(ctx, bd.inS, nb);
+        bd.alloc_nb = nb;
+    }
+    if (bd.alloc_m < p.m) {
+        dalloc(ctx, bd.goff, (size_t)p.m + 1);
+        bd.alloc_m = p.m;
+    }
     HIPCHK(ctx, hipMemcpyAsync(bd.perm, perm.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(bd.goff, goff.data(), sizeof(int32_t) * (p.m + 1), hipMemcpyHostToDevice, ctx->stream));
     launch_stage(ctx->stream, nb, bd.xyz0, bd.disp0, bd.perm, bd.inv_r, bd);
@@ -285,28 +295,56 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
         for (int t = 0; t < 3; ++t) launch_init_append(ctx->stream, ic, t);
     }
     HIPCHK(ctx, hipGetLastError());
-    const int chunk = 64;
+    if (!ctx->state_pin) HIPCHK(ctx, hipHostMalloc(reinterpret_cast<void**>(&ctx->state_pin), sizeof(GState)));
+    // Every iteration advances k by one, so the host knows the group of each
+    // launch.  A chunk of C iterations with C a multiple of m starts at the
+    // same phase of k mod m every time and is captured once into a graph.
+    const int m = p.m;
+    const bool use_graph = g_tuning.use_graph && m <= 256;
+    const int chunk = use_graph ? m * ((64 + m - 1) / m) : 64;
+    int64_t k = 3;
     for (;;) {
-        HIPCHK(ctx, hipMemcpyAsync(&ctx->state_h, ctx->state, sizeof(GState), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->state_pin, ctx->state, sizeof(GState), hipMemcpyDeviceToHost, ctx->stream));
         sync(ctx);
+        ctx->state_h = *ctx->state_pin;
         GState& h = ctx->state_h;
-        if (h.done == 4) {
-            h.done = 0;
-            HIPCHK(ctx, hipMemcpyAsync(ctx->state, &h, sizeof(GState), hipMemcpyHostToDevice, ctx->stream));
-        } else if (h.done != 0) {
-            break;
-        }
+        if (h.done == 4) fail(ctx, GCB_E_DEVICE, "internal error: factor capacity exhausted inside a chunk");
+        if (h.done != 0) break;
         if (h.n + chunk > ctx->sp.cap && ctx->sp.cap < p.nc_max) {
             const int64_t cap = std::min<int64_t>(p.nc_max, std::max<int64_t>(2 * ctx->sp.cap, h.n + chunk + 1));
             grow_support(ctx, cap, h.n);
         }
         if (h.log_len + chunk > ctx->log_cap) grow_log(ctx, h.log_len, std::max<int64_t>(2 * ctx->log_cap, h.log_len + chunk));
         IterCtx ic = make_ic();
-        for (int it = 0; it < chunk; ++it) {
-            const int n_ub = (int)n_upper(ctx, h.n, it + 1);
-            launch_iteration(ctx->stream, ic, n_ub);
+        if (use_graph) {
+            int64_t tol_bits;
+            std::memcpy(&tol_bits, &p.tol_abs, sizeof(tol_bits));
+            // everything the captured launches baked in: phase, capacities, buffers, parameters
+            const std::vector<int64_t> full = {k % m, m, chunk, ctx->sp.cap, ctx->log_cap, p.nc_max, tol_bits,
+                                               (int64_t)ctx->alloc_gen, (int64_t)(intptr_t)ctx->stream};
+            if (!ctx->chunk_exec || ctx->chunk_key != full) {
+                if (ctx->chunk_exec) (void)hipGraphExecDestroy(ctx->chunk_exec);
+                ctx->chunk_exec = nullptr;
+                if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+                hipGraph_t graph;
+                HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+                const int n_ub = (int)std::min<int64_t>(p.nc_max, ctx->sp.cap);
+                for (int it = 0; it < chunk; ++it) launch_iteration(ctx->cap_stream, ic, (int)((k + it) % m), n_ub);
+                HIPCHK(ctx, hipStreamEndCapture(ctx->cap_stream, &graph));
+                hipError_t e = hipGraphInstantiate(&ctx->chunk_exec, graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                HIPCHK(ctx, e);
+                ctx->chunk_key = full;
+            }
+            HIPCHK(ctx, hipGraphLaunch(ctx->chunk_exec, ctx->stream));
+        } else {
+            for (int it = 0; it < chunk; ++it) {
+                const int n_ub = (int)n_upper(ctx, h.n, it + 1);
+                launch_iteration(ctx->stream, ic, (int)((k + it) % m), n_ub);
+            }
         }
         HIPCHK(ctx, hipGetLastError());
+        k += chunk;
     }
     HIPCHK(ctx, hipEventRecord(ev1, ctx->stream));
     HIPCHK(ctx, hipEventSynchronize(ev1));
@@ -380,6 +418,11 @@ int gcb_partition(int64_t nb, int32_t m, uint64_t seed, int32_t* group_of) {
 
 int gcb_create(gcb_ctx** out, int device, void* hip_stream) {
     if (!out) return GCB_E_INVALID;
+    if (const char* e = std::getenv("GCB_SWEEP_LPT")) {
+        const int v = std::atoi(e);
+        if (v == 64 || v == 128 || v == 256) g_tuning.sweep_lpt_max = v;
+    }
+    if (const char* e = std::getenv("GCB_GRAPH")) g_tuning.use_graph = std::atoi(e) != 0;
     *out = nullptr;
     gcb_ctx* ctx = new (std::nothrow) gcb_ctx();
     if (!ctx) return GCB_E_NOMEM;
@@ -413,6 +456,9 @@ void gcb_destroy(gcb_ctx* ctx) {
     dfree(ctx->state); dfree(ctx->argrec); dfree(ctx->red); dfree(ctx->irec); dfree(ctx->Pb);
     dfree(ctx->log_group); dfree(ctx->log_node); dfree(ctx->log_err); dfree(ctx->log_app);
     if (ctx->tmp) (void)hipFree(ctx->tmp);
+    if (ctx->chunk_exec) (void)hipGraphExecDestroy(ctx->chunk_exec);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->state_pin) (void)hipHostFree(ctx->state_pin);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
     delete ctx;
 }
