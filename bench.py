@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-volume", type=int, default=3_000_000,
                     help="volume points in the oracle's timed sample")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before timing, one device-to-device copy of this many MiB (the known-size "
+                         "kernel that scales FETCH_SIZE / WRITE_SIZE counter readings)")
     return ap.parse_args()
 
 
@@ -85,6 +88,13 @@ def main():
     ctx.set_boundary(xyz, disp)
     ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
     stream = torch.cuda.current_stream(dev)
+    if a.calib_copy_mb > 0:
+        src = torch.empty(a.calib_copy_mb << 17, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         info = ctx.select()

@@ -227,7 +227,9 @@ __device__ __forceinline__ Decision decide_local(const GState& st, int n, int32_
 
 __device__ __forceinline__ bool better_rec(const ArgRec& a, const ArgRec& b) { return better(a.e2, a.orig, b.e2, b.orig); }
 
-constexpr int kPre = 4;   // supports per lane loaded before |S| is known
+
+// Supports staged in LDS per window: all loads of a window are issued at once.
+constexpr int kStage = 1280;
 
 __global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st, int t0, int T, int lpt, int tpl,
                                                   const double* __restrict__ px, const double* __restrict__ py,
@@ -235,8 +237,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st,
                                                   const double* __restrict__ pdy, const double* __restrict__ pdz,
                                                   const uint8_t* __restrict__ inS, const int32_t* __restrict__ perm,
                                                   SupportView sv, int64_t cap, ArgRec* __restrict__ rec) {
+    __shared__ double ls[6][kStage];
     __shared__ double red[3][4][kBlock / 64];
-    __shared__ int32_t s_n, s_done;
+    __shared__ double s_e2[kBlock / 64 * 4];
+    __shared__ int32_t s_or[kBlock / 64 * 4], s_cnt[kBlock / 64 * 4];
+    __shared__ int32_t s_win, s_tot, s_n, s_done;
     const int groups = kBlock / lpt;                // target groups per block
     const int grp = threadIdx.x / lpt;
     const int gl = threadIdx.x % lpt;               // lane within the group
@@ -245,7 +250,8 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st,
         s_n = st->n;
         s_done = st->done;
     }
-    // the group's targets and the first supports, loaded while |S| is in flight
+    // everything below is independent of |S| and is loaded in one round with the state:
+    // the group's targets, what the candidate threads need, and the first window of supports
     double tx[4], ty[4], tz[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -254,74 +260,80 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st,
         ty[q] = py[t0 + t];
         tz[q] = pz[t0 + t];
     }
-    // what the candidate threads (one per (group, q)) need at the end
     const int ncand = groups * 4;
-    double cdx = 0.0, cdy = 0.0, cdz = 0.0;
+    double cdx = 0.0, cdy = 0.0, cdz = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
     int32_t corig = 0x7fffffff;
     bool clive = false;
     int ct = 0;
     if ((int)threadIdx.x < ncand) {
         const int gq = threadIdx.x / 4, q = threadIdx.x % 4;
         ct = (blockIdx.x * groups + gq) * tpl + q;
-        clive = q < tpl && ct < T;
         const int tc = min(ct, T - 1);
-        clive = clive && !inS[t0 + tc];
+        clive = q < tpl && ct < T && !inS[t0 + tc];
         cdx = pdx[t0 + tc];
         cdy = pdy[t0 + tc];
         cdz = pdz[t0 + tc];
+        cx = px[t0 + tc];
+        cy = py[t0 + tc];
+        cz = pz[t0 + tc];
         corig = perm[t0 + tc];
     }
-    double sx[kPre], sy[kPre], sz[kPre], wx[kPre], wy[kPre], wz[kPre];
-#pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-        const int j = min(gl + lpt * u, (int)cap - 1);
-        sx[u] = sv.sx[j];
-        sy[u] = sv.sy[j];
-        sz[u] = sv.sz[j];
-        wx[u] = sv.wx[j];
-        wy[u] = sv.wy[j];
-        wz[u] = sv.wz[j];
+    const int w0end = (int)min((int64_t)kStage, cap);
+    for (int j = threadIdx.x; j < w0end; j += kBlock) {
+        ls[0][j] = sv.sx[j];
+        ls[1][j] = sv.sy[j];
+        ls[2][j] = sv.sz[j];
+        ls[3][j] = sv.wx[j];
+        ls[4][j] = sv.wy[j];
+        ls[5][j] = sv.wz[j];
     }
     __syncthreads();
     if (s_done) return;
     const int n = s_n;
     double ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0}, az[4] = {0, 0, 0, 0};
+    for (int w0 = 0; w0 < n; w0 += kStage) {
+        const int w1 = min(n, w0 + kStage);
+        if (w0 > 0) {
+            __syncthreads();
+            for (int j = w0 + threadIdx.x; j < w1; j += kBlock) {
+                ls[0][j - w0] = sv.sx[j];
+                ls[1][j - w0] = sv.sy[j];
+                ls[2][j - w0] = sv.sz[j];
+                ls[3][j - w0] = sv.wx[j];
+                ls[4][j - w0] = sv.wy[j];
+                ls[5][j - w0] = sv.wz[j];
+            }
+            __syncthreads();
+        }
+        // four supports per step: independent dependency chains keep a lone wave busy
+        int j = w0 + gl;
+        if (tpl == 1) {
+            double bx[4] = {0, 0, 0, 0}, by[4] = {0, 0, 0, 0}, bz[4] = {0, 0, 0, 0};
+            for (; j + 3 * lpt < w1; j += 4 * lpt) {
 #pragma unroll
-    for (int u = 0; u < kPre; ++u) {
-        if (gl + lpt * u < n) {
+                for (int u = 0; u < 4; ++u) {
+                    const int jj = j + u * lpt - w0;
+                    const double phi = wendland_r2(dist2(tx[0], ty[0], tz[0], ls[0][jj], ls[1][jj], ls[2][jj]));
+                    bx[u] = fma(ls[3][jj], phi, bx[u]);
+                    by[u] = fma(ls[4][jj], phi, by[u]);
+                    bz[u] = fma(ls[5][jj], phi, bz[u]);
+                }
+            }
+            ax[0] += (bx[0] + bx[1]) + (bx[2] + bx[3]);
+            ay[0] += (by[0] + by[1]) + (by[2] + by[3]);
+            az[0] += (bz[0] + bz[1]) + (bz[2] + bz[3]);
+        }
+        for (; j < w1; j += lpt) {
+            const int jj = j - w0;
+            const double sx = ls[0][jj], sy = ls[1][jj], sz = ls[2][jj];
+            const double wx = ls[3][jj], wy = ls[4][jj], wz = ls[5][jj];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if (q < tpl) {
-                    const double phi = wendland_r2(dist2(tx[q], ty[q], tz[q], sx[u], sy[u], sz[u]));
-                    ax[q] = fma(wx[u], phi, ax[q]);
-                    ay[q] = fma(wy[u], phi, ay[q]);
-                    az[q] = fma(wz[u], phi, az[q]);
-                }
-            }
-        }
-    }
-    for (int j0 = gl + lpt * kPre; j0 < n; j0 += lpt * kPre) {
-#pragma unroll
-        for (int u = 0; u < kPre; ++u) {
-            const int j = min(j0 + lpt * u, (int)cap - 1);
-            sx[u] = sv.sx[j];
-            sy[u] = sv.sy[j];
-            sz[u] = sv.sz[j];
-            wx[u] = sv.wx[j];
-            wy[u] = sv.wy[j];
-            wz[u] = sv.wz[j];
-        }
-#pragma unroll
-        for (int u = 0; u < kPre; ++u) {
-            if (j0 + lpt * u < n) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (q < tpl) {
-                        const double phi = wendland_r2(dist2(tx[q], ty[q], tz[q], sx[u], sy[u], sz[u]));
-                        ax[q] = fma(wx[u], phi, ax[q]);
-                        ay[q] = fma(wy[u], phi, ay[q]);
-                        az[q] = fma(wz[u], phi, az[q]);
-                    }
+                    const double phi = wendland_r2(dist2(tx[q], ty[q], tz[q], sx, sy, sz));
+                    ax[q] = fma(wx, phi, ax[q]);
+                    ay[q] = fma(wy, phi, ay[q]);
+                    az[q] = fma(wz, phi, az[q]);
                 }
             }
         }
@@ -345,9 +357,6 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st,
     __syncthreads();
     // one thread per (group, q): error of target tbase + q; the best is chosen on
     // (e^2, original index) only, then its owner writes the full record
-    __shared__ double s_e2[kBlock / 64 * 4];
-    __shared__ int32_t s_or[kBlock / 64 * 4], s_cnt[kBlock / 64 * 4];
-    __shared__ int32_t s_win, s_tot;
     double e2 = -1.0;
     if ((int)threadIdx.x < ncand) {
         const int gq = threadIdx.x / 4, q = threadIdx.x % 4;
@@ -383,12 +392,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st,
         o.orig = clive ? corig : 0x7fffffff;
         o.pos = t0 + ct;
         o.count = s_tot;
-        // the winner is one of the block's targets: its coordinates are in registers of some lane;
-        // re-read them here (one thread, off the critical path of the other blocks)
-        const int tc = min(ct, T - 1);
-        o.x = px[t0 + tc];
-        o.y = py[t0 + tc];
-        o.z = pz[t0 + tc];
+        o.x = cx;
+        o.y = cy;
+        o.z = cz;
         o.dx = cdx;
         o.dy = cdy;
         o.dz = cdz;
