@@ -43,6 +43,23 @@ def parse():
     return ap.parse_args()
 
 
+def measured_traffic(kernel_src: str) -> float | None:
+    """Per-launch HBM bytes of the volume sweep from the committed rocprofv3 summary,
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "volume_wing80k_traffic.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    vals = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:",
+                                                                           "kernel_source_sha256_prefix:")))
+    cur = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    if vals.get("kernel_source_sha256_prefix", "").strip() != cur:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def problem(name):
     import synth
     if name == "small":
@@ -151,7 +168,10 @@ def main():
                      "converged": bool(info["converged"])},
         "roofline": {"kernel": "k_volume64<double,double>", "bound": "alu", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": None, "flops_per_pair": FLOPS_PER_PAIR},
+                     "traffic": (measured_traffic(os.path.join(ROOT, "paper_2004_04817_amd", "csrc",
+                                                               "gcb_kernels.hip")) if a.config == "wing" else None),
+                     "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs_volume,
+                     "launch_ms": vol_avg_ms},
     }
     if not a.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(p, min(a.cpu_sample_volume, nv))
