@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-volume", type=int, default=3_000_000,
                     help="volume points in the oracle's timed sample")
+    ap.add_argument("--modes", type=int, default=64,
+                    help="also time Eq. 6 for this many deformation modes on the wing supports (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, one device-to-device copy of this many MiB (the known-size "
                          "kernel that scales FETCH_SIZE / WRITE_SIZE counter readings)")
@@ -173,6 +175,29 @@ def main():
                      "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs_volume,
                      "launch_ms": vol_avg_ms},
     }
+    if a.modes > 0 and a.config == "wing":
+        import synth
+        modes = torch.from_numpy(synth.config_modes(p, a.modes)).to(dev)
+        mout = torch.empty((nv, 3 * a.modes), dtype=torch.float64, device=dev)
+        ctx.deform_multi(modes, vol, out=mout)   # warm-up
+        ts = []
+        for _ in range(2):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.deform_multi(modes, vol, out=mout)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.mean(ts))
+        rhs = 3 * a.modes
+        flops = (2.0 * rhs + 15.0) * nv * nc   # matrix-core FMAs + the phi evaluation per pair
+        rec["modes"] = {"k_modes": a.modes, "rhs": rhs, "nv": nv, "nc": nc, "ms": ms,
+                        "pair_evals_per_s": nv * nc / (ms * 1e-3),
+                        "roofline": {"kernel": "k_volume_multi<double,double> (+ weight TRMMs)", "bound": "mfma",
+                                     "achieved": flops / (ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+                                     "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}}
+        del mout, modes
     if not a.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(p, min(a.cpu_sample_volume, nv))
     print(json.dumps(rec), flush=True)

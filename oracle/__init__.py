@@ -59,6 +59,9 @@ def load(path: str):
     L.orc_rc_factor.argtypes = [C.c_void_p, C.c_void_p]
     L.orc_select.restype = C.c_int
     L.orc_select.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_void_p, C.POINTER(_Log), C.POINTER(_Info)]
+    L.orc_solve_on_support.restype = C.c_int
+    L.orc_solve_on_support.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int32,
+                                       C.c_void_p, C.c_void_p]
     L.orc_validate.restype = C.c_int64
     L.orc_validate.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
@@ -250,6 +253,21 @@ def validate(xyz, disp, radius, m, tol_abs, S_init, group, node, appended, tau, 
                              float(tau), C.byref(reason), C.byref(gap))
     del keep
     return int(bad), int(reason.value), float(gap.value)
+
+
+def solve_on_support(xyz, S, radius, D) -> np.ndarray:
+    """Weights (n, K) of the K columns of D (nb, K) on support set S (in order)."""
+    xyz = _f64(xyz)
+    S = np.ascontiguousarray(S, dtype=np.int64)
+    D = _f64(D)
+    if D.ndim == 1:
+        D = D[:, None]
+    K = D.shape[1]
+    W = np.empty((max(len(S), 1), K))
+    st = lib().orc_solve_on_support(xyz.shape[0], _ptr(xyz), _ptr(S), len(S), float(radius), K, _ptr(D), _ptr(W))
+    if st != ORC_OK:
+        raise RuntimeError(f"orc_solve_on_support: status {st}")
+    return W[: len(S)]
 
 
 def cost_model(nc: float, nb: float, nv: float, m: float = 1.0) -> dict:

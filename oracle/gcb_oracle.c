@@ -439,6 +439,23 @@ int orc_select(const orc_problem *p, int64_t *S_out, double *W_out, orc_log *log
     return status;
 }
 
+/* ------------------------------------------------------------------ several right-hand sides */
+int orc_solve_on_support(int64_t nb, const double *xyz, const int64_t *S, int64_t n, double radius, int32_t K,
+                         const double *D, double *W_out) {
+    (void)nb;
+    orc_rc *rc = orc_rc_create(K);
+    double *b = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    int status = ORC_OK;
+    for (int64_t t = 0; t < n && status == ORC_OK; ++t) {
+        for (int64_t s = 0; s < t; ++s) b[s] = orc_phi(dist3(xyz + 3 * S[s], xyz + 3 * S[t]) / radius);
+        status = orc_rc_append(rc, b, orc_phi(0.0), D + (size_t)S[t] * (size_t)K);
+    }
+    if (status == ORC_OK) orc_rc_weights(rc, W_out);
+    free(b);
+    orc_rc_destroy(rc);
+    return status;
+}
+
 /* ------------------------------------------------------------------ follow-mode replay */
 int64_t orc_validate(const orc_problem *p, const int64_t S_init[3], int64_t n_iter,
                      const int32_t *group, const int64_t *node, const int8_t *appended,

@@ -101,6 +101,14 @@ typedef struct {
  * gets the support nodes in selection order, W_out (nc_max,3) their weights. */
 int orc_select(const orc_problem *p, int64_t *S_out, double *W_out, orc_log *log, orc_info *info);
 
+/* Weights of K right-hand sides on a given support set (Eqs. 4-5 restricted
+ * to S): the RC factor is grown over S in the given order, then
+ * Phi_S W = D_S is solved by forward and back substitution.  D (nb,K) holds
+ * the displacements of every boundary node; W_out (n,K).  Returns ORC_OK or
+ * ORC_E_SINGULAR. */
+int orc_solve_on_support(int64_t nb, const double *xyz, const int64_t *S, int64_t n, double radius, int32_t K,
+                         const double *D, double *W_out);
+
 /* Replays a foreign selection (per iteration: group, node, appended) and
  * checks each step against FP64 errors computed here, following the foreign
  * choice afterwards: the group is k mod m; an appended node lies in G_i \ S,

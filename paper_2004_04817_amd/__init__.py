@@ -276,6 +276,40 @@ class Context:
         self._check(lib().gcb_deform(self._h, nv, px, in_dt, po, out_dt, mx))
         return out
 
+    def deform_multi(self, modes, xyz, out=None, out_dtype=None):
+        """K displacement fields of the boundary (nb, 3K) solved on the selected
+        supports and evaluated at xyz (nv, 3): returns (nv, 3K)."""
+        if _is_tensor(xyz):
+            import torch
+            in_dt = GCB_F64 if xyz.dtype == torch.float64 else GCB_F32
+            if not _is_tensor(modes) or not modes.is_cuda:
+                raise ValueError("with device points, modes must be a device tensor too")
+            rc = int(modes.shape[1])
+            if out is None:
+                odt = torch.float64 if out_dtype in (None, np.float64, torch.float64) else torch.float32
+                out = torch.empty((xyz.shape[0], rc), dtype=odt, device=xyz.device)
+            px, mx, kx = _arg(xyz, np.float64 if in_dt == GCB_F64 else np.float32)
+            pm, mm, km = _arg(modes, np.float64)
+            out_dt = GCB_F64 if out.dtype == torch.float64 else GCB_F32
+            po, mo, ko = _arg(out, np.float64 if out_dt == GCB_F64 else np.float32)
+        else:
+            a = np.ascontiguousarray(xyz)
+            in_dt = GCB_F32 if a.dtype == np.float32 else GCB_F64
+            px, mx, kx = _arg(a, np.float32 if in_dt == GCB_F32 else np.float64)
+            pm, mm, km = _arg(modes, np.float64)
+            rc = int(km.shape[1])
+            if out is None:
+                out = np.empty((a.shape[0], rc), dtype=np.float32 if out_dtype == np.float32 else np.float64)
+            out_dt = GCB_F32 if out.dtype == np.float32 else GCB_F64
+            po, mo, ko = out.ctypes.data, GCB_MEM_HOST, out
+        if rc % 3:
+            raise ValueError("modes must have 3K columns")
+        if not (mx == mo == mm):
+            raise ValueError("modes, xyz and out must live in the same memory")
+        self.use_current_stream(kx)
+        self._check(lib().gcb_deform_multi(self._h, rc // 3, pm, int(kx.shape[0]), px, in_dt, po, out_dt, mx))
+        return out
+
     def certify(self):
         mx, rms = C.c_double(), C.c_double()
         self._check(lib().gcb_certify(self._h, C.byref(mx), C.byref(rms)))

@@ -1,0 +1,39 @@
+// Device helpers shared by the HIP kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace gcb {
+
+// ---------------------------------------------------------------- Eq. (2)
+// Wendland C2 from the squared scaled distance r2 = (|r - r_i| / R)^2:
+// eta = sqrt(r2) by one Newton step on the hardware reciprocal square root
+// and one on the square root itself; t = clamp(1 - eta, 0, 1);
+// phi = (1 - eta)^4 (4 eta + 1) = t^4 (5 - 4 t).  Exactly 0 for eta >= 1.
+__device__ __forceinline__ double wendland_r2(double r2) {
+    const double x = fmax(r2, 1e-200);
+    double r = __builtin_amdgcn_rsq(x);
+    double y = x * r;
+    const double e = fma(-y, r, 1.0);
+    r = fma(0.5 * r, e, r);
+    y = x * r;
+    const double d = fma(-y, y, x);
+    y = fma(0.5 * r, d, y);
+    const double t = fmin(fmax(1.0 - y, 0.0), 1.0);
+    const double t2 = t * t;
+    return (t2 * t2) * fma(-4.0, t, 5.0);
+}
+
+__device__ __forceinline__ double dist2(double ax, double ay, double az, double bx, double by, double bz) {
+    const double dx = ax - bx, dy = ay - by, dz = az - bz;
+    return fma(dz, dz, fma(dy, dy, dx * dx));
+}
+
+// Squared norm summed as (x^2 + y^2) + z^2 with no fused multiply-add, for
+// the integer decisions of the starting-node rule.
+__device__ __forceinline__ double sq3_exact(double x, double y, double z) {
+#pragma clang fp contract(off)
+    const double s = x * x + y * y;
+    return s + z * z;
+}
+
+}  // namespace gcb

@@ -40,6 +40,10 @@ struct IterCtx {
 int sweep_blocks(int gmax);
 void launch_init_append(hipStream_t s, const IterCtx& ic, int t);
 void launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub);
+int multi_padded_r(int rc);
+bool launch_deform_multi(hipStream_t s, const Support& sp, int n, int rc, const double* modes_dev, double* Dbuf,
+                         double* Ybuf, double* Wbuf, int64_t nv, const void* xyz, int in_f64, double inv_r, void* out,
+                         int out_f64);
 void launch_transpose_factor(hipStream_t s, const double* Mr, double* Mc, int n, int64_t cap);
 void launch_certify(hipStream_t s, const Boundary& bd, const Support& sp, int n, double* red, double* out);
 void launch_volume(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,

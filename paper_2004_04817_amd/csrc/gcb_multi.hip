@@ -1,0 +1,154 @@
+// Multiple right-hand sides on one support set (many deformation modes or
+// time steps; Eqs. 4-6 with a matrix of displacements): weights by the FP64
+// inverse factor, W = M^T (M D_S), and the volume sweep
+// out = Phi(targets, S) W as a dense contraction on FP64 matrix cores.
+#include "gcb_internal.h"
+#include "gcb_kernels.h"
+#include "gcb_device.h"
+
+namespace gcb {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// D_S[s][c] = modes[orig[s]][c] for the n supports (R columns, first rc real).
+__global__ __launch_bounds__(kBlock) void k_gather_modes(int n, int rc, int R, const int32_t* __restrict__ orig,
+                                                         const double* __restrict__ modes, double* __restrict__ D) {
+    const int64_t x = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (x >= (int64_t)n * R) return;
+    const int s = (int)(x / R), c = (int)(x % R);
+    D[x] = c < rc ? modes[(int64_t)orig[s] * rc + c] : 0.0;
+}
+
+// Y[i][c] = sum_{j <= i} M[i][j] D[j][c]; lanes are columns, the row of M is wave-uniform.
+__global__ __launch_bounds__(kBlock) void k_trmm_lower(int n, int R, const double* __restrict__ M,
+                                                       const double* __restrict__ D, double* __restrict__ Y) {
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    const int i = blockIdx.y;
+    if (c >= R) return;
+    const double* Mi = M + (size_t)i * (i + 1) / 2;
+    double a0 = 0.0, a1 = 0.0;
+    int j = 0;
+    for (; j + 1 <= i; j += 2) {
+        a0 = fma(Mi[j], D[(size_t)j * R + c], a0);
+        a1 = fma(Mi[j + 1], D[(size_t)(j + 1) * R + c], a1);
+    }
+    if (j <= i) a0 = fma(Mi[j], D[(size_t)j * R + c], a0);
+    Y[(size_t)i * R + c] = a0 + a1;
+}
+
+// W[j][c] = sum_{i >= j} M[i][j] Y[i][c], M read by columns from Mc.
+__global__ __launch_bounds__(kBlock) void k_trmm_upper(int n, int R, const double* __restrict__ Mc, int64_t cap,
+                                                       const double* __restrict__ Y, double* __restrict__ W) {
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    const int j = blockIdx.y;
+    if (c >= R) return;
+    const double* col = Mc + (size_t)j * cap - (size_t)j * (j - 1) / 2;
+    double a0 = 0.0, a1 = 0.0;
+    int i = j;
+    for (; i + 1 < n; i += 2) {
+        a0 = fma(col[i - j], Y[(size_t)i * R + c], a0);
+        a1 = fma(col[i + 1 - j], Y[(size_t)(i + 1) * R + c], a1);
+    }
+    if (i < n) a0 = fma(col[i - j], Y[(size_t)i * R + c], a0);
+    W[(size_t)j * R + c] = a0 + a1;
+}
+
+// Volume sweep with R right-hand sides (R a multiple of 16, at most kMaxR).
+// Block: kMWaves waves, each owning 16 targets and all R columns; supports in
+// chunks of kMChunk staged in LDS (coordinates and the chunk of W).  Per step
+// of 4 supports a lane evaluates one phi (target l%16, support l/16): the A
+// operand of v_mfma_f64_16x16x4f64; B is W[support][16 t + l%16]; the
+// accumulator of tile t holds out[target (l/16) + 4 r][16 t + l%16].
+constexpr int kMWaves = 8;
+constexpr int kMChunk = 32;
+constexpr int kMaxR = 192;
+
+template <typename TIn, typename TOut>
+__global__ __launch_bounds__(kMWaves * 64) void k_volume_multi(int64_t nv, const TIn* __restrict__ xyz, double inv_r,
+                                                                int n, const double* __restrict__ sx,
+                                                                const double* __restrict__ sy,
+                                                                const double* __restrict__ sz,
+                                                                const double* __restrict__ W, int R, int rc,
+                                                                TOut* __restrict__ out) {
+    __shared__ double lw[kMChunk][kMaxR];
+    __shared__ double lc[3][kMChunk];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int nt = R / 16;
+    const int64_t tbase = ((int64_t)blockIdx.x * kMWaves + wave) * 16;
+    const int64_t tgt = min(tbase + (lane & 15), nv - 1);
+    const double tx = (double)xyz[3 * tgt] * inv_r, ty = (double)xyz[3 * tgt + 1] * inv_r,
+                 tz = (double)xyz[3 * tgt + 2] * inv_r;
+    d4 acc[kMaxR / 16];
+#pragma unroll
+    for (int t = 0; t < kMaxR / 16; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    const int kq = lane >> 4;   // support within a step of 4 (A row / B column index k)
+    const int jl = lane & 15;
+    for (int c0 = 0; c0 < n; c0 += kMChunk) {
+        const int cn = min(kMChunk, n - c0);
+        __syncthreads();
+        for (int x = threadIdx.x; x < kMChunk * R; x += kMWaves * 64) {
+            const int s = x / R, c = x % R;
+            lw[s][c] = s < cn ? W[(size_t)(c0 + s) * R + c] : 0.0;
+        }
+        if (threadIdx.x < kMChunk) {
+            const int s = threadIdx.x;
+            lc[0][s] = s < cn ? sx[c0 + s] : 1e3;
+            lc[1][s] = s < cn ? sy[c0 + s] : 1e3;
+            lc[2][s] = s < cn ? sz[c0 + s] : 1e3;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int s0 = 0; s0 < kMChunk; s0 += 4) {
+            const int s = s0 + kq;
+            const double a = wendland_r2(dist2(tx, ty, tz, lc[0][s], lc[1][s], lc[2][s]));
+#pragma unroll
+            for (int t = 0; t < kMaxR / 16; ++t) {
+                if (t < nt) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, lw[s][16 * t + jl], acc[t], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kMaxR / 16; ++t) {
+        if (t < nt) {
+            const int c = 16 * t + jl;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = tbase + kq + 4 * r;
+                if (row < nv && c < rc) out[row * rc + c] = (TOut)acc[t][r];
+            }
+        }
+    }
+}
+
+int multi_padded_r(int rc) { return (rc + 15) / 16 * 16; }
+
+bool launch_deform_multi(hipStream_t s, const Support& sp, int n, int rc, const double* modes_dev, double* Dbuf,
+                         double* Ybuf, double* Wbuf, int64_t nv, const void* xyz, int in_f64, double inv_r, void* out,
+                         int out_f64) {
+    const int R = multi_padded_r(rc);
+    if (R > kMaxR || n <= 0) return false;
+    const int64_t cnt = (int64_t)n * R;
+    hipLaunchKernelGGL(k_gather_modes, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, rc, R,
+                       sp.orig, modes_dev, Dbuf);
+    const dim3 g((unsigned)((R + kBlock - 1) / kBlock), (unsigned)n);
+    hipLaunchKernelGGL(k_trmm_lower, g, dim3(kBlock), 0, s, n, R, sp.M, Dbuf, Ybuf);
+    hipLaunchKernelGGL(k_trmm_upper, g, dim3(kBlock), 0, s, n, R, sp.Mc, sp.cap, Ybuf, Wbuf);
+    if (nv <= 0) return true;
+    const unsigned gv = (unsigned)((nv + kMWaves * 16 - 1) / (kMWaves * 16));
+    if (in_f64 && out_f64)
+        hipLaunchKernelGGL((k_volume_multi<double, double>), dim3(gv), dim3(kMWaves * 64), 0, s, nv,
+                           (const double*)xyz, inv_r, n, sp.sx, sp.sy, sp.sz, Wbuf, R, rc, (double*)out);
+    else if (in_f64)
+        hipLaunchKernelGGL((k_volume_multi<double, float>), dim3(gv), dim3(kMWaves * 64), 0, s, nv,
+                           (const double*)xyz, inv_r, n, sp.sx, sp.sy, sp.sz, Wbuf, R, rc, (float*)out);
+    else if (out_f64)
+        hipLaunchKernelGGL((k_volume_multi<float, double>), dim3(gv), dim3(kMWaves * 64), 0, s, nv,
+                           (const float*)xyz, inv_r, n, sp.sx, sp.sy, sp.sz, Wbuf, R, rc, (double*)out);
+    else
+        hipLaunchKernelGGL((k_volume_multi<float, float>), dim3(gv), dim3(kMWaves * 64), 0, s, nv,
+                           (const float*)xyz, inv_r, n, sp.sx, sp.sy, sp.sz, Wbuf, R, rc, (float*)out);
+    return true;
+}
+
+}  // namespace gcb

@@ -666,10 +666,58 @@ int gcb_deform(gcb_ctx* ctx, int64_t nv, const void* xyz, int in_dtype, void* ou
     });
 }
 
-int gcb_deform_multi(gcb_ctx* ctx, int32_t, const double*, int64_t, const void*, int, void*, int, int) {
+int gcb_deform_multi(gcb_ctx* ctx, int32_t k_modes, const double* disp_modes, int64_t nv, const void* xyz,
+                     int in_dtype, void* out, int out_dtype, int mem) {
     return guard(ctx, [&] {
-        fail(ctx, GCB_E_STATE, "gcb_deform_multi is not available in this build");
-        return GCB_E_STATE;
+        if (!ctx->selected) fail(ctx, GCB_E_STATE, "no finished selection");
+        if (k_modes < 1 || 3 * (int64_t)k_modes > 192) fail(ctx, GCB_E_INVALID, "need 1 <= k_modes <= 64");
+        if (nv < 0) fail(ctx, GCB_E_INVALID, "nv < 0");
+        if (!disp_modes || (nv > 0 && (!xyz || !out))) fail(ctx, GCB_E_INVALID, "NULL pointer");
+        if ((in_dtype != GCB_F32 && in_dtype != GCB_F64) || (out_dtype != GCB_F32 && out_dtype != GCB_F64))
+            fail(ctx, GCB_E_INVALID, "dtype must be GCB_F32 or GCB_F64");
+        if (mem != GCB_MEM_HOST && mem != GCB_MEM_DEVICE) fail(ctx, GCB_E_INVALID, "bad mem kind");
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        const int rc = 3 * k_modes;
+        const int R = multi_padded_r(rc);
+        const int n = (int)ctx->info.nc;
+        const int64_t nb = ctx->bd.nb;
+        const size_t modes_b = sizeof(double) * (size_t)nb * rc;
+        const size_t in_b = (size_t)nv * 3 * (in_dtype == GCB_F64 ? 8 : 4);
+        const size_t out_b = (size_t)nv * rc * (out_dtype == GCB_F64 ? 8 : 4);
+        const size_t work_b = sizeof(double) * 3 * (size_t)n * R;
+        const size_t need = work_b + modes_b + (mem == GCB_MEM_HOST ? in_b + out_b : 0) + 1024;
+        if (ctx->tmp_cap < need) {
+            if (ctx->tmp) (void)hipFree(ctx->tmp);
+            ctx->tmp = nullptr;
+            ctx->tmp_cap = 0;
+            HIPCHK(ctx, hipMalloc(&ctx->tmp, need));
+            ctx->tmp_cap = need;
+        }
+        char* base = static_cast<char*>(ctx->tmp);
+        double* D = reinterpret_cast<double*>(base);
+        double* Y = D + (size_t)n * R;
+        double* Wm = Y + (size_t)n * R;
+        char* p = base + work_b;
+        double* modes_d = const_cast<double*>(disp_modes);
+        if (mem == GCB_MEM_HOST) {
+            modes_d = reinterpret_cast<double*>(p);
+            HIPCHK(ctx, hipMemcpyAsync(modes_d, disp_modes, modes_b, hipMemcpyHostToDevice, ctx->stream));
+        }
+        p += modes_b;
+        const void* din = xyz;
+        void* dout = out;
+        if (mem == GCB_MEM_HOST && nv > 0) {
+            HIPCHK(ctx, hipMemcpyAsync(p, xyz, in_b, hipMemcpyHostToDevice, ctx->stream));
+            din = p;
+            dout = p + in_b;
+        }
+        if (!launch_deform_multi(ctx->stream, ctx->sp, n, rc, modes_d, D, Y, Wm, nv, din, in_dtype == GCB_F64,
+                                 ctx->bd.inv_r, dout, out_dtype == GCB_F64))
+            fail(ctx, GCB_E_INVALID, "unsupported multi-RHS shape");
+        HIPCHK(ctx, hipGetLastError());
+        if (mem == GCB_MEM_HOST && nv > 0) HIPCHK(ctx, hipMemcpyAsync(out, dout, out_b, hipMemcpyDeviceToHost, ctx->stream));
+        if (mem == GCB_MEM_HOST) sync(ctx);
+        return GCB_OK;
     });
 }
 

@@ -329,3 +329,14 @@ def test_table1_cost_model():
     m = 9 * nb / (4 * nc)
     c2 = oracle.cost_model(nc, nb, 0, m)
     assert math.isclose(c2["errors"], c2["solve"], rel_tol=1e-12)
+
+
+def test_solve_on_support_matches_library_solve():
+    """Eqs. 4-5 restricted to S with several right-hand sides: RC forward/back
+    substitution equals numpy.linalg.solve for every column."""
+    p = synth.tiny_problem(nb=40, seed=9, radius=1.3)
+    S = np.array([3, 17, 8, 31, 0, 22, 39, 11])
+    D = np.random.default_rng(5).standard_normal((40, 7))
+    W = oracle.solve_on_support(p.xyz, S, p.radius, D)
+    Wr = np.linalg.solve(brute.rbf_matrix(p.xyz[S], p.xyz[S], p.radius), D[S])
+    assert np.abs(W - Wr).max() < 1e-10 * np.abs(Wr).max()
