@@ -155,6 +155,54 @@ int gcb_deform_multi(gcb_ctx *ctx, int32_t k_modes, const double *disp_modes, in
  * support set (the convergence certificate): max and RMS of |F(r_j) - d_j|_2. */
 int gcb_certify(gcb_ctx *ctx, double *max_err, double *rms_err);
 
+/* ------------------------------------------------------------------
+ * Batches: several independent surfaces advanced by shared launches.
+ * One greedy iteration of every running context of a batch is three kernel
+ * launches in total, whatever the number of contexts, so the launch latency
+ * that bounds a single selection is shared (uneven surfaces, continuous
+ * batching of requests).  Each context keeps its own state, support set and
+ * factor; results equal those of gcb_select on the same context.
+ * ------------------------------------------------------------------ */
+typedef struct gcb_batch gcb_batch;
+
+/* Create a batch on HIP device `device` that enqueues on the hipStream_t
+ * `hip_stream`, taken verbatim (NULL is the null stream).  Release with
+ * gcb_batch_destroy. */
+int gcb_batch_create(gcb_batch **out, int device, void *hip_stream);
+void gcb_batch_destroy(gcb_batch *b);   /* NULL-safe; contexts are not touched */
+const char *gcb_batch_last_error(const gcb_batch *b);
+
+/* Start the selection of ctx (boundary and parameters set, same device as
+ * the batch): partition and staging, the three starting nodes.  ctx is
+ * switched to the batch's stream.  Errors are those of gcb_select; the
+ * message is in gcb_last_error(ctx). */
+int gcb_batch_begin(gcb_batch *b, gcb_ctx *ctx);
+
+/* Run `iterations` (1..4096) further greedy iterations of every listed
+ * context whose selection is in progress (at most 64 of them), in shared
+ * launches; the host waits for the batch's stream first.  running[i]
+ * (may be NULL) gets 1 while context i still runs.  Returns the number of
+ * contexts still running, or a negative status (message in the failing
+ * context's gcb_last_error, or in gcb_batch_last_error). */
+int32_t gcb_batch_step(gcb_batch *b, gcb_ctx *const *ctxs, int32_t count, int32_t iterations, int32_t *running);
+
+/* Finish a context whose selection stopped: FP64 certificate over all its
+ * boundary nodes, result in *info (may be NULL).  Returns GCB_OK,
+ * GCB_NOT_CONVERGED or an error (GCB_E_STATE if it is still running). */
+int gcb_batch_end(gcb_batch *b, gcb_ctx *ctx, gcb_select_info *info);
+
+/* begin + step until none runs + end, for `count` contexts, in slices of at
+ * most 64 contexts; infos[i] (array may be NULL) gets each result.  Returns
+ * GCB_OK, GCB_NOT_CONVERGED if any context hit its cap, or the first error. */
+int gcb_select_batch(gcb_batch *b, gcb_ctx *const *ctxs, int32_t count, gcb_select_info *infos);
+
+/* Eq. (6) for every context in one launch: context i moves nv[i] points
+ * xyz[i] (nv[i] x 3 of in_dtype) into out[i] (nv[i] x 3 of out_dtype).  All
+ * pointers are device memory of the batch's device; every context needs a
+ * finished selection. */
+int gcb_deform_batch(gcb_batch *b, gcb_ctx *const *ctxs, int32_t count, const int64_t *nv, const void *const *xyz,
+                     int in_dtype, void *const *out, int out_dtype);
+
 /* Host-only: the seeded partition the library uses (Section 3: groups
  * pairwise disjoint, sizes differ by at most one).  Fisher-Yates shuffle pi
  * of 0..nb-1 driven by splitmix64(seed), node pi[t] to group t mod m.

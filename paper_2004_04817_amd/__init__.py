@@ -28,7 +28,9 @@ GCB_PREC_FP64, GCB_PREC_FP32_EVAL = 0, 1
 
 EXPORTS = ["gcb_version", "gcb_partition", "gcb_create", "gcb_destroy", "gcb_last_error", "gcb_set_stream",
            "gcb_set_boundary", "gcb_set_displacement", "gcb_set_params", "gcb_set_groups", "gcb_select",
-           "gcb_get_support", "gcb_get_log", "gcb_deform", "gcb_deform_multi", "gcb_certify"]
+           "gcb_get_support", "gcb_get_log", "gcb_deform", "gcb_deform_multi", "gcb_certify",
+           "gcb_batch_create", "gcb_batch_destroy", "gcb_batch_last_error", "gcb_batch_begin", "gcb_batch_step",
+           "gcb_batch_end", "gcb_select_batch", "gcb_deform_batch"]
 
 
 class GcbError(RuntimeError):
@@ -90,6 +92,17 @@ def lib():
         L.gcb_deform.argtypes = [vp, i64, vp, C.c_int, vp, C.c_int, C.c_int]
         L.gcb_deform_multi.argtypes = [vp, i32, vp, i64, vp, C.c_int, vp, C.c_int, C.c_int]
         L.gcb_certify.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.gcb_batch_create.argtypes = [C.POINTER(vp), C.c_int, vp]
+        L.gcb_batch_destroy.argtypes = [vp]
+        L.gcb_batch_destroy.restype = None
+        L.gcb_batch_last_error.argtypes = [vp]
+        L.gcb_batch_last_error.restype = C.c_char_p
+        L.gcb_batch_begin.argtypes = [vp, vp]
+        L.gcb_batch_step.argtypes = [vp, vp, i32, i32, vp]
+        L.gcb_batch_step.restype = i32
+        L.gcb_batch_end.argtypes = [vp, vp, C.POINTER(SelectInfo)]
+        L.gcb_select_batch.argtypes = [vp, vp, i32, vp]
+        L.gcb_deform_batch.argtypes = [vp, vp, i32, vp, vp, C.c_int, vp, C.c_int]
         for name in EXPORTS:
             getattr(L, name)
         _LIB = L
@@ -314,6 +327,115 @@ class Context:
         mx, rms = C.c_double(), C.c_double()
         self._check(lib().gcb_certify(self._h, C.byref(mx), C.byref(rms)))
         return mx.value, rms.value
+
+
+class Batch:
+    """Several contexts advanced by shared launches (wraps a gcb_batch).
+
+    Contexts handed to a batch run on the batch's stream from then on."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        """stream: a hipStream_t handle; None takes torch's current stream of the device."""
+        if stream is None:
+            import torch
+            stream = int(torch.cuda.current_stream(device).cuda_stream)
+        h = C.c_void_p()
+        rc = lib().gcb_batch_create(C.byref(h), int(device), C.c_void_p(stream) if stream else None)
+        if rc != GCB_OK:
+            raise GcbError(rc, lib().gcb_batch_last_error(None).decode())
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gcb_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def _raise(self, rc, ctxs=()):
+        msg = lib().gcb_batch_last_error(self._h).decode()
+        for c in ctxs:
+            cm = lib().gcb_last_error(c._h).decode()
+            if cm:
+                msg = (msg + "; " if msg else "") + cm
+        raise GcbError(rc, msg)
+
+    @staticmethod
+    def _handles(ctxs):
+        return (C.c_void_p * len(ctxs))(*[c._h.value for c in ctxs])
+
+    def begin(self, ctx: Context):
+        rc = lib().gcb_batch_begin(self._h, ctx._h)
+        if rc != GCB_OK:
+            self._raise(rc, [ctx])
+
+    def step(self, ctxs, iterations: int = 64) -> np.ndarray:
+        """Advance every running context; returns the 0/1 running flags."""
+        run = np.zeros(len(ctxs), np.int32)
+        n = lib().gcb_batch_step(self._h, self._handles(ctxs), len(ctxs), int(iterations), run.ctypes.data)
+        if n < 0:
+            self._raise(int(n), ctxs)
+        return run
+
+    def end(self, ctx: Context) -> dict:
+        info = SelectInfo()
+        rc = lib().gcb_batch_end(self._h, ctx._h, C.byref(info))
+        if rc not in (GCB_OK, GCB_NOT_CONVERGED):
+            self._raise(rc, [ctx])
+        ctx.nc = info.nc
+        return info.as_dict()
+
+    def select(self, ctxs) -> list:
+        infos = (SelectInfo * len(ctxs))()
+        rc = lib().gcb_select_batch(self._h, self._handles(ctxs), len(ctxs), infos)
+        if rc not in (GCB_OK, GCB_NOT_CONVERGED):
+            self._raise(rc, ctxs)
+        out = []
+        for c, inf in zip(ctxs, infos):
+            c.nc = inf.nc
+            out.append(inf.as_dict())
+        return out
+
+    def deform(self, ctxs, xyzs, outs=None, out_dtype=None):
+        """Eq. (6) for every context in one launch; xyzs are device tensors (nv_i, 3)."""
+        import torch
+        if len(xyzs) != len(ctxs):
+            raise ValueError("one point set per context")
+        if not xyzs:
+            return []
+        in_dt = GCB_F64 if xyzs[0].dtype == torch.float64 else GCB_F32
+        if outs is None:
+            odt = torch.float64 if out_dtype in (None, np.float64, torch.float64) else torch.float32
+            outs = [torch.empty(x.shape, dtype=odt, device=x.device) for x in xyzs]
+        out_dt = GCB_F64 if outs[0].dtype == torch.float64 else GCB_F32
+        keep = []
+        for x, o in zip(xyzs, outs):
+            px, mx, kx = _arg(x, np.float64 if in_dt == GCB_F64 else np.float32)
+            po, mo, ko = _arg(o, np.float64 if out_dt == GCB_F64 else np.float32)
+            if mx != GCB_MEM_DEVICE or mo != GCB_MEM_DEVICE:
+                raise ValueError("batched deformation takes device tensors")
+            if tuple(kx.shape) != tuple(ko.shape) or kx.shape[-1] != 3:
+                raise ValueError("points and outputs must be (nv, 3) of equal shape")
+            keep.append((px, po, int(kx.shape[0])))
+        nv = (C.c_int64 * len(keep))(*[k[2] for k in keep])
+        xp = (C.c_void_p * len(keep))(*[k[0] for k in keep])
+        op = (C.c_void_p * len(keep))(*[k[1] for k in keep])
+        rc = lib().gcb_deform_batch(self._h, self._handles(ctxs), len(ctxs), nv, xp, in_dt, op, out_dt)
+        if rc != GCB_OK:
+            self._raise(rc, ctxs)
+        return outs
 
 
 def select(xyz, disp, radius, m, tol_abs, nc_max=None, seed=0, precision=GCB_PREC_FP64, init_idx=None,

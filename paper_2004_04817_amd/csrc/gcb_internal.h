@@ -135,6 +135,9 @@ struct gcb_ctx {
     std::vector<int64_t> chunk_key;
     uint64_t alloc_gen = 0;            // bumped by every device allocation
     gcb::GState *state_pin = nullptr;   // pinned host copy of the state
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;   // selection start / end
+    int64_t k_host = 3;                // the next iteration's k
+    bool in_progress = false;          // a selection started by a batch and not yet finished
     // scratch for certificate / volume
     double *red = nullptr;
     int64_t red_cap = 0;

@@ -19,6 +19,73 @@ void launch_stage(hipStream_t s, int64_t nb, const double* xyz, const double* di
                   double inv_r, Boundary& bd);
 void launch_check_finite(hipStream_t s, int64_t count, const double* a, const double* b, int32_t* flag);
 void launch_init_nodes(hipStream_t s, const Boundary& bd, int32_t* init, ArgRec* rec);
+// Arguments of the three iteration kernels (by value for one surface, from a
+// table for a batch of surfaces).
+struct SweepArgs {
+    const GState* st;
+    int t0, T, lpt, tpl;
+    const double *px, *py, *pz, *pdx, *pdy, *pdz;
+    const uint8_t* inS;
+    const int32_t* perm;
+    SupportView sv;
+    int64_t cap;
+    ArgRec* rec;
+};
+
+struct FactorLArgs {
+    GState* st;
+    IterRec* irec;
+    const ArgRec* srec;
+    int nrec;
+    int32_t m;
+    int g;
+    int init_t;
+    const int32_t* init;
+    const int32_t* pos_of;
+    const double *px, *py, *pz, *pdx, *pdy, *pdz;
+    SupportView sv;
+    const double* Mr;
+    double* l;
+    double* Pb;
+    double tol_abs;
+    int64_t nc_max, cap;
+    int32_t* log_group;
+    int32_t* log_node;
+    double* log_err;
+    int8_t* log_app;
+    int64_t log_cap;
+    int32_t active;
+};
+
+struct FactorUArgs {
+    GState* st;
+    const IterRec* irec;
+    uint8_t* inS;
+    SupportMut sm;
+    double* Mc;
+    int64_t cap;
+    const double* l;
+    const double* Pb;
+    int32_t active;
+};
+
+constexpr int kMaxBatch = 64;
+// Blocks of a batched launch: surface s owns blocks [off[s], off[s+1]).
+struct BlockMap {
+    int count;
+    int off[kMaxBatch + 1];
+};
+
+// One surface of a batched volume sweep.
+struct VolDesc {
+    const void* xyz;
+    void* out;
+    int64_t nv;
+    SupportView sv;
+    int n;
+    double inv_r;
+};
+
 // Everything one greedy iteration's kernels touch.
 struct IterCtx {
     GState* st;
@@ -38,6 +105,15 @@ struct IterCtx {
 };
 
 int sweep_blocks(int gmax);
+// Block records a sweep with these arguments writes (0 for an empty group).
+int sweep_records(const SweepArgs& A);
+int factor_blocks(int64_t n_ub);
+SweepArgs make_sweep_args(const IterCtx& ic, int g);
+FactorLArgs make_factor_l_args(const IterCtx& ic, int g, int nrec, int init_t);
+FactorUArgs make_factor_u_args(const IterCtx& ic);
+void launch_volume_batch(hipStream_t s, const VolDesc* tab, const BlockMap& map, int in_f64, int out_f64);
+void launch_iteration_batch(hipStream_t s, const SweepArgs* sweep_tab, const FactorLArgs* fl_tab,
+                            const FactorUArgs* fu_tab, const BlockMap& sweep_map, const BlockMap& factor_map);
 void launch_init_append(hipStream_t s, const IterCtx& ic, int t);
 void launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub);
 int multi_padded_r(int rc);

@@ -11,6 +11,8 @@
 
 namespace gcb {
 
+#define GCB_LAUNCH(kern, grid, block, stream, ...) hipLaunchKernelGGL(kern, grid, block, 0, stream, __VA_ARGS__)
+
 // Accumulate sum_{j in [s0, s1)} w_j phi(|t - s_j|) for one target per lane.
 __device__ __forceinline__ void accumulate64(double tx, double ty, double tz, int s0, int s1,
                                              const double* __restrict__ sx, const double* __restrict__ sy,
@@ -157,6 +159,11 @@ inline void sweep_layout(int T, int& lpt, int& tpl) {
     if (lpt > g_tuning.sweep_lpt_max) lpt = g_tuning.sweep_lpt_max;
 }
 
+__host__ __device__ inline int sweep_nblocks_dev(int T, int lpt, int tpl) {
+    const int per = (kBlock / lpt) * tpl;
+    return T > 0 ? (T + per - 1) / per : 1;
+}
+
 inline int sweep_nblocks(int T) {
     int lpt, tpl;
     sweep_layout(T, lpt, tpl);
@@ -200,12 +207,20 @@ __device__ __forceinline__ bool better_rec(const ArgRec& a, const ArgRec& b) { r
 // Supports staged in LDS per window: all loads of a window are issued at once.
 constexpr int kStage = 1280;
 
-__global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st, int t0, int T, int lpt, int tpl,
-                                                  const double* __restrict__ px, const double* __restrict__ py,
-                                                  const double* __restrict__ pz, const double* __restrict__ pdx,
-                                                  const double* __restrict__ pdy, const double* __restrict__ pdz,
-                                                  const uint8_t* __restrict__ inS, const int32_t* __restrict__ perm,
-                                                  SupportView sv, int64_t cap, ArgRec* __restrict__ rec) {
+__device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
+    const GState* __restrict__ st = A.st;
+    const int t0 = A.t0, T = A.T, lpt = A.lpt, tpl = A.tpl;
+    const double* __restrict__ px = A.px;
+    const double* __restrict__ py = A.py;
+    const double* __restrict__ pz = A.pz;
+    const double* __restrict__ pdx = A.pdx;
+    const double* __restrict__ pdy = A.pdy;
+    const double* __restrict__ pdz = A.pdz;
+    const uint8_t* __restrict__ inS = A.inS;
+    const int32_t* __restrict__ perm = A.perm;
+    const SupportView sv = A.sv;
+    const int64_t cap = A.cap;
+    ArgRec* __restrict__ rec = A.rec;
     __shared__ double ls[6][kStage];
     __shared__ double red[3][4][kBlock / 64];
     __shared__ double s_e2[kBlock / 64 * 4];
@@ -214,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st,
     const int groups = kBlock / lpt;                // target groups per block
     const int grp = threadIdx.x / lpt;
     const int gl = threadIdx.x % lpt;               // lane within the group
-    const int tbase = (blockIdx.x * groups + grp) * tpl;
+    const int tbase = (bid * groups + grp) * tpl;
     if (threadIdx.x == 0) {
         s_n = st->n;
         s_done = st->done;
@@ -236,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st,
     int ct = 0;
     if ((int)threadIdx.x < ncand) {
         const int gq = threadIdx.x / 4, q = threadIdx.x % 4;
-        ct = (blockIdx.x * groups + gq) * tpl + q;
+        ct = (bid * groups + gq) * tpl + q;
         const int tc = min(ct, T - 1);
         clive = q < tpl && ct < T && !inS[t0 + tc];
         cdx = pdx[t0 + tc];
@@ -356,7 +371,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st,
     }
     __syncthreads();
     if ((int)threadIdx.x == s_win) {
-        ArgRec& o = rec[blockIdx.x];
+        ArgRec& o = rec[bid];
         o.e2 = e2;
         o.orig = clive ? corig : 0x7fffffff;
         o.pos = t0 + ct;
@@ -370,20 +385,41 @@ __global__ __launch_bounds__(kBlock) void k_sweep(const GState* __restrict__ st,
     }
 }
 
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) { sweep_body(A, blockIdx.x); }
+
 // l = M b, one wave per row of M (kRowsL rows per block); b_j = phi(|r_new -
 // s_j| / R) staged in LDS windows.  Block partials Pb[blk] = (b.W over
 // columns [i0, i0 + kRowsL), l.l over rows [i0, i0 + kRowsL)).  Before that,
 // every block reduces the sweep records (nrec of them) to the group maximum
 // and takes the decision; block 0 stores it.  With init_t >= 0 the node is
 // the starting node init[init_t] instead.
-__global__ __launch_bounds__(kBigBlock) void k_factor_l(
-    GState* __restrict__ st, IterRec* __restrict__ irec, const ArgRec* __restrict__ srec, int nrec, int32_t m, int g,
-    int init_t, const int32_t* __restrict__ init, const int32_t* __restrict__ pos_of, const double* __restrict__ px,
-    const double* __restrict__ py, const double* __restrict__ pz, const double* __restrict__ pdx,
-    const double* __restrict__ pdy, const double* __restrict__ pdz, SupportView sv, const double* __restrict__ Mr,
-    double* __restrict__ l, double* __restrict__ Pb, double tol_abs, int64_t nc_max, int64_t cap,
-    int32_t* __restrict__ log_group, int32_t* __restrict__ log_node, double* __restrict__ log_err,
-    int8_t* __restrict__ log_app, int64_t log_cap) {
+__device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bid) {
+    GState* __restrict__ st = A.st;
+    IterRec* __restrict__ irec = A.irec;
+    const ArgRec* __restrict__ srec = A.srec;
+    const int nrec = A.nrec;
+    const int32_t m = A.m;
+    const int g = A.g;
+    const int init_t = A.init_t;
+    const int32_t* __restrict__ init = A.init;
+    const int32_t* __restrict__ pos_of = A.pos_of;
+    const double* __restrict__ px = A.px;
+    const double* __restrict__ py = A.py;
+    const double* __restrict__ pz = A.pz;
+    const double* __restrict__ pdx = A.pdx;
+    const double* __restrict__ pdy = A.pdy;
+    const double* __restrict__ pdz = A.pdz;
+    const SupportView sv = A.sv;
+    const double* __restrict__ Mr = A.Mr;
+    double* __restrict__ l = A.l;
+    double* __restrict__ Pb = A.Pb;
+    const double tol_abs = A.tol_abs;
+    const int64_t nc_max = A.nc_max, cap = A.cap;
+    int32_t* __restrict__ log_group = A.log_group;
+    int32_t* __restrict__ log_node = A.log_node;
+    double* __restrict__ log_err = A.log_err;
+    int8_t* __restrict__ log_app = A.log_app;
+    const int64_t log_cap = A.log_cap;
     __shared__ double bw[kBWindow];
     __shared__ double sl[kRowsL];
     __shared__ GState s_st;
@@ -421,21 +457,21 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_l(
     }
     double wsx = 0.0, wsy = 0.0, wsz = 0.0, wwx = 0.0, wwy = 0.0, wwz = 0.0;
     if (wave == 0 && lane < kRowsL) {
-        const int j = min((int)blockIdx.x * kRowsL + lane, (int)cap - 1);
+        const int j = min((int)bid * kRowsL + lane, (int)cap - 1);
         wsx = sv.sx[j]; wsy = sv.sy[j]; wsz = sv.sz[j];
         wwx = sv.wx[j]; wwy = sv.wy[j]; wwz = sv.wz[j];
     }
     __syncthreads();
     const GState sg = s_st;
     if (init_t < 0 && sg.done) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (bid == 0 && threadIdx.x == 0) {
             irec->app = 0;
             irec->ran = 0;
         }
         return;
     }
     const int n = init_t >= 0 ? init_t : sg.n;
-    const int i0 = blockIdx.x * kRowsL;
+    const int i0 = bid * kRowsL;
     const int i = i0 + wave;
     // this wave's row of M, loaded while the decision is taken
     constexpr int kRowPre = 16;
@@ -455,7 +491,7 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_l(
             s_q[0] = px[p];
             s_q[1] = py[p];
             s_q[2] = pz[p];
-            if (blockIdx.x == 0) {
+            if (bid == 0) {
                 irec->n = init_t;
                 irec->app = 1;
                 irec->init = 1;
@@ -525,7 +561,7 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_l(
             s_q[0] = b.x;
             s_q[1] = b.y;
             s_q[2] = b.z;
-            if (blockIdx.x == 0) {
+            if (bid == 0) {
                 if (d.done != 4) {
                     const int64_t it = sg.log_len;
                     if (it < log_cap) {
@@ -558,7 +594,7 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_l(
     __syncthreads();
     if (!s_app) return;
     const int nblk = max(1, (n + kRowsL - 1) / kRowsL);
-    if ((int)blockIdx.x >= nblk) return;
+    if ((int)bid >= nblk) return;
     const int i1 = min(n, i0 + kRowsL);
     const double qx = s_q[0], qy = s_q[1], qz = s_q[2];
     double acc = 0.0;
@@ -619,23 +655,30 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_l(
         fz = wave_sum(fz);
         ll = wave_sum(ll);
         if (lane == 0) {
-            Pb[4 * blockIdx.x + 0] = fx;
-            Pb[4 * blockIdx.x + 1] = fy;
-            Pb[4 * blockIdx.x + 2] = fz;
-            Pb[4 * blockIdx.x + 3] = ll;
+            Pb[4 * bid + 0] = fx;
+            Pb[4 * bid + 1] = fy;
+            Pb[4 * bid + 2] = fz;
+            Pb[4 * bid + 3] = ll;
         }
     }
 }
+
+__global__ __launch_bounds__(kBigBlock) void k_factor_l(FactorLArgs A) { factor_l_body(A, blockIdx.x); }
 
 // u = M^T l, one wave per column j of M read from the column-major copy Mc
 // (column j holds rows j.. at offset j*cap - j(j-1)/2).  Every block first
 // sums the k_factor_l partials in block order to s = 1 - l.l and
 // e = d_new - b.W.  Writes the new row [-u^T/sqrt(s), 1/sqrt(s)] into both
 // copies of M and W <- [W - u e/s; e/s]; block 0 commits the iteration.
-__global__ __launch_bounds__(kBigBlock) void k_factor_u(GState* __restrict__ st, const IterRec* __restrict__ irec,
-                                                        uint8_t* __restrict__ inS, SupportMut sm,
-                                                        double* __restrict__ Mc, int64_t cap,
-                                                        const double* __restrict__ l, const double* __restrict__ Pb) {
+__device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bid) {
+    GState* __restrict__ st = A.st;
+    const IterRec* __restrict__ irec = A.irec;
+    uint8_t* __restrict__ inS = A.inS;
+    const SupportMut sm = A.sm;
+    double* __restrict__ Mc = A.Mc;
+    const int64_t cap = A.cap;
+    const double* __restrict__ l = A.l;
+    const double* __restrict__ Pb = A.Pb;
     __shared__ double part[4][kBigBlock / 64];
     __shared__ double sh[4];
     __shared__ int32_t s_bad;
@@ -651,10 +694,10 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_u(GState* __restrict__ st,
     if (!r.app) return;
     const int n = r.n;
     const int ncb = max(1, (n + kRowsL - 1) / kRowsL);
-    if ((int)blockIdx.x >= ncb) return;
+    if ((int)bid >= ncb) return;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int j = blockIdx.x * kRowsL + wave;
+    const int j = bid * kRowsL + wave;
     // column j of M and the matching entries of l, loaded before s is known
     constexpr int kColPre = 16;
     double mc[kColPre], lv[kColPre];
@@ -697,7 +740,7 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_u(GState* __restrict__ st,
         __syncthreads();
     }
     if (s_bad) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (bid == 0 && threadIdx.x == 0) {
             st->done = 3;
             st->singular_node = r.node_orig;
         }
@@ -724,7 +767,7 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_u(GState* __restrict__ st,
             sm.wz[j] = fma(-u, cz, sm.wz[j]);
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (bid == 0 && threadIdx.x == 0) {
         const int p = r.node_pos;
         sm.M[(size_t)n * (n + 1) / 2 + n] = rs;
         Mc[(size_t)n * cap - (size_t)n * (n - 1) / 2] = rs;
@@ -740,6 +783,40 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_u(GState* __restrict__ st,
         if (r.init) st->init_left -= 1;   // starting nodes are not loop appends
         else st->pairs_append += (uint64_t)n;
     }
+}
+
+__global__ __launch_bounds__(kBigBlock) void k_factor_u(FactorUArgs A) { factor_u_body(A, blockIdx.x); }
+
+// ---------------------------------------------------------------- batched iteration kernels (a10)
+// One launch advances every surface of a batch: block b belongs to surface s
+// with map.off[s] <= b < map.off[s+1]; the surface's arguments for this
+// iteration are read from a table the host fills before each chunk.
+__device__ __forceinline__ int batch_surface(const BlockMap& map, int b) {
+    int s = 0;
+    while (s + 1 < map.count && map.off[s + 1] <= b) ++s;
+    return s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sweep_batch(const SweepArgs* __restrict__ tab, BlockMap map) {
+    const int s = batch_surface(map, blockIdx.x);
+    const SweepArgs A = tab[s];
+    const int local = blockIdx.x - map.off[s];
+    if (A.T <= 0 || local >= sweep_nblocks_dev(A.T, A.lpt, A.tpl)) return;
+    sweep_body(A, local);
+}
+
+__global__ __launch_bounds__(kBigBlock) void k_factor_l_batch(const FactorLArgs* __restrict__ tab, BlockMap map) {
+    const int s = batch_surface(map, blockIdx.x);
+    const FactorLArgs A = tab[s];
+    if (!A.active) return;
+    factor_l_body(A, blockIdx.x - map.off[s]);
+}
+
+__global__ __launch_bounds__(kBigBlock) void k_factor_u_batch(const FactorUArgs* __restrict__ tab, BlockMap map) {
+    const int s = batch_surface(map, blockIdx.x);
+    const FactorUArgs A = tab[s];
+    if (!A.active) return;
+    factor_u_body(A, blockIdx.x - map.off[s]);
 }
 
 // Column-major copy of the first n rows of the packed row-major factor for
@@ -861,6 +938,37 @@ __global__ __launch_bounds__(kBlock) void k_volume64(int64_t nv, const TIn* __re
     }
 }
 
+// Eq. (6) for several surfaces in one launch: block b belongs to surface s
+// with map.off[s] <= b < map.off[s+1].
+template <typename TIn, typename TOut>
+__global__ __launch_bounds__(kBlock) void k_volume_batch(const VolDesc* __restrict__ tab, BlockMap map) {
+    const int s = batch_surface(map, blockIdx.x);
+    const VolDesc d = tab[s];
+    const int64_t t = (int64_t)(blockIdx.x - map.off[s]) * kBlock + threadIdx.x;
+    const bool live = t < d.nv;
+    const int64_t tt = live ? t : d.nv - 1;
+    const TIn* xyz = static_cast<const TIn*>(d.xyz);
+    const double tx = (double)xyz[3 * tt] * d.inv_r;
+    const double ty = (double)xyz[3 * tt + 1] * d.inv_r;
+    const double tz = (double)xyz[3 * tt + 2] * d.inv_r;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    accumulate64(tx, ty, tz, 0, d.n, d.sv.sx, d.sv.sy, d.sv.sz, d.sv.wx, d.sv.wy, d.sv.wz, ax, ay, az);
+    if (live) {
+        TOut* out = static_cast<TOut*>(d.out);
+        out[3 * t] = (TOut)ax;
+        out[3 * t + 1] = (TOut)ay;
+        out[3 * t + 2] = (TOut)az;
+    }
+}
+
+void launch_volume_batch(hipStream_t s, const VolDesc* tab, const BlockMap& map, int in_f64, int out_f64) {
+    const dim3 g((unsigned)map.off[map.count]);
+    if (in_f64 && out_f64) GCB_LAUNCH((k_volume_batch<double, double>), g, dim3(kBlock), s, tab, map);
+    else if (in_f64) GCB_LAUNCH((k_volume_batch<double, float>), g, dim3(kBlock), s, tab, map);
+    else if (out_f64) GCB_LAUNCH((k_volume_batch<float, double>), g, dim3(kBlock), s, tab, map);
+    else GCB_LAUNCH((k_volume_batch<float, float>), g, dim3(kBlock), s, tab, map);
+}
+
 // ---------------------------------------------------------------- staging (a1)
 // Gather the caller's AoS boundary into the permuted, group-contiguous SoA
 // layout, coordinates scaled by 1/R.
@@ -895,7 +1003,6 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(int64_t count, const do
 }
 
 // ---------------------------------------------------------------- launchers
-#define GCB_LAUNCH(kern, grid, block, stream, ...) hipLaunchKernelGGL(kern, grid, block, 0, stream, __VA_ARGS__)
 
 void launch_stage(hipStream_t s, int64_t nb, const double* xyz, const double* disp, const int32_t* perm,
                   double inv_r, Boundary& bd) {
@@ -916,39 +1023,78 @@ void launch_init_nodes(hipStream_t s, const Boundary& bd, int32_t* init, ArgRec*
     }
 }
 
-static void launch_factor(hipStream_t s, const IterCtx& ic, int grid, int init_t, int g, int nrec) {
+SweepArgs make_sweep_args(const IterCtx& ic, int g) {
+    const Boundary& bd = *ic.bd;
+    SweepArgs A;
+    A.st = ic.st;
+    A.t0 = bd.goff_h[g];
+    A.T = bd.goff_h[g + 1] - A.t0;
+    sweep_layout(A.T, A.lpt, A.tpl);
+    A.px = bd.px; A.py = bd.py; A.pz = bd.pz;
+    A.pdx = bd.pdx; A.pdy = bd.pdy; A.pdz = bd.pdz;
+    A.inS = bd.inS;
+    A.perm = bd.perm;
+    A.sv = view(*ic.sp);
+    A.cap = ic.sp->cap;
+    A.rec = ic.srec;
+    return A;
+}
+
+FactorLArgs make_factor_l_args(const IterCtx& ic, int g, int nrec, int init_t) {
     const Boundary& bd = *ic.bd;
     Support& sp = *ic.sp;
-    GCB_LAUNCH(k_factor_l, dim3(grid), dim3(kBigBlock), s, ic.st, ic.irec, ic.srec, nrec, bd.m, g, init_t, ic.init,
-               bd.pos_of, bd.px, bd.py, bd.pz, bd.pdx, bd.pdy, bd.pdz, view(sp), sp.M, sp.l, ic.Pb, ic.tol_abs,
-               ic.nc_max, sp.cap, ic.log_group, ic.log_node, ic.log_err, ic.log_app, ic.log_cap);
-    GCB_LAUNCH(k_factor_u, dim3(grid), dim3(kBigBlock), s, ic.st, ic.irec, bd.inS, mut(sp), sp.Mc, sp.cap, sp.l, ic.Pb);
+    FactorLArgs A;
+    A.st = ic.st; A.irec = ic.irec; A.srec = ic.srec; A.nrec = nrec; A.m = bd.m; A.g = g; A.init_t = init_t;
+    A.init = ic.init; A.pos_of = bd.pos_of;
+    A.px = bd.px; A.py = bd.py; A.pz = bd.pz; A.pdx = bd.pdx; A.pdy = bd.pdy; A.pdz = bd.pdz;
+    A.sv = view(sp); A.Mr = sp.M; A.l = sp.l; A.Pb = ic.Pb;
+    A.tol_abs = ic.tol_abs; A.nc_max = ic.nc_max; A.cap = sp.cap;
+    A.log_group = ic.log_group; A.log_node = ic.log_node; A.log_err = ic.log_err; A.log_app = ic.log_app;
+    A.log_cap = ic.log_cap;
+    A.active = 1;
+    return A;
+}
+
+FactorUArgs make_factor_u_args(const IterCtx& ic) {
+    const Boundary& bd = *ic.bd;
+    Support& sp = *ic.sp;
+    FactorUArgs A;
+    A.st = ic.st; A.irec = ic.irec; A.inS = bd.inS; A.sm = mut(sp); A.Mc = sp.Mc; A.cap = sp.cap; A.l = sp.l;
+    A.Pb = ic.Pb;
+    A.active = 1;
+    return A;
+}
+
+int sweep_records(const SweepArgs& A) { return A.T > 0 ? sweep_nblocks_dev(A.T, A.lpt, A.tpl) : 0; }
+
+int factor_blocks(int64_t n_ub) { return (int)std::max<int64_t>(1, (n_ub + kRowsL - 1) / kRowsL); }
+
+static void launch_factor(hipStream_t s, const IterCtx& ic, int grid, int init_t, int g, int nrec) {
+    GCB_LAUNCH(k_factor_l, dim3(grid), dim3(kBigBlock), s, make_factor_l_args(ic, g, nrec, init_t));
+    GCB_LAUNCH(k_factor_u, dim3(grid), dim3(kBigBlock), s, make_factor_u_args(ic));
 }
 
 void launch_init_append(hipStream_t s, const IterCtx& ic, int t) { launch_factor(s, ic, 1, t, 0, 0); }
 
 int sweep_blocks(int gmax) {
     int best = 1;
-    for (int T = 1; T <= gmax; T = (T < gmax && T * 2 > gmax) ? gmax : T * 2)
-        best = std::max(best, sweep_nblocks(T));
-    for (int T : {std::min(gmax, 512), std::min(gmax, 1024), std::min(gmax, 2048), std::min(gmax, 8192), gmax})
-        best = std::max(best, sweep_nblocks(T));
+    for (int T : {std::min(gmax, 512), std::min(gmax, 4096), std::min(gmax, 8192), gmax})
+        if (T > 0) best = std::max(best, sweep_nblocks(T));
     return best;
 }
 
 void launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub) {
-    const Boundary& bd = *ic.bd;
-    const int t0 = bd.goff_h[g];
-    const int T = bd.goff_h[g + 1] - t0;
-    const int nrec = sweep_nblocks(T);
-    if (T > 0) {
-        int lpt, tpl;
-        sweep_layout(T, lpt, tpl);
-        GCB_LAUNCH(k_sweep, dim3(nrec), dim3(kBlock), s, ic.st, t0, T, lpt, tpl, bd.px, bd.py, bd.pz, bd.pdx, bd.pdy, bd.pdz,
-                   bd.inS, bd.perm, view(*ic.sp), ic.sp->cap, ic.srec);
-    }
-    const int grid = std::max(1, (n_ub + kRowsL - 1) / kRowsL);
-    launch_factor(s, ic, grid, -1, g, T > 0 ? nrec : 0);
+    const SweepArgs A = make_sweep_args(ic, g);
+    const int nrec = A.T > 0 ? sweep_nblocks(A.T) : 0;
+    if (A.T > 0) GCB_LAUNCH(k_sweep, dim3(nrec), dim3(kBlock), s, A);
+    launch_factor(s, ic, factor_blocks(n_ub), -1, g, nrec);
+}
+
+void launch_iteration_batch(hipStream_t s, const SweepArgs* sweep_tab, const FactorLArgs* fl_tab,
+                            const FactorUArgs* fu_tab, const BlockMap& sweep_map, const BlockMap& factor_map) {
+    GCB_LAUNCH(k_sweep_batch, dim3(sweep_map.off[sweep_map.count]), dim3(kBlock), s, sweep_tab, sweep_map);
+    GCB_LAUNCH(k_factor_l_batch, dim3(factor_map.off[factor_map.count]), dim3(kBigBlock), s, fl_tab, factor_map);
+    GCB_LAUNCH(k_factor_u_batch, dim3(factor_map.off[factor_map.count]), dim3(kBigBlock), s, fu_tab, factor_map);
 }
 
 void launch_transpose_factor(hipStream_t s, const double* Mr, double* Mc, int n, int64_t cap) {

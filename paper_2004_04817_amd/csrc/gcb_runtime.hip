@@ -232,7 +232,27 @@ int64_t n_upper(const gcb_ctx* ctx, int64_t n, int64_t iters) {
     return std::min<int64_t>(ctx->params.nc_max, n + iters);
 }
 
-void run_select(gcb_ctx* ctx, gcb_select_info* info) {
+IterCtx make_ic(gcb_ctx* ctx) {
+    IterCtx ic;
+    ic.st = ctx->state;
+    ic.irec = ctx->irec;
+    ic.srec = ctx->argrec;
+    ic.init = reinterpret_cast<int32_t*>(ctx->argrec + ctx->argrec_cap - 1);
+    ic.bd = &ctx->bd;
+    ic.sp = &ctx->sp;
+    ic.Pb = ctx->Pb;
+    ic.tol_abs = ctx->params.tol_abs;
+    ic.nc_max = ctx->params.nc_max;
+    ic.log_cap = ctx->log_cap;
+    ic.log_group = ctx->log_group;
+    ic.log_node = ctx->log_node;
+    ic.log_err = ctx->log_err;
+    ic.log_app = ctx->log_app;
+    return ic;
+}
+
+// Stage the boundary, allocate, pick and append the three starting nodes.
+void select_begin(gcb_ctx* ctx) {
     check_params(ctx);
     ctx->selected = false;
     stage_boundary(ctx);
@@ -250,21 +270,21 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     }
     if (!ctx->state) dalloc(ctx, ctx->state, 1);
     if (!ctx->irec) dalloc(ctx, ctx->irec, 1);
+    if (!ctx->state_pin) HIPCHK(ctx, hipHostMalloc(reinterpret_cast<void**>(&ctx->state_pin), sizeof(GState)));
+    if (!ctx->ev0) HIPCHK(ctx, hipEventCreate(&ctx->ev0));
+    if (!ctx->ev1) HIPCHK(ctx, hipEventCreate(&ctx->ev1));
     HIPCHK(ctx, hipMemsetAsync(ctx->irec, 0, sizeof(IterRec), ctx->stream));
     if (ctx->log_cap == 0) grow_log(ctx, 0, 65536);
     int32_t* init = reinterpret_cast<int32_t*>(ctx->argrec + ctx->argrec_cap - 1);
     static_assert(sizeof(ArgRec) >= 3 * sizeof(int32_t), "record too small");
-
-    hipEvent_t ev0, ev1;
-    HIPCHK(ctx, hipEventCreate(&ev0));
-    HIPCHK(ctx, hipEventCreate(&ev1));
-    HIPCHK(ctx, hipEventRecord(ev0, ctx->stream));
-
+    HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     GState st{};
     st.k = 3;
     st.init_left = 3;
     st.singular_node = -1;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->state, &st, sizeof(st), hipMemcpyHostToDevice, ctx->stream));
+    *ctx->state_pin = st;
+    ctx->state_h = st;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->state, ctx->state_pin, sizeof(st), hipMemcpyHostToDevice, ctx->stream));
     if (p.use_init) {
         int32_t h[3] = {(int32_t)p.init_idx[0], (int32_t)p.init_idx[1], (int32_t)p.init_idx[2]};
         HIPCHK(ctx, hipMemcpyAsync(init, h, sizeof(h), hipMemcpyHostToDevice, ctx->stream));
@@ -272,50 +292,84 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     } else {
         launch_init_nodes(ctx->stream, bd, init, ctx->argrec);
     }
-    auto make_ic = [&]() {
-        IterCtx ic;
-        ic.st = ctx->state;
-        ic.irec = ctx->irec;
-        ic.srec = ctx->argrec;
-        ic.init = init;
-        ic.bd = &ctx->bd;
-        ic.sp = &ctx->sp;
-        ic.Pb = ctx->Pb;
-        ic.tol_abs = p.tol_abs;
-        ic.nc_max = p.nc_max;
-        ic.log_cap = ctx->log_cap;
-        ic.log_group = ctx->log_group;
-        ic.log_node = ctx->log_node;
-        ic.log_err = ctx->log_err;
-        ic.log_app = ctx->log_app;
-        return ic;
-    };
-    {
-        IterCtx ic = make_ic();
-        for (int t = 0; t < 3; ++t) launch_init_append(ctx->stream, ic, t);
-    }
+    const IterCtx ic = make_ic(ctx);
+    for (int t = 0; t < 3; ++t) launch_init_append(ctx->stream, ic, t);
     HIPCHK(ctx, hipGetLastError());
-    if (!ctx->state_pin) HIPCHK(ctx, hipHostMalloc(reinterpret_cast<void**>(&ctx->state_pin), sizeof(GState)));
+    ctx->k_host = 3;
+    ctx->in_progress = true;
+}
+
+// After the state has been copied to state_pin and the stream synchronised:
+// true while the selection runs; grows the factor and the log so the next
+// `chunk` iterations fit.
+bool select_poll(gcb_ctx* ctx, int chunk) {
+    ctx->state_h = *ctx->state_pin;
+    const GState& h = ctx->state_h;
+    if (h.done == 4) fail(ctx, GCB_E_DEVICE, "internal error: factor capacity exhausted inside a chunk");
+    if (h.done != 0) return false;
+    const gcb_params& p = ctx->params;
+    if (h.n + chunk > ctx->sp.cap && ctx->sp.cap < p.nc_max) {
+        const int64_t cap = std::min<int64_t>(p.nc_max, std::max<int64_t>(2 * ctx->sp.cap, h.n + chunk + 1));
+        grow_support(ctx, cap, h.n);
+    }
+    if (h.log_len + chunk > ctx->log_cap) grow_log(ctx, h.log_len, std::max<int64_t>(2 * ctx->log_cap, h.log_len + chunk));
+    return true;
+}
+
+// Certificate and result of a finished selection.
+void select_end(gcb_ctx* ctx, gcb_select_info* info) {
+    const gcb_params& p = ctx->params;
+    Boundary& bd = ctx->bd;
+    ctx->in_progress = false;
+    HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    const GState& h = ctx->state_h;
+    if (h.done == 3) {
+        ctx->err = "support matrix not numerically SPD when appending node " + std::to_string(h.singular_node);
+        throw Fail{GCB_E_SINGULAR};
+    }
+    gcb_select_info inf{};
+    inf.nc = h.n;
+    inf.iterations = h.log_len;
+    inf.status = h.done == 2 ? GCB_NOT_CONVERGED : GCB_OK;
+    inf.pairs_group = h.pairs_group;
+    inf.pairs_append = h.pairs_append;
+    // FP64 certificate over all boundary nodes
+    if (ctx->red_cap < 2 * (bd.nb / kBlock + 2) + 2) {
+        ctx->red_cap = 2 * (bd.nb / kBlock + 2) + 2;
+        dalloc(ctx, ctx->red, ctx->red_cap);
+    }
+    launch_certify(ctx->stream, bd, ctx->sp, h.n, ctx->red, ctx->red + ctx->red_cap - 2);
+    HIPCHK(ctx, hipGetLastError());
+    double mr[2];
+    HIPCHK(ctx, hipMemcpyAsync(mr, ctx->red + ctx->red_cap - 2, sizeof(mr), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    inf.ms_select = ms;
+    inf.final_max_err = std::sqrt(mr[0]);
+    inf.final_rms_err = std::sqrt(mr[1] / (double)bd.nb);
+    inf.converged = inf.final_max_err <= p.tol_abs;
+    inf.pairs_cert = (uint64_t)bd.nb * (uint64_t)h.n;
+    ctx->info = inf;
+    ctx->selected = true;
+    if (info) *info = inf;
+}
+
+void run_select(gcb_ctx* ctx, gcb_select_info* info) {
+    select_begin(ctx);
+    const gcb_params& p = ctx->params;
     // Every iteration advances k by one, so the host knows the group of each
     // launch.  A chunk of C iterations with C a multiple of m starts at the
     // same phase of k mod m every time and is captured once into a graph.
     const int m = p.m;
     const bool use_graph = g_tuning.use_graph && m <= 256;
     const int chunk = use_graph ? m * ((64 + m - 1) / m) : 64;
-    int64_t k = 3;
     for (;;) {
         HIPCHK(ctx, hipMemcpyAsync(ctx->state_pin, ctx->state, sizeof(GState), hipMemcpyDeviceToHost, ctx->stream));
         sync(ctx);
-        ctx->state_h = *ctx->state_pin;
-        GState& h = ctx->state_h;
-        if (h.done == 4) fail(ctx, GCB_E_DEVICE, "internal error: factor capacity exhausted inside a chunk");
-        if (h.done != 0) break;
-        if (h.n + chunk > ctx->sp.cap && ctx->sp.cap < p.nc_max) {
-            const int64_t cap = std::min<int64_t>(p.nc_max, std::max<int64_t>(2 * ctx->sp.cap, h.n + chunk + 1));
-            grow_support(ctx, cap, h.n);
-        }
-        if (h.log_len + chunk > ctx->log_cap) grow_log(ctx, h.log_len, std::max<int64_t>(2 * ctx->log_cap, h.log_len + chunk));
-        IterCtx ic = make_ic();
+        if (!select_poll(ctx, chunk)) break;
+        const int64_t k = ctx->k_host;
+        const IterCtx ic = make_ic(ctx);
         if (use_graph) {
             int64_t tol_bits;
             std::memcpy(&tol_bits, &p.tol_abs, sizeof(tol_bits));
@@ -339,48 +393,14 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
             HIPCHK(ctx, hipGraphLaunch(ctx->chunk_exec, ctx->stream));
         } else {
             for (int it = 0; it < chunk; ++it) {
-                const int n_ub = (int)n_upper(ctx, h.n, it + 1);
+                const int n_ub = (int)n_upper(ctx, ctx->state_h.n, it + 1);
                 launch_iteration(ctx->stream, ic, (int)((k + it) % m), n_ub);
             }
         }
         HIPCHK(ctx, hipGetLastError());
-        k += chunk;
+        ctx->k_host = k + chunk;
     }
-    HIPCHK(ctx, hipEventRecord(ev1, ctx->stream));
-    HIPCHK(ctx, hipEventSynchronize(ev1));
-    float ms = 0.f;
-    HIPCHK(ctx, hipEventElapsedTime(&ms, ev0, ev1));
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
-    const GState& h = ctx->state_h;
-    if (h.done == 3) {
-        ctx->err = "support matrix not numerically SPD when appending node " + std::to_string(h.singular_node);
-        throw Fail{GCB_E_SINGULAR};
-    }
-    gcb_select_info inf{};
-    inf.nc = h.n;
-    inf.iterations = h.log_len;
-    inf.status = h.done == 2 ? GCB_NOT_CONVERGED : GCB_OK;
-    inf.pairs_group = h.pairs_group;
-    inf.pairs_append = h.pairs_append;
-    inf.ms_select = ms;
-    // FP64 certificate over all boundary nodes
-    if (ctx->red_cap < 2 * (bd.nb / kBlock + 2) + 2) {
-        ctx->red_cap = 2 * (bd.nb / kBlock + 2) + 2;
-        dalloc(ctx, ctx->red, ctx->red_cap);
-    }
-    launch_certify(ctx->stream, bd, ctx->sp, h.n, ctx->red, ctx->red + ctx->red_cap - 2);
-    HIPCHK(ctx, hipGetLastError());
-    double mr[2];
-    HIPCHK(ctx, hipMemcpyAsync(mr, ctx->red + ctx->red_cap - 2, sizeof(mr), hipMemcpyDeviceToHost, ctx->stream));
-    sync(ctx);
-    inf.final_max_err = std::sqrt(mr[0]);
-    inf.final_rms_err = std::sqrt(mr[1] / (double)bd.nb);
-    inf.converged = inf.final_max_err <= p.tol_abs;
-    inf.pairs_cert = (uint64_t)bd.nb * (uint64_t)h.n;
-    ctx->info = inf;
-    ctx->selected = true;
-    if (info) *info = inf;
+    select_end(ctx, info);
 }
 
 template <typename F>
@@ -402,7 +422,269 @@ int guard(gcb_ctx* ctx, F&& f) {
 
 }  // namespace
 
+struct gcb_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    // per-iteration argument tables (device) and their pinned staging
+    void* dtab = nullptr;
+    size_t dtab_cap = 0;
+    void* htab = nullptr;
+    size_t htab_cap = 0;
+};
+
+namespace {
+
+struct BFail {
+    int code;
+};
+
+[[noreturn]] void bfail(gcb_batch* b, int code, const std::string& msg) {
+    b->err = msg;
+    throw BFail{code};
+}
+
+#define BHIPCHK(b, expr)                                                                          \
+    do {                                                                                          \
+        hipError_t _e = (expr);                                                                   \
+        if (_e != hipSuccess) bfail((b), GCB_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+    } while (0)
+
+template <typename F>
+int bguard(gcb_batch* b, F&& f) {
+    if (!b) return GCB_E_INVALID;
+    try {
+        b->err.clear();
+        return f();
+    } catch (const BFail& e) {
+        return e.code;
+    } catch (const Fail& e) {
+        return e.code;   // message in the context
+    } catch (const std::bad_alloc&) {
+        b->err = "host allocation failed";
+        return GCB_E_NOMEM;
+    } catch (...) {
+        b->err = "unexpected internal error";
+        return GCB_E_DEVICE;
+    }
+}
+
+void ensure_tables(gcb_batch* b, size_t bytes) {
+    if (b->dtab_cap < bytes) {
+        if (b->dtab) (void)hipFree(b->dtab);
+        b->dtab = nullptr;
+        b->dtab_cap = 0;
+        BHIPCHK(b, hipMalloc(&b->dtab, bytes));
+        b->dtab_cap = bytes;
+    }
+    if (b->htab_cap < bytes) {
+        if (b->htab) (void)hipHostFree(b->htab);
+        b->htab = nullptr;
+        b->htab_cap = 0;
+        BHIPCHK(b, hipHostMalloc(&b->htab, bytes));
+        b->htab_cap = bytes;
+    }
+}
+
+void attach(gcb_batch* b, gcb_ctx* ctx) {
+    if (!ctx) bfail(b, GCB_E_INVALID, "NULL context");
+    if (ctx->device != b->device) bfail(b, GCB_E_INVALID, "context on another device");
+    if (ctx->stream != b->stream) {
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        ctx->stream = b->stream;
+    }
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int32_t batch_step(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, int32_t iterations, int32_t* running) {
+    if (count < 0 || (count > 0 && !ctxs)) bfail(b, GCB_E_INVALID, "bad context list");
+    if (iterations < 1 || iterations > 4096) bfail(b, GCB_E_INVALID, "iterations must be in [1, 4096]");
+    BHIPCHK(b, hipSetDevice(b->device));
+    for (int32_t i = 0; i < count; ++i) {
+        attach(b, ctxs[i]);
+        if (ctxs[i]->in_progress)
+            HIPCHK(ctxs[i], hipMemcpyAsync(ctxs[i]->state_pin, ctxs[i]->state, sizeof(GState), hipMemcpyDeviceToHost,
+                                           b->stream));
+    }
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    std::vector<gcb_ctx*> run;
+    for (int32_t i = 0; i < count; ++i) {
+        gcb_ctx* c = ctxs[i];
+        bool r = false;
+        if (c->in_progress) r = select_poll(c, iterations);
+        if (running) running[i] = r ? 1 : 0;
+        if (r) run.push_back(c);
+    }
+    const int L = (int)run.size();
+    if (L == 0) return 0;
+    if (L > kMaxBatch) bfail(b, GCB_E_INVALID, "at most 64 running contexts per step");
+    const size_t s_b = align_up(sizeof(SweepArgs) * (size_t)L);
+    const size_t l_b = align_up(sizeof(FactorLArgs) * (size_t)L);
+    const size_t u_b = align_up(sizeof(FactorUArgs) * (size_t)L);
+    const size_t per_it = s_b + l_b + u_b;
+    ensure_tables(b, per_it * (size_t)iterations);
+    BlockMap smap{}, fmap{};
+    smap.count = fmap.count = L;
+    for (int j = 0; j < L; ++j) {
+        smap.off[j + 1] = smap.off[j] + sweep_blocks(run[j]->bd.gmax);
+        fmap.off[j + 1] = fmap.off[j] + factor_blocks(std::min<int64_t>(run[j]->params.nc_max, run[j]->sp.cap));
+    }
+    char* h = static_cast<char*>(b->htab);
+    std::vector<IterCtx> ics;
+    ics.reserve(L);
+    for (int j = 0; j < L; ++j) ics.push_back(make_ic(run[j]));
+    for (int it = 0; it < iterations; ++it) {
+        SweepArgs* sa = reinterpret_cast<SweepArgs*>(h + per_it * it);
+        FactorLArgs* la = reinterpret_cast<FactorLArgs*>(h + per_it * it + s_b);
+        FactorUArgs* ua = reinterpret_cast<FactorUArgs*>(h + per_it * it + s_b + l_b);
+        for (int j = 0; j < L; ++j) {
+            const int g = (int)((run[j]->k_host + it) % run[j]->params.m);
+            sa[j] = make_sweep_args(ics[j], g);
+            la[j] = make_factor_l_args(ics[j], g, sweep_records(sa[j]), -1);
+            ua[j] = make_factor_u_args(ics[j]);
+        }
+    }
+    BHIPCHK(b, hipMemcpyAsync(b->dtab, b->htab, per_it * (size_t)iterations, hipMemcpyHostToDevice, b->stream));
+    char* d = static_cast<char*>(b->dtab);
+    for (int it = 0; it < iterations; ++it) {
+        launch_iteration_batch(b->stream, reinterpret_cast<SweepArgs*>(d + per_it * it),
+                               reinterpret_cast<FactorLArgs*>(d + per_it * it + s_b),
+                               reinterpret_cast<FactorUArgs*>(d + per_it * it + s_b + l_b), smap, fmap);
+    }
+    BHIPCHK(b, hipGetLastError());
+    for (int j = 0; j < L; ++j) run[j]->k_host += iterations;
+    return L;
+}
+
+}  // namespace
+
 extern "C" {
+
+int gcb_batch_create(gcb_batch** out, int device, void* hip_stream) {
+    if (!out) return GCB_E_INVALID;
+    *out = nullptr;
+    gcb_batch* b = new (std::nothrow) gcb_batch();
+    if (!b) return GCB_E_NOMEM;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || device < 0 || device >= n) {
+        g_create_err = e != hipSuccess ? std::string("hipGetDeviceCount: ") + hipGetErrorString(e)
+                                       : "device index out of range";
+        delete b;
+        return e != hipSuccess ? GCB_E_DEVICE : GCB_E_INVALID;
+    }
+    b->device = device;
+    e = hipSetDevice(device);
+    if (e != hipSuccess) {
+        g_create_err = std::string("hipSetDevice: ") + hipGetErrorString(e);
+        delete b;
+        return GCB_E_DEVICE;
+    }
+    b->stream = static_cast<hipStream_t>(hip_stream);   // verbatim: NULL is the null stream
+    *out = b;
+    return GCB_OK;
+}
+
+void gcb_batch_destroy(gcb_batch* b) {
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->dtab) (void)hipFree(b->dtab);
+    if (b->htab) (void)hipHostFree(b->htab);
+    delete b;
+}
+
+const char* gcb_batch_last_error(const gcb_batch* b) { return b ? b->err.c_str() : g_create_err.c_str(); }
+
+int gcb_batch_begin(gcb_batch* b, gcb_ctx* ctx) {
+    return bguard(b, [&] {
+        BHIPCHK(b, hipSetDevice(b->device));
+        attach(b, ctx);
+        return guard(ctx, [&] {
+            select_begin(ctx);
+            return GCB_OK;
+        });
+    });
+}
+
+int32_t gcb_batch_step(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, int32_t iterations, int32_t* running) {
+    int32_t nrun = 0;
+    const int rc = bguard(b, [&] {
+        nrun = batch_step(b, ctxs, count, iterations, running);
+        return GCB_OK;
+    });
+    return rc < 0 ? rc : nrun;
+}
+
+int gcb_batch_end(gcb_batch* b, gcb_ctx* ctx, gcb_select_info* info) {
+    return bguard(b, [&] {
+        BHIPCHK(b, hipSetDevice(b->device));
+        attach(b, ctx);
+        return guard(ctx, [&] {
+            if (!ctx->in_progress) fail(ctx, GCB_E_STATE, "no selection in progress");
+            if (ctx->state_h.done == 0) fail(ctx, GCB_E_STATE, "selection still running");
+            select_end(ctx, info);
+            return ctx->info.status;
+        });
+    });
+}
+
+int gcb_select_batch(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, gcb_select_info* infos) {
+    return bguard(b, [&] {
+        if (count < 1 || !ctxs) bfail(b, GCB_E_INVALID, "need at least one context");
+        int status = GCB_OK;
+        for (int32_t s0 = 0; s0 < count; s0 += kMaxBatch) {   // slices of at most 64 contexts
+            const int32_t sc = std::min<int32_t>(kMaxBatch, count - s0);
+            for (int32_t i = s0; i < s0 + sc; ++i) {
+                const int rc = gcb_batch_begin(b, ctxs[i]);
+                if (rc < 0) return rc;
+            }
+            for (;;) {
+                const int32_t n = gcb_batch_step(b, ctxs + s0, sc, 64, nullptr);
+                if (n < 0) return (int)n;
+                if (n == 0) break;
+            }
+            for (int32_t i = s0; i < s0 + sc; ++i) {
+                const int rc = gcb_batch_end(b, ctxs[i], infos ? &infos[i] : nullptr);
+                if (rc < 0) return rc;
+                if (rc == GCB_NOT_CONVERGED) status = GCB_NOT_CONVERGED;
+            }
+        }
+        return status;
+    });
+}
+
+int gcb_deform_batch(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, const int64_t* nv, const void* const* xyz,
+                     int in_dtype, void* const* out, int out_dtype) {
+    return bguard(b, [&] {
+        if (count < 1 || count > kMaxBatch || !ctxs || !nv || !xyz || !out)
+            bfail(b, GCB_E_INVALID, "bad arguments (1 <= count <= 64, non-NULL arrays)");
+        if ((in_dtype != GCB_F32 && in_dtype != GCB_F64) || (out_dtype != GCB_F32 && out_dtype != GCB_F64))
+            bfail(b, GCB_E_INVALID, "dtype must be GCB_F32 or GCB_F64");
+        BHIPCHK(b, hipSetDevice(b->device));
+        const size_t bytes = align_up(sizeof(VolDesc) * (size_t)count);
+        ensure_tables(b, bytes);
+        BHIPCHK(b, hipStreamSynchronize(b->stream));   // the tables may still be read by earlier launches
+        VolDesc* t = static_cast<VolDesc*>(b->htab);
+        BlockMap map{};
+        map.count = count;
+        for (int32_t i = 0; i < count; ++i) {
+            gcb_ctx* c = ctxs[i];
+            attach(b, c);
+            if (!c->selected) bfail(b, GCB_E_STATE, "context without a finished selection");
+            if (nv[i] < 0 || (nv[i] > 0 && (!xyz[i] || !out[i]))) bfail(b, GCB_E_INVALID, "bad volume arguments");
+            t[i] = VolDesc{xyz[i], out[i], nv[i], view(c->sp), (int)c->info.nc, c->bd.inv_r};
+            map.off[i + 1] = map.off[i] + (int)((nv[i] + kBlock - 1) / kBlock);
+        }
+        if (map.off[count] == 0) return GCB_OK;
+        BHIPCHK(b, hipMemcpyAsync(b->dtab, b->htab, bytes, hipMemcpyHostToDevice, b->stream));
+        launch_volume_batch(b->stream, static_cast<VolDesc*>(b->dtab), map, in_dtype == GCB_F64, out_dtype == GCB_F64);
+        BHIPCHK(b, hipGetLastError());
+        return GCB_OK;
+    });
+}
+
 
 const char* gcb_version(void) { return "gcb-mi355x 0.1 (gfx950, FP64 sweeps, inverse-factor append)"; }
 
@@ -458,6 +740,8 @@ void gcb_destroy(gcb_ctx* ctx) {
     if (ctx->tmp) (void)hipFree(ctx->tmp);
     if (ctx->chunk_exec) (void)hipGraphExecDestroy(ctx->chunk_exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
     if (ctx->state_pin) (void)hipHostFree(ctx->state_pin);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
     delete ctx;
