@@ -39,6 +39,8 @@ def parse():
                     help="volume points in the oracle's timed sample")
     ap.add_argument("--modes", type=int, default=64,
                     help="also time Eq. 6 for this many deformation modes on the wing supports (0: skip)")
+    ap.add_argument("--surfaces", type=int, default=32,
+                    help="also time this many uneven independent surfaces, batched vs one at a time (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, one device-to-device copy of this many MiB (the known-size "
                          "kernel that scales FETCH_SIZE / WRITE_SIZE counter readings)")
@@ -86,6 +88,60 @@ def cpu_baseline(p, nv_sample):
             "sample": f"full greedy (Nb={p.nb}, m={p.m}, Nc={r.nc}, {r.iterations} iterations, {t1 - t0:.2f} s) "
                       f"+ Eq. 6 at {vol.shape[0]} volume points ({t2 - t1:.2f} s)",
             "seconds": t2 - t0}
+
+
+def multi_surface(count, dev):
+    """Uneven independent surfaces (Nb log-uniform in [1e3, 5e4], Nv = 25 Nb), each selected and
+    deformed: one context at a time vs one batch (shared launches)."""
+    import torch
+    import synth
+    import paper_2004_04817_amd as gcb
+    probs = synth.config_multi_surface(count, with_volume=True)
+    vols = [torch.from_numpy(q.volume).to(dev) for q in probs]
+    for q in probs:
+        q.volume = None
+    ctxs = []
+    for q in probs:
+        c = gcb.Context(0)
+        c.set_boundary(torch.from_numpy(q.xyz).to(dev), torch.from_numpy(q.disp).to(dev))
+        c.set_params(q.radius, q.m, q.tol_abs, seed=q.seed)
+        ctxs.append(c)
+    outs = [torch.empty_like(v) for v in vols]
+
+    def one_at_a_time():
+        infos = []
+        for c, v, o in zip(ctxs, vols, outs):
+            infos.append(c.select())
+            c.deform(v, out=o)
+        return infos
+
+    batch = gcb.Batch(0)
+
+    def batched():
+        infos = batch.select(ctxs)
+        batch.deform(ctxs, vols, outs)
+        return infos
+
+    res = {}
+    for name, fn in (("one_at_a_time", one_at_a_time), ("batched", batched)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        pairs = sum(i["pairs_group"] + i["pairs_append"] + v.shape[0] * i["nc"] for i, v in zip(infos, vols))
+        res[name] = {"ms": 1e3 * dt, "pair_evals_per_s": pairs / dt,
+                     "iterations_max": max(i["iterations"] for i in infos),
+                     "iterations_sum": sum(i["iterations"] for i in infos),
+                     "all_converged": all(bool(i["converged"]) for i in infos)}
+    res["speedup"] = res["one_at_a_time"]["ms"] / res["batched"]["ms"]
+    res.update({"surfaces": count, "nb_sum": sum(q.nb for q in probs), "nv_sum": sum(v.shape[0] for v in vols),
+                "precision": "fp64"})
+    batch.close()
+    for c in ctxs:
+        c.close()
+    return res
 
 
 def main():
@@ -198,6 +254,8 @@ def main():
                                      "achieved": flops / (ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
                                      "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}}
         del mout, modes
+    if a.surfaces > 0:
+        rec["multi_surface"] = multi_surface(a.surfaces, dev)
     if not a.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(p, min(a.cpu_sample_volume, nv))
     print(json.dumps(rec), flush=True)

@@ -14,7 +14,8 @@ constexpr int kBlock = 256;          // threads per workgroup of the sweep kerne
 constexpr int kLdsTile = 256;        // supports staged in LDS per pass
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kBigBlock = 1024;      // threads per workgroup of the factor kernels (16 wave64)
-constexpr int kRowsL = kBigBlock / 64;   // rows (columns) of M per factor block, one wave each
+constexpr int kRowsL = kBigBlock / 64;   // rows (columns) of M per factor block and per wave round
+constexpr int kMaxRowsPerWave = 4;       // rounds of kRowsL rows a factor block may hold
 constexpr int kBWindow = 4096;       // phi-vector entries staged in LDS at a time
 constexpr double kSingularTol = 64.0 * 2.220446049250313e-16;  // phi0 - l.l below this: not SPD
 

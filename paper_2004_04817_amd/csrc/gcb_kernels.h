@@ -28,7 +28,7 @@ struct SweepArgs {
     const uint8_t* inS;
     const int32_t* perm;
     SupportView sv;
-    int64_t cap;
+    int64_t nub;      // upper bound of |S| at this iteration (<= capacity): extent of the first staged window
     ArgRec* rec;
 };
 
@@ -107,13 +107,17 @@ struct IterCtx {
 int sweep_blocks(int gmax);
 // Block records a sweep with these arguments writes (0 for an empty group).
 int sweep_records(const SweepArgs& A);
-int factor_blocks(int64_t n_ub);
+int factor_blocks(int64_t n_ub, int rpw = 1);
+void sweep_layout_batch(int T, int& lpt, int& tpl);
 SweepArgs make_sweep_args(const IterCtx& ic, int g);
 FactorLArgs make_factor_l_args(const IterCtx& ic, int g, int nrec, int init_t);
 FactorUArgs make_factor_u_args(const IterCtx& ic);
 void launch_volume_batch(hipStream_t s, const VolDesc* tab, const BlockMap& map, int in_f64, int out_f64);
+// One greedy iteration of every context of a batch: three launches.  rpw
+// (1 or kMaxRowsPerWave) is the rows of M per factor wave; it must match the
+// block maps, and does not change any result.
 void launch_iteration_batch(hipStream_t s, const SweepArgs* sweep_tab, const FactorLArgs* fl_tab,
-                            const FactorUArgs* fu_tab, const BlockMap& sweep_map, const BlockMap& factor_map);
+                            const FactorUArgs* fu_tab, const BlockMap& sweep_map, const BlockMap& factor_map, int rpw);
 void launch_init_append(hipStream_t s, const IterCtx& ic, int t);
 void launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub);
 int multi_padded_r(int rc);

@@ -206,7 +206,10 @@ __device__ __forceinline__ bool better_rec(const ArgRec& a, const ArgRec& b) { r
 
 // Supports staged in LDS per window: all loads of a window are issued at once.
 constexpr int kStage = 1280;
+// batched launches hold many more blocks: a smaller window keeps several blocks per CU
+constexpr int kStageBatch = 256;
 
+template <int STAGE>
 __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
     const GState* __restrict__ st = A.st;
     const int t0 = A.t0, T = A.T, lpt = A.lpt, tpl = A.tpl;
@@ -219,9 +222,9 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
     const uint8_t* __restrict__ inS = A.inS;
     const int32_t* __restrict__ perm = A.perm;
     const SupportView sv = A.sv;
-    const int64_t cap = A.cap;
+    const int64_t nub = A.nub;
     ArgRec* __restrict__ rec = A.rec;
-    __shared__ double ls[6][kStage];
+    __shared__ double ls[6][STAGE];
     __shared__ double red[3][4][kBlock / 64];
     __shared__ double s_e2[kBlock / 64 * 4];
     __shared__ int32_t s_or[kBlock / 64 * 4], s_cnt[kBlock / 64 * 4];
@@ -262,7 +265,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
         cz = pz[t0 + tc];
         corig = perm[t0 + tc];
     }
-    const int w0end = (int)min((int64_t)kStage, cap);
+    const int w0end = (int)min((int64_t)STAGE, nub);
     for (int j = threadIdx.x; j < w0end; j += kBlock) {
         ls[0][j] = sv.sx[j];
         ls[1][j] = sv.sy[j];
@@ -275,8 +278,8 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
     if (s_done) return;
     const int n = s_n;
     double ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0}, az[4] = {0, 0, 0, 0};
-    for (int w0 = 0; w0 < n; w0 += kStage) {
-        const int w1 = min(n, w0 + kStage);
+    for (int w0 = 0; w0 < n; w0 += STAGE) {
+        const int w1 = min(n, w0 + STAGE);
         if (w0 > 0) {
             __syncthreads();
             for (int j = w0 + threadIdx.x; j < w1; j += kBlock) {
@@ -385,7 +388,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) { sweep_body(A, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) { sweep_body<kStage>(A, blockIdx.x); }
 
 // l = M b, one wave per row of M (kRowsL rows per block); b_j = phi(|r_new -
 // s_j| / R) staged in LDS windows.  Block partials Pb[blk] = (b.W over
@@ -393,6 +396,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) { sweep_body(A, b
 // every block reduces the sweep records (nrec of them) to the group maximum
 // and takes the decision; block 0 stores it.  With init_t >= 0 the node is
 // the starting node init[init_t] instead.
+template <int RPW>
 __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bid) {
     GState* __restrict__ st = A.st;
     IterRec* __restrict__ irec = A.irec;
@@ -421,16 +425,18 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
     int8_t* __restrict__ log_app = A.log_app;
     const int64_t log_cap = A.log_cap;
     __shared__ double bw[kBWindow];
-    __shared__ double sl[kRowsL];
+    __shared__ double sl[kRowsL * RPW];
     __shared__ GState s_st;
     __shared__ double s_we2[kBigBlock / 64];
     __shared__ int32_t s_wor[kBigBlock / 64], s_wri[kBigBlock / 64], s_cnt[kBigBlock / 64];
     __shared__ double s_win[6];
     __shared__ int32_t s_winpos;
-    __shared__ int32_t s_app, s_n;
+    __shared__ int32_t s_app;
     __shared__ double s_q[3];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
+    constexpr int rpw = RPW;             // rows of M per wave
+    constexpr int rpb = kRowsL * rpw;    // rows of M per block
     if (threadIdx.x == 0) s_st = *st;
     // each thread keeps the best of its records on (e^2, original index), with its fields
     double be2 = -1.0, bx = 0.0, by = 0.0, bz = 0.0, bdx = 0.0, bdy = 0.0, bdz = 0.0;
@@ -457,7 +463,7 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
     }
     double wsx = 0.0, wsy = 0.0, wsz = 0.0, wwx = 0.0, wwy = 0.0, wwz = 0.0;
     if (wave == 0 && lane < kRowsL) {
-        const int j = min((int)bid * kRowsL + lane, (int)cap - 1);
+        const int j = min((int)bid * rpb + lane, (int)cap - 1);
         wsx = sv.sx[j]; wsy = sv.sy[j]; wsz = sv.sz[j];
         wwx = sv.wx[j]; wwy = sv.wy[j]; wwz = sv.wz[j];
     }
@@ -471,8 +477,8 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
         return;
     }
     const int n = init_t >= 0 ? init_t : sg.n;
-    const int i0 = bid * kRowsL;
-    const int i = i0 + wave;
+    const int i0 = bid * rpb;
+    const int i = i0 + wave;   // first of this wave's rows i, i + kRowsL, ...
     // this wave's row of M, loaded while the decision is taken
     constexpr int kRowPre = 16;
     double mrow[kRowPre];
@@ -487,7 +493,6 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
             const int o = init[init_t];
             const int p = pos_of[o];
             s_app = 1;
-            s_n = init_t;
             s_q[0] = px[p];
             s_q[1] = py[p];
             s_q[2] = pz[p];
@@ -557,7 +562,6 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
             }
             const Decision d = decide_local(sg, n, m, b.e2, tol_abs, nc_max, cap);
             s_app = d.app;
-            s_n = n;
             s_q[0] = b.x;
             s_q[1] = b.y;
             s_q[2] = b.z;
@@ -593,11 +597,13 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
     }
     __syncthreads();
     if (!s_app) return;
-    const int nblk = max(1, (n + kRowsL - 1) / kRowsL);
+    const int nblk = max(1, (n + rpb - 1) / rpb);
     if ((int)bid >= nblk) return;
-    const int i1 = min(n, i0 + kRowsL);
+    const int i1 = min(n, i0 + rpb);
     const double qx = s_q[0], qy = s_q[1], qz = s_q[2];
-    double acc = 0.0;
+    double acc[RPW];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) acc[r] = 0.0;
     for (int w0 = 0; w0 < i1; w0 += kBWindow) {
         const int w1 = min(i1, w0 + kBWindow);
         __syncthreads();
@@ -614,62 +620,86 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
                 bw[j - w0] = wendland_r2(dist2(qx, qy, qz, sv.sx[j], sv.sy[j], sv.sz[j]));
         }
         __syncthreads();
-        if (i < i1) {
-            const int je = min(w1, i + 1);
-            int j = w0 + lane;
-            if (w0 == 0) {
 #pragma unroll
-                for (int u = 0; u < kRowPre; ++u)
-                    if (lane + 64 * u < je) acc = fma(mrow[u], bw[lane + 64 * u], acc);
-                j = lane + 64 * kRowPre;
+        for (int r = 0; r < RPW; ++r) {
+            const int ir = i + kRowsL * r;
+            if (ir < i1) {
+                const double* Mir = Mr + (size_t)ir * (ir + 1) / 2;
+                const int je = min(w1, ir + 1);
+                int j = w0 + lane;
+                double a0 = 0.0, a1 = 0.0;
+                if (w0 == 0) {
+                    // the same summation order for every row, whichever wave and round holds it
+#pragma unroll
+                    for (int u = 0; u < kRowPre; ++u) {
+                        const int jj = lane + 64 * u;
+                        if (jj < je) a0 = fma(r == 0 ? mrow[u] : Mir[jj], bw[jj], a0);
+                    }
+                    j = lane + 64 * kRowPre;
+                }
+                for (; j + 64 < je; j += 128) {
+                    const double m0 = Mir[j], m1 = Mir[j + 64];
+                    a0 = fma(m0, bw[j - w0], a0);
+                    a1 = fma(m1, bw[j + 64 - w0], a1);
+                }
+                if (j < je) a0 = fma(Mir[j], bw[j - w0], a0);
+                acc[r] += a0 + a1;
             }
-            double a1 = 0.0;
-            for (; j + 64 < je; j += 128) {
-                const double m0 = Mi[j], m1 = Mi[j + 64];
-                acc = fma(m0, bw[j - w0], acc);
-                a1 = fma(m1, bw[j + 64 - w0], a1);
-            }
-            if (j < je) acc = fma(Mi[j], bw[j - w0], acc);
-            acc += a1;
         }
     }
-    const double li = wave_sum(acc);
-    if (lane == 0 && i < i1) {
-        l[i] = li;
-        sl[wave] = li;
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+        const int ir = i + kRowsL * r;
+        const double li = wave_sum(acc[r]);
+        if (lane == 0 && ir < i1) {
+            l[ir] = li;
+            sl[kRowsL * r + wave] = li;
+        }
     }
     __syncthreads();
     if (wave == 0) {
-        // this block's share of b.W (columns i0..i1-1) and of l.l (rows i0..i1-1), xor-tree order
-        double fx = 0.0, fy = 0.0, fz = 0.0, ll = 0.0;
-        const int j = i0 + lane;
-        if (lane < kRowsL && j < i1) {
-            const double bj = wendland_r2(dist2(qx, qy, qz, wsx, wsy, wsz));
-            fx = bj * wwx;
-            fy = bj * wwy;
-            fz = bj * wwz;
-            ll = sl[lane] * sl[lane];
-        }
-        fx = wave_sum(fx);
-        fy = wave_sum(fy);
-        fz = wave_sum(fz);
-        ll = wave_sum(ll);
-        if (lane == 0) {
-            Pb[4 * bid + 0] = fx;
-            Pb[4 * bid + 1] = fy;
-            Pb[4 * bid + 2] = fz;
-            Pb[4 * bid + 3] = ll;
+        // shares of b.W and l.l per chunk of kRowsL rows (chunk index i / kRowsL, whatever
+        // the rows per block), each in xor-tree order, so the sums do not depend on rpw
+        for (int r = 0; r < rpw; ++r) {
+            const int c0 = i0 + kRowsL * r;
+            if (r > 0 && c0 >= i1) break;   // chunk 0 is always written (zeros while |S| = 0)
+            double fx = 0.0, fy = 0.0, fz = 0.0, ll = 0.0;
+            const int j = c0 + lane;
+            if (lane < kRowsL && j < i1) {
+                double sx = wsx, sy = wsy, sz = wsz, wx = wwx, wy = wwy, wz = wwz;
+                if (r > 0) {
+                    sx = sv.sx[j]; sy = sv.sy[j]; sz = sv.sz[j];
+                    wx = sv.wx[j]; wy = sv.wy[j]; wz = sv.wz[j];
+                }
+                const double bj = wendland_r2(dist2(qx, qy, qz, sx, sy, sz));
+                fx = bj * wx;
+                fy = bj * wy;
+                fz = bj * wz;
+                ll = sl[kRowsL * r + lane] * sl[kRowsL * r + lane];
+            }
+            fx = wave_sum(fx);
+            fy = wave_sum(fy);
+            fz = wave_sum(fz);
+            ll = wave_sum(ll);
+            if (lane == 0) {
+                const int cb = c0 / kRowsL;
+                Pb[4 * cb + 0] = fx;
+                Pb[4 * cb + 1] = fy;
+                Pb[4 * cb + 2] = fz;
+                Pb[4 * cb + 3] = ll;
+            }
         }
     }
 }
 
-__global__ __launch_bounds__(kBigBlock) void k_factor_l(FactorLArgs A) { factor_l_body(A, blockIdx.x); }
+__global__ __launch_bounds__(kBigBlock) void k_factor_l(FactorLArgs A) { factor_l_body<1>(A, blockIdx.x); }
 
 // u = M^T l, one wave per column j of M read from the column-major copy Mc
 // (column j holds rows j.. at offset j*cap - j(j-1)/2).  Every block first
 // sums the k_factor_l partials in block order to s = 1 - l.l and
 // e = d_new - b.W.  Writes the new row [-u^T/sqrt(s), 1/sqrt(s)] into both
 // copies of M and W <- [W - u e/s; e/s]; block 0 commits the iteration.
+template <int RPW>
 __device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bid) {
     GState* __restrict__ st = A.st;
     const IterRec* __restrict__ irec = A.irec;
@@ -686,7 +716,9 @@ __device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bi
     const IterRec r = *irec;
     // this thread's share of the k_factor_l partials, loaded with the record (masked once n is known)
     double pv[4] = {0.0, 0.0, 0.0, 0.0};
-    const int nbl_cap = (int)((cap + kRowsL - 1) / kRowsL);
+    constexpr int rpw = RPW;             // columns of M per wave
+    constexpr int rpb = kRowsL * rpw;    // columns of M per block (as in k_factor_l)
+    const int nbl_cap = (int)((cap + kRowsL - 1) / kRowsL);   // partials come per chunk of kRowsL rows
     if ((int)threadIdx.x < nbl_cap) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) pv[c] = Pb[4 * threadIdx.x + c];
@@ -694,10 +726,10 @@ __device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bi
     if (!r.app) return;
     const int n = r.n;
     const int ncb = max(1, (n + kRowsL - 1) / kRowsL);
-    if ((int)bid >= ncb) return;
+    if ((int)bid >= max(1, (n + rpb - 1) / rpb)) return;
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    const int j = bid * kRowsL + wave;
+    const int j = bid * rpb + wave;   // first of this wave's columns j, j + kRowsL, ...
     // column j of M and the matching entries of l, loaded before s is known
     constexpr int kColPre = 16;
     double mc[kColPre], lv[kColPre];
@@ -747,24 +779,37 @@ __device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bi
         return;
     }
     const double rs = sh[0], cx = sh[1], cy = sh[2], cz = sh[3];
-    if (j < n) {
-        double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-        for (int u = 0; u < kColPre; ++u) a0 = fma(mc[u], lv[u], a0);
-        int ii = j + lane + 64 * kColPre;
-        for (; ii + 64 < n; ii += 128) {
-            a0 = fma(col[ii - j], l[ii], a0);
-            a1 = fma(col[ii + 64 - j], l[ii + 64], a1);
-        }
-        if (ii < n) a0 = fma(col[ii - j], l[ii], a0);
-        const double u = wave_sum(a0 + a1);
-        if (lane == 0) {
-            const double v = -u * rs;
-            sm.M[(size_t)n * (n + 1) / 2 + j] = v;
-            Mc[(size_t)j * cap - (size_t)j * (j - 1) / 2 + (n - j)] = v;
-            sm.wx[j] = fma(-u, cx, sm.wx[j]);
-            sm.wy[j] = fma(-u, cy, sm.wy[j]);
-            sm.wz[j] = fma(-u, cz, sm.wz[j]);
+    for (int q = 0; q < RPW; ++q) {
+        const int jq = j + kRowsL * q;
+        if (jq < n) {
+            double* cq = Mc + (size_t)jq * cap - (size_t)jq * (jq - 1) / 2;
+            double a0 = 0.0, a1 = 0.0;
+            // the same summation order for every column, whichever wave and round holds it
+#pragma unroll
+            for (int u = 0; u < kColPre; ++u) {
+                if (q == 0) {
+                    a0 = fma(mc[u], lv[u], a0);
+                } else {
+                    const int ii = jq + lane + 64 * u;
+                    if (ii < n) a0 = fma(cq[ii - jq], l[ii], a0);
+                }
+            }
+            int ii = jq + lane + 64 * kColPre;
+            for (; ii + 64 < n; ii += 128) {
+                a0 = fma(cq[ii - jq], l[ii], a0);
+                a1 = fma(cq[ii + 64 - jq], l[ii + 64], a1);
+            }
+            if (ii < n) a0 = fma(cq[ii - jq], l[ii], a0);
+            const double u = wave_sum(a0 + a1);
+            if (lane == 0) {
+                const double v = -u * rs;
+                sm.M[(size_t)n * (n + 1) / 2 + jq] = v;
+                cq[n - jq] = v;
+                sm.wx[jq] = fma(-u, cx, sm.wx[jq]);
+                sm.wy[jq] = fma(-u, cy, sm.wy[jq]);
+                sm.wz[jq] = fma(-u, cz, sm.wz[jq]);
+            }
         }
     }
     if (bid == 0 && threadIdx.x == 0) {
@@ -785,7 +830,7 @@ __device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bi
     }
 }
 
-__global__ __launch_bounds__(kBigBlock) void k_factor_u(FactorUArgs A) { factor_u_body(A, blockIdx.x); }
+__global__ __launch_bounds__(kBigBlock) void k_factor_u(FactorUArgs A) { factor_u_body<1>(A, blockIdx.x); }
 
 // ---------------------------------------------------------------- batched iteration kernels (a10)
 // One launch advances every surface of a batch: block b belongs to surface s
@@ -802,21 +847,23 @@ __global__ __launch_bounds__(kBlock) void k_sweep_batch(const SweepArgs* __restr
     const SweepArgs A = tab[s];
     const int local = blockIdx.x - map.off[s];
     if (A.T <= 0 || local >= sweep_nblocks_dev(A.T, A.lpt, A.tpl)) return;
-    sweep_body(A, local);
+    sweep_body<kStageBatch>(A, local);
 }
 
+template <int RPW>
 __global__ __launch_bounds__(kBigBlock) void k_factor_l_batch(const FactorLArgs* __restrict__ tab, BlockMap map) {
     const int s = batch_surface(map, blockIdx.x);
     const FactorLArgs A = tab[s];
     if (!A.active) return;
-    factor_l_body(A, blockIdx.x - map.off[s]);
+    factor_l_body<RPW>(A, blockIdx.x - map.off[s]);
 }
 
+template <int RPW>
 __global__ __launch_bounds__(kBigBlock) void k_factor_u_batch(const FactorUArgs* __restrict__ tab, BlockMap map) {
     const int s = batch_surface(map, blockIdx.x);
     const FactorUArgs A = tab[s];
     if (!A.active) return;
-    factor_u_body(A, blockIdx.x - map.off[s]);
+    factor_u_body<RPW>(A, blockIdx.x - map.off[s]);
 }
 
 // Column-major copy of the first n rows of the packed row-major factor for
@@ -1035,7 +1082,7 @@ SweepArgs make_sweep_args(const IterCtx& ic, int g) {
     A.inS = bd.inS;
     A.perm = bd.perm;
     A.sv = view(*ic.sp);
-    A.cap = ic.sp->cap;
+    A.nub = ic.sp->cap;
     A.rec = ic.srec;
     return A;
 }
@@ -1067,7 +1114,17 @@ FactorUArgs make_factor_u_args(const IterCtx& ic) {
 
 int sweep_records(const SweepArgs& A) { return A.T > 0 ? sweep_nblocks_dev(A.T, A.lpt, A.tpl) : 0; }
 
-int factor_blocks(int64_t n_ub) { return (int)std::max<int64_t>(1, (n_ub + kRowsL - 1) / kRowsL); }
+int factor_blocks(int64_t n_ub, int rpw) {
+    const int64_t rpb = (int64_t)kRowsL * rpw;
+    return (int)std::max<int64_t>(1, (n_ub + rpb - 1) / rpb);
+}
+
+// Group sweep layout of a batched launch: the batch supplies the parallelism,
+// so blocks hold more targets (fewer blocks, each staging the supports once).
+void sweep_layout_batch(int T, int& lpt, int& tpl) {
+    lpt = 64;
+    tpl = T <= 64 ? 1 : (T <= 512 ? 2 : 4);
+}
 
 static void launch_factor(hipStream_t s, const IterCtx& ic, int grid, int init_t, int g, int nrec) {
     GCB_LAUNCH(k_factor_l, dim3(grid), dim3(kBigBlock), s, make_factor_l_args(ic, g, nrec, init_t));
@@ -1091,10 +1148,17 @@ void launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub) {
 }
 
 void launch_iteration_batch(hipStream_t s, const SweepArgs* sweep_tab, const FactorLArgs* fl_tab,
-                            const FactorUArgs* fu_tab, const BlockMap& sweep_map, const BlockMap& factor_map) {
-    GCB_LAUNCH(k_sweep_batch, dim3(sweep_map.off[sweep_map.count]), dim3(kBlock), s, sweep_tab, sweep_map);
-    GCB_LAUNCH(k_factor_l_batch, dim3(factor_map.off[factor_map.count]), dim3(kBigBlock), s, fl_tab, factor_map);
-    GCB_LAUNCH(k_factor_u_batch, dim3(factor_map.off[factor_map.count]), dim3(kBigBlock), s, fu_tab, factor_map);
+                            const FactorUArgs* fu_tab, const BlockMap& sweep_map, const BlockMap& factor_map, int rpw) {
+    if (sweep_map.off[sweep_map.count] > 0)   // every group of the step may be empty
+        GCB_LAUNCH(k_sweep_batch, dim3(sweep_map.off[sweep_map.count]), dim3(kBlock), s, sweep_tab, sweep_map);
+    const dim3 fg((unsigned)factor_map.off[factor_map.count]);
+    if (rpw == kMaxRowsPerWave) {
+        GCB_LAUNCH(k_factor_l_batch<kMaxRowsPerWave>, fg, dim3(kBigBlock), s, fl_tab, factor_map);
+        GCB_LAUNCH(k_factor_u_batch<kMaxRowsPerWave>, fg, dim3(kBigBlock), s, fu_tab, factor_map);
+    } else {
+        GCB_LAUNCH(k_factor_l_batch<1>, fg, dim3(kBigBlock), s, fl_tab, factor_map);
+        GCB_LAUNCH(k_factor_u_batch<1>, fg, dim3(kBigBlock), s, fu_tab, factor_map);
+    }
 }
 
 void launch_transpose_factor(hipStream_t s, const double* Mr, double* Mc, int n, int64_t cap) {

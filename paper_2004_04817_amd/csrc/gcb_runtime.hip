@@ -524,12 +524,11 @@ int32_t batch_step(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, int32_t it
     const size_t u_b = align_up(sizeof(FactorUArgs) * (size_t)L);
     const size_t per_it = s_b + l_b + u_b;
     ensure_tables(b, per_it * (size_t)iterations);
-    BlockMap smap{}, fmap{};
-    smap.count = fmap.count = L;
-    for (int j = 0; j < L; ++j) {
-        smap.off[j + 1] = smap.off[j] + sweep_blocks(run[j]->bd.gmax);
-        fmap.off[j + 1] = fmap.off[j] + factor_blocks(std::min<int64_t>(run[j]->params.nc_max, run[j]->sp.cap));
-    }
+    // With several running contexts the batch supplies the parallelism: blocks take more
+    // targets (sweep) and more rows of M (factor), so one launch needs fewer block rounds.
+    const bool wide = L >= 4;
+    const int rpw = wide ? kMaxRowsPerWave : 1;
+    std::vector<BlockMap> smaps((size_t)iterations), fmaps((size_t)iterations);
     char* h = static_cast<char*>(b->htab);
     std::vector<IterCtx> ics;
     ics.reserve(L);
@@ -538,11 +537,22 @@ int32_t batch_step(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, int32_t it
         SweepArgs* sa = reinterpret_cast<SweepArgs*>(h + per_it * it);
         FactorLArgs* la = reinterpret_cast<FactorLArgs*>(h + per_it * it + s_b);
         FactorUArgs* ua = reinterpret_cast<FactorUArgs*>(h + per_it * it + s_b + l_b);
+        BlockMap& sm = smaps[it];
+        BlockMap& fm = fmaps[it];
+        sm.count = fm.count = L;
+        sm.off[0] = fm.off[0] = 0;
         for (int j = 0; j < L; ++j) {
-            const int g = (int)((run[j]->k_host + it) % run[j]->params.m);
+            gcb_ctx* c = run[j];
+            const int g = (int)((c->k_host + it) % c->params.m);
+            // at most one append per iteration: |S| <= n_poll + it here
+            const int64_t n_ub = std::min<int64_t>(c->sp.cap, c->state_h.n + it + 1);
             sa[j] = make_sweep_args(ics[j], g);
+            if (wide) sweep_layout_batch(sa[j].T, sa[j].lpt, sa[j].tpl);
+            sa[j].nub = n_ub;
             la[j] = make_factor_l_args(ics[j], g, sweep_records(sa[j]), -1);
             ua[j] = make_factor_u_args(ics[j]);
+            sm.off[j + 1] = sm.off[j] + sweep_records(sa[j]);
+            fm.off[j + 1] = fm.off[j] + factor_blocks(std::min<int64_t>(c->params.nc_max, n_ub), rpw);
         }
     }
     BHIPCHK(b, hipMemcpyAsync(b->dtab, b->htab, per_it * (size_t)iterations, hipMemcpyHostToDevice, b->stream));
@@ -550,7 +560,8 @@ int32_t batch_step(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, int32_t it
     for (int it = 0; it < iterations; ++it) {
         launch_iteration_batch(b->stream, reinterpret_cast<SweepArgs*>(d + per_it * it),
                                reinterpret_cast<FactorLArgs*>(d + per_it * it + s_b),
-                               reinterpret_cast<FactorUArgs*>(d + per_it * it + s_b + l_b), smap, fmap);
+                               reinterpret_cast<FactorUArgs*>(d + per_it * it + s_b + l_b), smaps[it], fmaps[it],
+                               rpw);
     }
     BHIPCHK(b, hipGetLastError());
     for (int j = 0; j < L; ++j) run[j]->k_host += iterations;
