@@ -22,7 +22,8 @@ ORC_OK, ORC_NOT_CONVERGED, ORC_E_INVALID, ORC_E_SINGULAR = 0, 1, -1, -4
 class _Problem(C.Structure):
     _fields_ = [("nb", C.c_int64), ("xyz", C.c_void_p), ("disp", C.c_void_p), ("radius", C.c_double),
                 ("m", C.c_int32), ("seed", C.c_uint64), ("tol_abs", C.c_double), ("nc_max", C.c_int64),
-                ("group_of", C.c_void_p), ("init_idx", C.c_void_p), ("nthreads", C.c_int32)]
+                ("group_of", C.c_void_p), ("init_idx", C.c_void_p), ("nthreads", C.c_int32),
+                ("warm_S", C.c_void_p), ("warm_n", C.c_int64)]
 
 
 class _Info(C.Structure):
@@ -195,16 +196,23 @@ class SelectResult:
     log_appended: np.ndarray
 
 
-def _problem(xyz, disp, radius, m, seed, tol_abs, nc_max, group_of=None, init_idx=None, nthreads=0):
-    keep = [xyz, disp, group_of, init_idx]
+def _problem(xyz, disp, radius, m, seed, tol_abs, nc_max, group_of=None, init_idx=None, nthreads=0, warm_S=None):
+    if warm_S is not None:
+        warm_S = np.ascontiguousarray(warm_S, dtype=np.int64)
+    keep = [xyz, disp, group_of, init_idx, warm_S]
     p = _Problem(xyz.shape[0], _ptr(xyz), _ptr(disp), float(radius), int(m), int(seed) & 0xFFFFFFFFFFFFFFFF,
-                 float(tol_abs), int(nc_max), _ptr(group_of), _ptr(init_idx), int(nthreads))
+                 float(tol_abs), int(nc_max), _ptr(group_of), _ptr(init_idx), int(nthreads),
+                 _ptr(warm_S), 0 if warm_S is None else len(warm_S))
     return p, keep
 
 
 def select(xyz, disp, radius, m, tol_abs, nc_max=None, seed=0, group_of=None, init_idx=None,
-           nthreads: int = 0, log_cap: int | None = None) -> SelectResult:
-    """Algorithm 1 (GCB greedy) in FP64 with the RC solve."""
+           nthreads: int = 0, log_cap: int | None = None, warm_S=None) -> SelectResult:
+    """Algorithm 1 (GCB greedy) in FP64 with the RC solve.
+
+    warm_S: a kept support set (>= 3 distinct nodes, in order) to start from
+    instead of the three starting nodes; the selection ends at once when it
+    already meets E* for these displacements, else the loop runs from k = len(warm_S)."""
     xyz, disp = _f64(xyz), _f64(disp)
     nb = xyz.shape[0]
     nc_max = nb if nc_max is None else int(nc_max)
@@ -212,7 +220,7 @@ def select(xyz, disp, radius, m, tol_abs, nc_max=None, seed=0, group_of=None, in
         group_of = np.ascontiguousarray(group_of, dtype=np.int32)
     if init_idx is not None:
         init_idx = np.ascontiguousarray(init_idx, dtype=np.int64)
-    p, keep = _problem(xyz, disp, radius, m, seed, tol_abs, nc_max, group_of, init_idx, nthreads)
+    p, keep = _problem(xyz, disp, radius, m, seed, tol_abs, nc_max, group_of, init_idx, nthreads, warm_S)
     if log_cap is None:
         log_cap = (nc_max + 1) * int(m) + 8
     lg = np.empty(log_cap, dtype=np.int32)
@@ -233,7 +241,7 @@ def select(xyz, disp, radius, m, tol_abs, nc_max=None, seed=0, group_of=None, in
 
 
 def validate(xyz, disp, radius, m, tol_abs, S_init, group, node, appended, tau, nc_max=None, seed=0,
-             group_of=None, init_idx=None, nthreads: int = 0):
+             group_of=None, init_idx=None, nthreads: int = 0, warm_S=None):
     """Follow-mode replay of a foreign selection; returns (first_bad or -1, reason, max_gap)."""
     xyz, disp = _f64(xyz), _f64(disp)
     nb = xyz.shape[0]
@@ -242,7 +250,7 @@ def validate(xyz, disp, radius, m, tol_abs, S_init, group, node, appended, tau, 
         group_of = np.ascontiguousarray(group_of, dtype=np.int32)
     if init_idx is not None:
         init_idx = np.ascontiguousarray(init_idx, dtype=np.int64)
-    p, keep = _problem(xyz, disp, radius, m, seed, tol_abs, nc_max, group_of, init_idx, nthreads)
+    p, keep = _problem(xyz, disp, radius, m, seed, tol_abs, nc_max, group_of, init_idx, nthreads, warm_S)
     S_init = np.ascontiguousarray(S_init[:3], dtype=np.int64)
     group = np.ascontiguousarray(group, dtype=np.int32)
     node = np.ascontiguousarray(node, dtype=np.int64)

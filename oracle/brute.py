@@ -44,16 +44,26 @@ def start_nodes(xyz: np.ndarray, disp: np.ndarray) -> list[int]:
     return [n0, n1, n2]
 
 
-def gcb_brute(xyz, disp, radius, group_of, m, tol_abs, nc_max=None, init=None):
+def gcb_brute(xyz, disp, radius, group_of, m, tol_abs, nc_max=None, init=None, warm=None):
     """Algorithm 1 by brute force.  Returns (S, log) with log entries
-    (k, group, node, E, appended)."""
+    (k, group, node, E, appended).  warm: a kept support set to start from
+    (no iteration if it already meets tol_abs at every node, else k starts
+    at len(warm))."""
     xyz = np.asarray(xyz, np.float64)
     disp = np.asarray(disp, np.float64)
     nb = xyz.shape[0]
     nc_max = nb if nc_max is None else nc_max
-    S = list(start_nodes(xyz, disp) if init is None else init)
     log = []
-    k, quiet = 3, 0
+    if warm is not None:
+        S = [int(j) for j in warm]
+        W = solve_weights(xyz[S], disp[S], radius)
+        F = rbf_matrix(xyz, xyz[S], radius) @ W
+        if np.sqrt(((F - disp) ** 2).sum(axis=1)).max() <= tol_abs:
+            return S, log
+        k, quiet = len(S), 0
+    else:
+        S = list(start_nodes(xyz, disp) if init is None else init)
+        k, quiet = 3, 0
     while True:
         g = k % m
         W = solve_weights(xyz[S], disp[S], radius)

@@ -229,6 +229,18 @@ static int validate_problem(const orc_problem *p) {
     if (p->group_of)
         for (int64_t j = 0; j < p->nb; ++j)
             if (p->group_of[j] < 0 || p->group_of[j] >= p->m) return 0;
+    if (p->warm_n != 0) {
+        if (!p->warm_S || p->warm_n < 3 || p->warm_n > p->nc_max) return 0;
+        char *seen = (char *)calloc((size_t)p->nb, 1);
+        int ok = 1;
+        for (int64_t t = 0; t < p->warm_n && ok; ++t) {
+            int64_t j = p->warm_S[t];
+            if (j < 0 || j >= p->nb || seen[j]) ok = 0;
+            else seen[j] = 1;
+        }
+        free(seen);
+        if (!ok) return 0;
+    }
     if (p->init_idx) {
         for (int t = 0; t < 3; ++t)
             if (p->init_idx[t] < 0 || p->init_idx[t] >= p->nb) return 0;
@@ -351,6 +363,16 @@ static int start_support(orc_state *st) {
     return ORC_OK;
 }
 
+/* Warm start: the kept support set in its order, factor and W for the current displacements. */
+static int warm_support(orc_state *st) {
+    const orc_problem *p = st->p;
+    for (int64_t t = 0; t < p->warm_n; ++t) {
+        int rc = state_append(st, p->warm_S[t]);
+        if (rc != ORC_OK) return rc;
+    }
+    return ORC_OK;
+}
+
 static void certificate(orc_state *st, orc_info *info) {
     const orc_problem *p = st->p;
     double *F = (double *)malloc(sizeof(double) * 3 * (size_t)p->nb);
@@ -379,15 +401,28 @@ int orc_select(const orc_problem *p, int64_t *S_out, double *W_out, orc_log *log
     orc_state st;
     state_init(&st, p);
     double t0 = now_s();
-    int rc = start_support(&st);
+    int rc = p->warm_n >= 3 ? warm_support(&st) : start_support(&st);
     info->t_solve += now_s() - t0;
     if (rc != ORC_OK) {
         info->status = rc;
         state_free(&st);
         return rc;
     }
-    int64_t k = 3, quiet = 0;
+    const int64_t k0 = p->warm_n >= 3 ? p->warm_n : 3;
+    int64_t k = k0, quiet = 0;
     int status = ORC_OK;
+    if (p->warm_n >= 3) {
+        /* the kept support set may already meet E* for the new displacements */
+        certificate(&st, info);
+        if (info->converged) {
+            info->nc = st.nS;
+            info->status = ORC_OK;
+            if (S_out) memcpy(S_out, st.S, sizeof(int64_t) * (size_t)st.nS);
+            if (W_out) memcpy(W_out, st.W, sizeof(double) * 3 * (size_t)st.nS);
+            state_free(&st);
+            return ORC_OK;
+        }
+    }
     for (;;) {
         int32_t g = (int32_t)(k % p->m);
         int64_t gsize = st.goff[g + 1] - st.goff[g];
@@ -418,7 +453,7 @@ int orc_select(const orc_problem *p, int64_t *S_out, double *W_out, orc_log *log
         } else {
             quiet++;
         }
-        int64_t it = k - 3;
+        int64_t it = k - k0;
         if (log && it < log->cap) {
             if (log->group) log->group[it] = g;
             if (log->node) log->node[it] = n;
@@ -429,7 +464,7 @@ int orc_select(const orc_problem *p, int64_t *S_out, double *W_out, orc_log *log
         if (stop) break;
         if (quiet >= p->m) break;
     }
-    info->iterations = k - 3;
+    info->iterations = k - k0;
     info->nc = st.nS;
     if (status >= 0) certificate(&st, info);
     info->status = status;
@@ -466,18 +501,41 @@ int64_t orc_validate(const orc_problem *p, const int64_t S_init[3], int64_t n_it
     if (!validate_problem(p)) { if (reason) *reason = 1; return 0; }
     orc_state st;
     state_init(&st, p);
-    int64_t init[3];
-    orc_initial_nodes(p->nb, p->xyz, p->disp, init);
-    if (p->init_idx) { init[0] = p->init_idx[0]; init[1] = p->init_idx[1]; init[2] = p->init_idx[2]; }
-    if (S_init[0] != init[0] || S_init[1] != init[1] || S_init[2] != init[2]) {
-        if (reason) *reason = 2;
-        state_free(&st);
-        return 0;
+    int64_t k0 = 3;
+    if (p->warm_n >= 3) {
+        /* warm start: the foreign run keeps warm_S; it may skip the loop only when the
+         * kept set already meets E* (within tau), and must run it otherwise */
+        k0 = p->warm_n;
+        if (warm_support(&st) != ORC_OK) { if (reason) *reason = 5; state_free(&st); return 0; }
+        orc_info ci;
+        memset(&ci, 0, sizeof(ci));
+        certificate(&st, &ci);
+        if ((n_iter == 0 && !(ci.final_max_err <= p->tol_abs + tau)) ||
+            (n_iter > 0 && !(ci.final_max_err > p->tol_abs - tau))) {
+            if (reason) *reason = 6;
+            state_free(&st);
+            return 0;
+        }
+        if (n_iter == 0) {
+            if (reason) *reason = 0;
+            if (max_gap) *max_gap = 0.0;
+            state_free(&st);
+            return -1;
+        }
+    } else {
+        int64_t init[3];
+        orc_initial_nodes(p->nb, p->xyz, p->disp, init);
+        if (p->init_idx) { init[0] = p->init_idx[0]; init[1] = p->init_idx[1]; init[2] = p->init_idx[2]; }
+        if (S_init[0] != init[0] || S_init[1] != init[1] || S_init[2] != init[2]) {
+            if (reason) *reason = 2;
+            state_free(&st);
+            return 0;
+        }
+        if (start_support(&st) != ORC_OK) { if (reason) *reason = 5; state_free(&st); return 0; }
     }
-    if (start_support(&st) != ORC_OK) { if (reason) *reason = 5; state_free(&st); return 0; }
     int64_t quiet = 0;
     for (int64_t it = 0; it < n_iter; ++it) {
-        int64_t k = it + 3;
+        int64_t k = it + k0;
         int32_t g = (int32_t)(k % p->m);
         if (group[it] != g) { bad = it; r = 1; break; }
         group_errors(&st, g, p->nthreads);

@@ -70,11 +70,19 @@ typedef struct {
     const int32_t *group_of;  /* optional explicit partition (NULL: seeded) */
     const int64_t *init_idx;  /* optional 3 starting nodes (NULL: farthest rule) */
     int32_t nthreads;         /* OpenMP threads for the sweeps (<= 0: runtime default) */
+    /* Warm start (an extension of Algorithm 1 for a mesh whose support set is
+     * kept while its displacements change): when warm_n >= 3, S starts as
+     * warm_S[0..warm_n) (distinct node indices, in that order), the factor and
+     * W are built over it for the current displacements, and if the all-node
+     * error is already <= E* the selection ends with no iteration; otherwise
+     * the loop of Algorithm 1 runs from k = warm_n.  init_idx is ignored. */
+    const int64_t *warm_S;
+    int64_t warm_n;
 } orc_problem;
 
 typedef struct {
     int64_t nc;               /* |S| */
-    int64_t iterations;       /* loop iterations k = 3, 4, ... that ran */
+    int64_t iterations;       /* loop iterations k = 3, 4, ... (k = warm_n, ... for a warm start) that ran */
     int32_t status;           /* ORC_OK, ORC_NOT_CONVERGED, ORC_E_* */
     int32_t converged;        /* final all-node max error <= E* */
     double final_max_err;     /* certificate: max_j |F(r_j) - d_j| over all nb nodes */
@@ -114,7 +122,9 @@ int orc_solve_on_support(int64_t nb, const double *xyz, const int64_t *S, int64_
  * choice afterwards: the group is k mod m; an appended node lies in G_i \ S,
  * its error is >= E_max - tau and > E* - tau; a skipped iteration has
  * E_max <= E* + tau (or |S| = nc_max).  The foreign start must equal
- * S_init.  Returns -1 when every step is valid, else the first bad
+ * S_init (with a warm start, S_init is ignored: the run starts from warm_S,
+ * and it has no iteration only if the kept set meets E* within tau, or
+ * reason 6).  Returns -1 when every step is valid, else the first bad
  * iteration index; *reason gets a code (1 group, 2 node outside group or in
  * S, 3 not within tau of the max, 4 wrong append decision, 5 singular,
  * 6 bad termination).  *max_gap gets the largest E_max - e(chosen). */

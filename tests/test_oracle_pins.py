@@ -340,3 +340,53 @@ def test_solve_on_support_matches_library_solve():
     W = oracle.solve_on_support(p.xyz, S, p.radius, D)
     Wr = np.linalg.solve(brute.rbf_matrix(p.xyz[S], p.xyz[S], p.radius), D[S])
     assert np.abs(W - Wr).max() < 1e-10 * np.abs(Wr).max()
+
+
+def test_warm_start_from_the_starting_nodes_is_algorithm1():
+    """A warm start from the three starting nodes fails the certificate and then
+    runs the loop from k = 3: exactly Algorithm 1."""
+    p = synth.config_small_ellipsoid(with_volume=False)
+    r = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed)
+    w = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed, warm_S=r.S[:3])
+    assert np.array_equal(w.S, r.S) and np.array_equal(w.W, r.W)
+    assert w.iterations == r.iterations
+    assert np.array_equal(w.log_node, r.log_node) and np.array_equal(w.log_group, r.log_group)
+
+
+@pytest.mark.parametrize("nb,m", [(13, 1), (16, 2), (40, 3), (70, 3)])
+def test_warm_start_brute_force(nb, m):
+    """Kept support set, new displacement field: brute force (dense solves) from the same set."""
+    p = synth.tiny_problem(nb=nb, seed=nb + 5, m=m)
+    tol = 0.02 * p.max_disp
+    r = oracle.select(p.xyz, p.disp, p.radius, m, tol, seed=p.seed)
+    g = oracle.partition(p.nb, m, p.seed)
+    rot = np.array([[0.0, 1.0, 0.0], [0.0, 0.0, 1.0], [1.0, 0.0, 0.0]])
+    for disp2, expect_iters in ((p.disp, False), (1.7 * p.disp @ rot + 0.01, True)):
+        w = oracle.select(p.xyz, disp2, p.radius, m, tol, seed=p.seed, warm_S=r.S)
+        Sb, logb = brute.gcb_brute(p.xyz, disp2, p.radius, g, m, tol, warm=r.S)
+        assert list(w.S) == Sb
+        assert w.iterations == len(logb)
+        assert [e[2] for e in logb] == list(w.log_node)
+        assert [e[1] for e in logb] == list(w.log_group)
+        if not expect_iters:
+            assert w.iterations == 0 and w.converged
+        # the weights interpolate the new field at every support node
+        F = oracle.interpolate(p.xyz[w.S], w.W, p.radius, p.xyz[w.S])
+        assert np.abs(F - disp2[w.S]).max() <= 1e-9 * np.abs(disp2).max()
+
+
+def test_warm_start_validation_and_replay():
+    p = synth.tiny_problem(nb=40, seed=3, m=3)
+    tol = 0.02 * p.max_disp
+    r = oracle.select(p.xyz, p.disp, p.radius, 3, tol, seed=p.seed)
+    bad = oracle.select(p.xyz, p.disp, p.radius, 3, tol, seed=p.seed, warm_S=[r.S[0], r.S[1], r.S[0]])
+    assert bad.status == oracle.ORC_E_INVALID
+    d2 = 1.5 * p.disp[:, ::-1].copy()
+    w = oracle.select(p.xyz, d2, p.radius, 3, tol, seed=p.seed, warm_S=r.S)
+    assert w.iterations > 0
+    ok = oracle.validate(p.xyz, d2, p.radius, 3, tol, r.S, w.log_group, w.log_node, w.log_appended, 1e-12,
+                         seed=p.seed, warm_S=r.S)
+    assert ok[0] == -1
+    # claiming that the kept set already meets E* is rejected (reason 6)
+    none = oracle.validate(p.xyz, d2, p.radius, 3, tol, r.S, [], [], [], 1e-12, seed=p.seed, warm_S=r.S)
+    assert none[0] == 0 and none[1] == 6
