@@ -64,6 +64,10 @@ typedef struct {
     int32_t precision;   /* enum gcb_precision */
     int32_t use_init;    /* 1: start from init_idx; 0: farthest-point rule */
     int64_t init_idx[3]; /* three distinct boundary indices when use_init = 1 */
+    int32_t warm_start;  /* 1: start from the support set of the context's last finished selection
+                          * (an extension of Algorithm 1 for a mesh whose boundary stays while its
+                          * displacements change, see gcb_select); 0: from three starting nodes */
+    int32_t reserved;    /* 0 */
 } gcb_params;
 
 typedef struct {
@@ -123,7 +127,15 @@ int gcb_set_groups(gcb_ctx *ctx, const int32_t *group_of, int mem);
  * factored in FP64 and extended by one row per appended node (the recurrence
  * idea of Section 1), here as the inverse factor M = L^-1.  A final FP64
  * sweep over all nb nodes fills final_max_err / final_rms_err.  info may be
- * NULL.  Returns GCB_OK, GCB_NOT_CONVERGED or an error. */
+ * NULL.  Returns GCB_OK, GCB_NOT_CONVERGED or an error.
+ *
+ * Warm start (params.warm_start = 1): the support set S0 and its factor
+ * from the last finished selection stay (gcb_set_displacement keeps them;
+ * gcb_set_boundary and gcb_set_groups drop them, and radius, m, seed must be
+ * unchanged, else GCB_E_STATE).  The weights are recomputed for the current
+ * displacements as W = M^T (M Delta_S0); if the FP64 all-node error is then
+ * <= E* the selection ends with no iteration, otherwise the loop above runs
+ * from k = |S0|.  nc_max must be >= |S0|. */
 int gcb_select(gcb_ctx *ctx, gcb_select_info *info);
 
 /* Selected support nodes in selection order (original boundary indices,

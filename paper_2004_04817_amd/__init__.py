@@ -42,7 +42,7 @@ class GcbError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("radius", C.c_double), ("m", C.c_int32), ("seed", C.c_uint64), ("tol_abs", C.c_double),
                 ("nc_max", C.c_int64), ("precision", C.c_int32), ("use_init", C.c_int32),
-                ("init_idx", C.c_int64 * 3)]
+                ("init_idx", C.c_int64 * 3), ("warm_start", C.c_int32), ("reserved", C.c_int32)]
 
 
 class SelectInfo(C.Structure):
@@ -219,7 +219,9 @@ class Context:
         self._check(lib().gcb_set_displacement(self._h, pd, md))
 
     def set_params(self, radius: float, m: int, tol_abs: float, nc_max: int | None = None, seed: int = 0,
-                   precision: int = GCB_PREC_FP64, init_idx=None):
+                   precision: int = GCB_PREC_FP64, init_idx=None, warm_start: bool = False):
+        """warm_start: start from the support set of the last finished selection (same
+        boundary, radius, m and seed; new displacements via set_displacement)."""
         p = Params()
         p.radius = float(radius)
         p.m = int(m)
@@ -231,6 +233,7 @@ class Context:
         if init_idx is not None:
             for t in range(3):
                 p.init_idx[t] = int(init_idx[t])
+        p.warm_start = 1 if warm_start else 0
         self._check(lib().gcb_set_params(self._h, C.byref(p)))
 
     def set_groups(self, group_of):

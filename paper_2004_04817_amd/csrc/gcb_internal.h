@@ -139,6 +139,12 @@ struct gcb_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // selection start / end
     int64_t k_host = 3;                // the next iteration's k
     bool in_progress = false;          // a selection started by a batch and not yet finished
+    // kept support set for a warm start (valid after a finished selection on this boundary)
+    bool warm_ok = false;
+    double warm_radius = 0.0;
+    int32_t warm_m = 0;
+    uint64_t warm_seed = 0;
+    int64_t warm_n = 0;
     // scratch for certificate / volume
     double *red = nullptr;
     int64_t red_cap = 0;

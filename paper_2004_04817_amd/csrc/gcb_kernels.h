@@ -121,6 +121,11 @@ void launch_iteration_batch(hipStream_t s, const SweepArgs* sweep_tab, const Fac
 void launch_init_append(hipStream_t s, const IterCtx& ic, int t);
 void launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub);
 int multi_padded_r(int rc);
+// Weights of the kept support set for the displacements disp (nb, 3):
+// W = M^T (M Delta_S) into sp.wx/wy/wz.  Buffers hold n * multi_padded_r(3) doubles each.
+bool launch_support_weights(hipStream_t s, Support& sp, int n, const double* disp, double* Dbuf, double* Ybuf,
+                            double* Wbuf);
+void launch_mark_support(hipStream_t s, const Boundary& bd, const Support& sp, int n);
 bool launch_deform_multi(hipStream_t s, const Support& sp, int n, int rc, const double* modes_dev, double* Dbuf,
                          double* Ybuf, double* Wbuf, int64_t nv, const void* xyz, int in_f64, double inv_r, void* out,
                          int out_f64);

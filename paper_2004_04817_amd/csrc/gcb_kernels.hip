@@ -1049,7 +1049,20 @@ __global__ __launch_bounds__(kBlock) void k_check_finite(int64_t count, const do
     if (bad) flag[0] = 1;
 }
 
+// Nodes of a kept support set are in S again after the boundary is re-staged.
+__global__ __launch_bounds__(kBlock) void k_mark_support(int n, const int32_t* __restrict__ orig,
+                                                         const int32_t* __restrict__ pos_of, uint8_t* __restrict__ inS) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j < n) inS[pos_of[orig[j]]] = 1;
+}
+
 // ---------------------------------------------------------------- launchers
+
+void launch_mark_support(hipStream_t s, const Boundary& bd, const Support& sp, int n) {
+    if (n <= 0) return;
+    GCB_LAUNCH(k_mark_support, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), s, n, sp.orig, bd.pos_of,
+               bd.inS);
+}
 
 void launch_stage(hipStream_t s, int64_t nb, const double* xyz, const double* disp, const int32_t* perm,
                   double inv_r, Boundary& bd) {

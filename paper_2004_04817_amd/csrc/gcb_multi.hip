@@ -123,6 +123,16 @@ __global__ __launch_bounds__(kMWaves * 64) void k_volume_multi(int64_t nv, const
 
 int multi_padded_r(int rc) { return (rc + 15) / 16 * 16; }
 
+__global__ __launch_bounds__(kBlock) void k_scatter_w(int n, int R, const double* __restrict__ W,
+                                                      double* __restrict__ wx, double* __restrict__ wy,
+                                                      double* __restrict__ wz) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    wx[j] = W[(size_t)j * R];
+    wy[j] = W[(size_t)j * R + 1];
+    wz[j] = W[(size_t)j * R + 2];
+}
+
 bool launch_deform_multi(hipStream_t s, const Support& sp, int n, int rc, const double* modes_dev, double* Dbuf,
                          double* Ybuf, double* Wbuf, int64_t nv, const void* xyz, int in_f64, double inv_r, void* out,
                          int out_f64) {
@@ -148,6 +158,14 @@ bool launch_deform_multi(hipStream_t s, const Support& sp, int n, int rc, const 
     else
         hipLaunchKernelGGL((k_volume_multi<float, float>), dim3(gv), dim3(kMWaves * 64), 0, s, nv,
                            (const float*)xyz, inv_r, n, sp.sx, sp.sy, sp.sz, Wbuf, R, rc, (float*)out);
+    return true;
+}
+
+bool launch_support_weights(hipStream_t s, Support& sp, int n, const double* disp, double* Dbuf, double* Ybuf,
+                            double* Wbuf) {
+    if (!launch_deform_multi(s, sp, n, 3, disp, Dbuf, Ybuf, Wbuf, 0, nullptr, 1, 0.0, nullptr, 1)) return false;
+    hipLaunchKernelGGL(k_scatter_w, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n,
+                       multi_padded_r(3), Wbuf, sp.wx, sp.wy, sp.wz);
     return true;
 }
 

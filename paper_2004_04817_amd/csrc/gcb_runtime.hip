@@ -251,10 +251,75 @@ IterCtx make_ic(gcb_ctx* ctx) {
     return ic;
 }
 
+void ensure_red(gcb_ctx* ctx) {
+    const int64_t need = 2 * (ctx->bd.nb / kBlock + 2) + 2;
+    if (ctx->red_cap < need) {
+        ctx->red_cap = need;
+        dalloc(ctx, ctx->red, ctx->red_cap);
+    }
+}
+
+void ensure_tmp(gcb_ctx* ctx, size_t need) {
+    if (ctx->tmp_cap < need) {
+        if (ctx->tmp) (void)hipFree(ctx->tmp);
+        ctx->tmp = nullptr;
+        ctx->tmp_cap = 0;
+        HIPCHK(ctx, hipMalloc(&ctx->tmp, need));
+        ctx->tmp_cap = need;
+    }
+}
+
+// Warm start: keep S0 and its factor, re-stage the boundary with the current
+// displacements, W = M^T (M Delta_S0), and end at once if the FP64 all-node
+// error already meets E*; else the loop continues from k = |S0|.
+void warm_begin(gcb_ctx* ctx) {
+    check_params(ctx);
+    const gcb_params& p = ctx->params;
+    if (!ctx->warm_ok) fail(ctx, GCB_E_STATE, "a warm start needs a finished selection on this boundary");
+    if (p.m != ctx->warm_m || p.seed != ctx->warm_seed || p.radius != ctx->warm_radius)
+        fail(ctx, GCB_E_STATE, "a warm start needs the radius, m and seed of the kept selection");
+    const int64_t n = ctx->warm_n;
+    if (p.nc_max < n) fail(ctx, GCB_E_INVALID, "nc_max is below the kept support count");
+    ctx->selected = false;
+    ctx->warm_ok = false;   // until this selection finishes
+    stage_boundary(ctx);    // the same partition; the new displacements; S cleared
+    Boundary& bd = ctx->bd;
+    launch_mark_support(ctx->stream, bd, ctx->sp, (int)n);
+    HIPCHK(ctx, hipMemsetAsync(ctx->irec, 0, sizeof(IterRec), ctx->stream));
+    HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    const int R = multi_padded_r(3);
+    ensure_tmp(ctx, sizeof(double) * 3 * (size_t)n * R + 256);
+    double* D = static_cast<double*>(ctx->tmp);
+    if (!launch_support_weights(ctx->stream, ctx->sp, (int)n, bd.disp0, D, D + (size_t)n * R, D + 2 * (size_t)n * R))
+        fail(ctx, GCB_E_DEVICE, "internal error: weight recomputation rejected");
+    ensure_red(ctx);
+    launch_certify(ctx->stream, bd, ctx->sp, (int)n, ctx->red, ctx->red + ctx->red_cap - 2);
+    HIPCHK(ctx, hipGetLastError());
+    double mr[2];
+    HIPCHK(ctx, hipMemcpyAsync(mr, ctx->red + ctx->red_cap - 2, sizeof(mr), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    GState st{};
+    st.k = n;
+    st.n = (int32_t)n;
+    st.singular_node = -1;
+    st.done = std::sqrt(mr[0]) <= p.tol_abs ? 1 : 0;
+    *ctx->state_pin = st;
+    ctx->state_h = st;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->state, ctx->state_pin, sizeof(st), hipMemcpyHostToDevice, ctx->stream));
+    sync(ctx);   // the pinned state is read back later
+    ctx->k_host = n;
+    ctx->in_progress = true;
+}
+
 // Stage the boundary, allocate, pick and append the three starting nodes.
 void select_begin(gcb_ctx* ctx) {
+    if (ctx->params.warm_start) {
+        warm_begin(ctx);
+        return;
+    }
     check_params(ctx);
     ctx->selected = false;
+    ctx->warm_ok = false;   // the support set is rebuilt from three nodes
     stage_boundary(ctx);
     const gcb_params& p = ctx->params;
     Boundary& bd = ctx->bd;
@@ -334,10 +399,7 @@ void select_end(gcb_ctx* ctx, gcb_select_info* info) {
     inf.pairs_group = h.pairs_group;
     inf.pairs_append = h.pairs_append;
     // FP64 certificate over all boundary nodes
-    if (ctx->red_cap < 2 * (bd.nb / kBlock + 2) + 2) {
-        ctx->red_cap = 2 * (bd.nb / kBlock + 2) + 2;
-        dalloc(ctx, ctx->red, ctx->red_cap);
-    }
+    ensure_red(ctx);
     launch_certify(ctx->stream, bd, ctx->sp, h.n, ctx->red, ctx->red + ctx->red_cap - 2);
     HIPCHK(ctx, hipGetLastError());
     double mr[2];
@@ -352,6 +414,11 @@ void select_end(gcb_ctx* ctx, gcb_select_info* info) {
     inf.pairs_cert = (uint64_t)bd.nb * (uint64_t)h.n;
     ctx->info = inf;
     ctx->selected = true;
+    ctx->warm_ok = true;
+    ctx->warm_radius = p.radius;
+    ctx->warm_m = p.m;
+    ctx->warm_seed = p.seed;
+    ctx->warm_n = h.n;
     if (info) *info = inf;
 }
 
@@ -778,6 +845,7 @@ int gcb_set_boundary(gcb_ctx* ctx, int64_t nb, const double* xyz, const double* 
             fail(ctx, GCB_E_INVALID, "non-finite boundary coordinate or displacement");
         HIPCHK(ctx, hipSetDevice(ctx->device));
         ctx->selected = false;
+        ctx->warm_ok = false;
         free_boundary(ctx->bd);
         ctx->bd.nb = nb;
         dalloc(ctx, ctx->bd.xyz0, 3 * (size_t)nb);
@@ -842,6 +910,7 @@ int gcb_set_params(gcb_ctx* ctx, const gcb_params* p) {
 int gcb_set_groups(gcb_ctx* ctx, const int32_t* group_of, int mem) {
     return guard(ctx, [&] {
         if (!group_of) {
+            if (ctx->have_groups) ctx->warm_ok = false;
             ctx->have_groups = false;
             ctx->groups_h.clear();
             return GCB_OK;
@@ -857,6 +926,7 @@ int gcb_set_groups(gcb_ctx* ctx, const int32_t* group_of, int mem) {
         }
         ctx->have_groups = true;
         ctx->selected = false;
+        ctx->warm_ok = false;
         return GCB_OK;
     });
 }
