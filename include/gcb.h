@@ -215,6 +215,79 @@ int gcb_select_batch(gcb_batch *b, gcb_ctx *const *ctxs, int32_t count, gcb_sele
 int gcb_deform_batch(gcb_batch *b, gcb_ctx *const *ctxs, int32_t count, const int64_t *nv, const void *const *xyz,
                      int in_dtype, void *const *out, int out_dtype);
 
+/* ------------------------------------------------------------------
+ * Serving: a request loop over deformation requests of different sizes.
+ * Requests wait in FIFO order and are admitted as slots (max_active) and the
+ * device-memory budget allow.  With GCB_SERVE_BATCH the admitted selections
+ * advance together in shared launches (gcb_batch_step), new requests joining
+ * at the next step (continuous batching), and finished ones are deformed in
+ * one batched volume launch; without it, each admitted request runs
+ * gcb_select and gcb_deform on its own, one at a time.  With GCB_SERVE_CACHE
+ * a finished mesh (keyed by mesh_key) stays resident with its support set
+ * and factor; a later request with the same key, the same boundary and new
+ * displacements is served by a warm start (see gcb_select).  Idle resident
+ * meshes are evicted, least recently used first, when a new mesh would
+ * exceed the budget.  Every result equals that of the same call sequence on
+ * a context of its own.
+ * ------------------------------------------------------------------ */
+typedef struct gcb_server gcb_server;
+
+enum gcb_serve_flags { GCB_SERVE_BATCH = 1, GCB_SERVE_CACHE = 2 };
+
+typedef struct {
+    int64_t mesh_key;        /* >= 0: identity of the boundary for the resident cache; -1: never kept */
+    int64_t nb;              /* boundary nodes */
+    const double *xyz;       /* (nb, 3) host memory, read at admission */
+    const double *disp;      /* (nb, 3) host memory, read at admission */
+    gcb_params params;       /* as for gcb_set_params; the server sets warm_start itself */
+    int64_t nv;              /* volume points (0: selection only) */
+    const void *vol_xyz;     /* (nv, 3) of in_dtype, device memory */
+    int32_t in_dtype;        /* GCB_F32 or GCB_F64 */
+    int32_t out_dtype;       /* GCB_F32 or GCB_F64 */
+    void *out;               /* (nv, 3) of out_dtype, device memory: the displacements of Eq. (6) */
+    double t_arrival;        /* arrival time on gcb_server_clock(); < 0: the time of submission */
+} gcb_request;
+
+typedef struct {
+    int32_t state;           /* 0 queued, 1 selecting, 2 deforming, 3 done; < 0: failed with this status */
+    int32_t warm;            /* 1: served by a warm start from a resident support set */
+    int32_t kept;            /* 1: its mesh stays resident afterwards (until evicted) */
+    int32_t reserved;
+    gcb_select_info info;    /* the selection's result (state 3) */
+    double t_arrival;        /* server clock, seconds */
+    double t_admit;          /* admission (slot and memory granted) */
+    double t_done;           /* the output is complete on the device (event time mapped to the clock) */
+} gcb_result;
+
+/* Monotonic clock of the server, seconds. */
+double gcb_server_clock(void);
+
+/* Create a server on `device` enqueueing on `hip_stream` (verbatim; NULL is
+ * the null stream).  hbm_budget: device bytes the resident and running
+ * meshes may hold (a soft cap: a request is admitted alone when nothing else
+ * runs); max_active: 1..64 concurrent selections; flags: gcb_serve_flags. */
+int gcb_server_create(gcb_server **out, int device, void *hip_stream, uint64_t hbm_budget, int32_t max_active,
+                      int32_t flags);
+void gcb_server_destroy(gcb_server *s);   /* NULL-safe; waits for the device */
+const char *gcb_server_last_error(const gcb_server *s);
+
+/* Queue a request (arguments are checked now; buffers must stay valid
+ * until its result reaches state 3 or fails).  *ticket identifies it. */
+int gcb_server_submit(gcb_server *s, const gcb_request *req, int64_t *ticket);
+
+/* One scheduling round: record finished outputs, admit waiting requests,
+ * run `iterations` (1..4096) greedy iterations of every admitted selection,
+ * finish and deform those that stopped.  *in_flight (may be NULL) gets the
+ * number of requests not yet done.  A failing request is marked failed;
+ * the round goes on. */
+int gcb_server_progress(gcb_server *s, int32_t iterations, int32_t *in_flight);
+
+/* The state and timings of a ticket. */
+int gcb_server_result(const gcb_server *s, int64_t ticket, gcb_result *res);
+
+/* Device bytes held by resident and running meshes, and the resident count. */
+int gcb_server_memory(const gcb_server *s, uint64_t *bytes, int32_t *resident);
+
 /* Host-only: the seeded partition the library uses (Section 3: groups
  * pairwise disjoint, sizes differ by at most one).  Fisher-Yates shuffle pi
  * of 0..nb-1 driven by splitmix64(seed), node pi[t] to group t mod m.

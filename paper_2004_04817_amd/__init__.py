@@ -25,12 +25,15 @@ GCB_E_INVALID, GCB_E_STATE, GCB_E_NOMEM, GCB_E_SINGULAR, GCB_E_DEVICE = -1, -2, 
 GCB_MEM_HOST, GCB_MEM_DEVICE = 0, 1
 GCB_F32, GCB_F64 = 0, 1
 GCB_PREC_FP64, GCB_PREC_FP32_EVAL = 0, 1
+GCB_SERVE_BATCH, GCB_SERVE_CACHE = 1, 2
 
 EXPORTS = ["gcb_version", "gcb_partition", "gcb_create", "gcb_destroy", "gcb_last_error", "gcb_set_stream",
            "gcb_set_boundary", "gcb_set_displacement", "gcb_set_params", "gcb_set_groups", "gcb_select",
            "gcb_get_support", "gcb_get_log", "gcb_deform", "gcb_deform_multi", "gcb_certify",
            "gcb_batch_create", "gcb_batch_destroy", "gcb_batch_last_error", "gcb_batch_begin", "gcb_batch_step",
-           "gcb_batch_end", "gcb_select_batch", "gcb_deform_batch"]
+           "gcb_batch_end", "gcb_select_batch", "gcb_deform_batch",
+           "gcb_server_clock", "gcb_server_create", "gcb_server_destroy", "gcb_server_last_error",
+           "gcb_server_submit", "gcb_server_progress", "gcb_server_result", "gcb_server_memory"]
 
 
 class GcbError(RuntimeError):
@@ -52,6 +55,18 @@ class SelectInfo(C.Structure):
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Request(C.Structure):
+    _fields_ = [("mesh_key", C.c_int64), ("nb", C.c_int64), ("xyz", C.c_void_p), ("disp", C.c_void_p),
+                ("params", Params), ("nv", C.c_int64), ("vol_xyz", C.c_void_p), ("in_dtype", C.c_int32),
+                ("out_dtype", C.c_int32), ("out", C.c_void_p), ("t_arrival", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("state", C.c_int32), ("warm", C.c_int32), ("kept", C.c_int32), ("reserved", C.c_int32),
+                ("info", SelectInfo), ("t_arrival", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double)]
 
 
 _LIB = None
@@ -103,6 +118,16 @@ def lib():
         L.gcb_batch_end.argtypes = [vp, vp, C.POINTER(SelectInfo)]
         L.gcb_select_batch.argtypes = [vp, vp, i32, vp]
         L.gcb_deform_batch.argtypes = [vp, vp, i32, vp, vp, C.c_int, vp, C.c_int]
+        L.gcb_server_clock.restype = C.c_double
+        L.gcb_server_create.argtypes = [C.POINTER(vp), C.c_int, vp, C.c_uint64, i32, i32]
+        L.gcb_server_destroy.argtypes = [vp]
+        L.gcb_server_destroy.restype = None
+        L.gcb_server_last_error.argtypes = [vp]
+        L.gcb_server_last_error.restype = C.c_char_p
+        L.gcb_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(i64)]
+        L.gcb_server_progress.argtypes = [vp, i32, C.POINTER(i32)]
+        L.gcb_server_result.argtypes = [vp, i64, C.POINTER(Result)]
+        L.gcb_server_memory.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(i32)]
         for name in EXPORTS:
             getattr(L, name)
         _LIB = L
@@ -439,6 +464,114 @@ class Batch:
         if rc != GCB_OK:
             self._raise(rc, ctxs)
         return outs
+
+
+def clock() -> float:
+    """The serving clock (monotonic seconds) that request arrival times use."""
+    return float(lib().gcb_server_clock())
+
+
+class Server:
+    """Request loop (wraps a gcb_server): FIFO admission by slots and device
+    memory, continuous batching (GCB_SERVE_BATCH) and resident meshes served by
+    warm starts (GCB_SERVE_CACHE)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 8 << 30, max_active: int = 32,
+                 flags: int = GCB_SERVE_BATCH | GCB_SERVE_CACHE, stream: int | None = None):
+        if stream is None:
+            import torch
+            stream = int(torch.cuda.current_stream(device).cuda_stream)
+        h = C.c_void_p()
+        rc = lib().gcb_server_create(C.byref(h), int(device), C.c_void_p(stream) if stream else None,
+                                     int(hbm_budget), int(max_active), int(flags))
+        if rc != GCB_OK:
+            raise GcbError(rc, "gcb_server_create failed")
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gcb_server_destroy(self._h)
+            self._h = None
+            self._keep = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+        return False
+
+    def _check(self, rc):
+        if rc != GCB_OK:
+            raise GcbError(rc, lib().gcb_server_last_error(self._h).decode())
+
+    def submit(self, xyz, disp, radius, m, tol_abs, seed=0, nc_max=None, mesh_key=-1, vol=None, out=None,
+               t_arrival=-1.0) -> int:
+        """Queue a request: boundary (nb, 3) host arrays, volume and output device tensors."""
+        import torch
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        disp = np.ascontiguousarray(disp, dtype=np.float64)
+        nb = xyz.shape[0]
+        r = Request()
+        r.mesh_key = int(mesh_key)
+        r.nb = nb
+        r.xyz = xyz.ctypes.data
+        r.disp = disp.ctypes.data
+        r.params.radius = float(radius)
+        r.params.m = int(m)
+        r.params.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+        r.params.tol_abs = float(tol_abs)
+        r.params.nc_max = int(nb if nc_max is None else nc_max)
+        keep = [xyz, disp]
+        if vol is not None:
+            if not (_is_tensor(vol) and vol.is_cuda and _is_tensor(out) and out.is_cuda):
+                raise ValueError("vol and out must be device tensors")
+            if not (vol.is_contiguous() and out.is_contiguous()) or tuple(vol.shape) != tuple(out.shape):
+                raise ValueError("vol and out must be contiguous (nv, 3) tensors")
+            r.nv = int(vol.shape[0])
+            r.vol_xyz = vol.data_ptr()
+            r.out = out.data_ptr()
+            r.in_dtype = GCB_F64 if vol.dtype == torch.float64 else GCB_F32
+            r.out_dtype = GCB_F64 if out.dtype == torch.float64 else GCB_F32
+            keep += [vol, out]
+        else:
+            r.in_dtype = r.out_dtype = GCB_F64
+        r.t_arrival = float(t_arrival)
+        t = C.c_int64()
+        self._check(lib().gcb_server_submit(self._h, C.byref(r), C.byref(t)))
+        self._keep[t.value] = keep
+        return t.value
+
+    def progress(self, iterations: int = 16) -> int:
+        n = C.c_int32()
+        self._check(lib().gcb_server_progress(self._h, int(iterations), C.byref(n)))
+        return n.value
+
+    def result(self, ticket: int) -> dict:
+        r = Result()
+        self._check(lib().gcb_server_result(self._h, int(ticket), C.byref(r)))
+        d = {"state": r.state, "warm": bool(r.warm), "kept": bool(r.kept), "t_arrival": r.t_arrival,
+             "t_admit": r.t_admit,
+             "t_done": r.t_done}
+        d.update(r.info.as_dict())
+        if r.state == 3 or r.state < 0:
+            self._keep.pop(int(ticket), None)
+        return d
+
+    def memory(self):
+        b, n = C.c_uint64(), C.c_int32()
+        self._check(lib().gcb_server_memory(self._h, C.byref(b), C.byref(n)))
+        return b.value, n.value
+
+    def last_error(self) -> str:
+        return lib().gcb_server_last_error(self._h).decode()
 
 
 def select(xyz, disp, radius, m, tol_abs, nc_max=None, seed=0, precision=GCB_PREC_FP64, init_idx=None,

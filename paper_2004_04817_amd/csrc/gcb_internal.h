@@ -151,3 +151,8 @@ struct gcb_ctx {
     void *tmp = nullptr;
     size_t tmp_cap = 0;
 };
+
+namespace gcb {
+// Device bytes a context holds now (boundary, support set and factor, records, log, scratch).
+size_t ctx_device_bytes(const gcb_ctx* ctx);
+}  // namespace gcb

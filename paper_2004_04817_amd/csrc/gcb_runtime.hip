@@ -489,6 +489,24 @@ int guard(gcb_ctx* ctx, F&& f) {
 
 }  // namespace
 
+namespace gcb {
+size_t ctx_device_bytes(const gcb_ctx* ctx) {
+    if (!ctx) return 0;
+    const Boundary& bd = ctx->bd;
+    const Support& sp = ctx->sp;
+    size_t b = 0;
+    if (bd.xyz0) b += 48 * (size_t)bd.nb;                                    // xyz0, disp0
+    b += (size_t)bd.alloc_nb * (6 * sizeof(double) + 2 * sizeof(int32_t) + 1);  // staged SoA, perm, pos_of, inS
+    b += sizeof(int32_t) * ((size_t)bd.alloc_m + 1);
+    const size_t tri = (size_t)sp.cap * (size_t)(sp.cap + 1) / 2;
+    b += (size_t)sp.cap * (7 * sizeof(double) + sizeof(int32_t)) + 2 * sizeof(double) * tri;
+    b += sizeof(double) * (size_t)ctx->Pb_cap + sizeof(ArgRec) * (size_t)ctx->argrec_cap;
+    b += (size_t)ctx->log_cap * (2 * sizeof(int32_t) + sizeof(double) + 1);
+    b += sizeof(double) * (size_t)ctx->red_cap + ctx->tmp_cap + sizeof(GState) + sizeof(IterRec);
+    return b;
+}
+}  // namespace gcb
+
 struct gcb_batch {
     int device = 0;
     hipStream_t stream = nullptr;

@@ -17,6 +17,6 @@ from .geometry import (  # noqa: F401
 )
 from .configs import (  # noqa: F401
     Problem, config_small_ellipsoid, config_wing, config_wing_large,
-    config_modes, config_multi_surface, multi_surface_problem, config_requests, tiny_problem,
+    config_modes, config_multi_surface, multi_surface_problem, config_requests, request_mesh, request_field, tiny_problem,
     partition_seed,
 )

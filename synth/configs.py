@@ -155,6 +155,22 @@ def config_requests(n_requests: int = 650, rate: float = 20.0, repeat_p: float =
     return reqs
 
 
+def request_mesh(key: int, nb_target: int) -> Problem:
+    """The boundary of mesh `key` of a request stream (ellipsoid for even keys, wing for odd)."""
+    return multi_surface_problem(key, nb_target, SEED_REQUESTS * 1000 + key)
+
+
+def request_field(base: Problem, field_seed: int) -> np.ndarray:
+    """A new smooth displacement field on a resident mesh: a seeded random mix of
+    the base field's components plus a small chordwise tilt."""
+    gen = g.rng(field_seed & 0x7FFFFFFF, 5)
+    A = np.eye(3) + 0.6 * gen.standard_normal((3, 3))
+    d = base.disp @ A.T
+    x = base.xyz[:, 0]
+    d[:, 2] += 0.02 * base.max_disp * (x - x.min()) / max(float(np.ptp(x)), 1e-12)
+    return np.ascontiguousarray(d)
+
+
 def tiny_problem(nb: int = 12, seed: int = 7, m: int = 3, radius: float = 1.5, tol_rel: float = 0.0,
                  nc_max: int | None = None) -> Problem:
     """Small random point set on a unit sphere with a smooth field (for brute force)."""

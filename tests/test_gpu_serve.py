@@ -1,0 +1,102 @@
+"""The request loop: continuous batching, memory-budgeted admission and
+resident meshes.  Every served output must equal the same request computed
+on a context of its own (a fresh selection, or a warm start from the mesh's
+previous support set when the server kept it), within 1e-12 max|d|."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+import paper_2004_04817_amd as gcb
+from paper_2004_04817_amd import serving
+
+pytestmark = pytest.mark.gpu
+
+TOL_SAME = 1e-12
+
+
+def alone_reference(served):
+    """Recompute every request in its admission order on private contexts."""
+    refs = {}        # mesh key -> context holding the mesh's kept support set
+    outs = {}
+    order = sorted(served, key=lambda s: s.result["t_admit"])
+    extra = []
+    for s in order:
+        r = s.result
+        if r["warm"]:
+            c = refs[s.req.key]
+            c.set_displacement(s.disp)
+            c.set_params(s.radius, s.m, s.tol_abs, seed=s.seed, warm_start=True)
+        else:
+            c = gcb.Context(0)
+            c.set_boundary(s.xyz, s.disp)
+            c.set_params(s.radius, s.m, s.tol_abs, seed=s.seed)
+            if r["kept"]:
+                refs[s.req.key] = c
+            else:
+                extra.append(c)
+        info = c.select()
+        assert info["nc"] == r["nc"] and info["iterations"] == r["iterations"], s.req
+        outs[s.ticket] = c.deform(s.vol)
+    torch.cuda.synchronize()
+    for c in list(refs.values()) + extra:
+        c.close()
+    return outs
+
+
+def check_same(served):
+    ref = alone_reference(served)
+    for s in served:
+        assert s.result["state"] == 3, (s.req, s.result["state"])
+        md = float(np.sqrt((s.disp ** 2).sum(axis=1)).max())
+        d = (s.out - ref[s.ticket]).abs().max().item() if s.out.numel() else 0.0
+        assert d <= TOL_SAME * md, (s.req, d)
+
+
+def small_stream(n, repeat_p, scale=0.08):
+    return serving.materialise(synth.config_requests(n, rate=200.0, repeat_p=repeat_p, size_scale=scale))
+
+
+def test_served_mix_equals_alone():
+    items = small_stream(14, 0.4)
+    pool = serving.volume_pool(40_000, "cuda")
+    with gcb.Server(0, hbm_budget=4 << 30, max_active=8) as srv:
+        served = serving.replay(srv, items, pool, nv_per_nb=6, iterations=8)
+        assert any(s.result["warm"] for s in served)
+        # requests overlapped: some were admitted before an earlier one finished
+        adm = sorted((s.result["t_admit"], s.result["t_done"]) for s in served)
+        assert any(adm[i + 1][0] < adm[i][1] for i in range(len(adm) - 1))
+        check_same(served)
+
+
+def test_one_at_a_time_equals_alone():
+    items = small_stream(6, 0.0)
+    pool = serving.volume_pool(40_000, "cuda")
+    with gcb.Server(0, hbm_budget=4 << 30, max_active=1, flags=0) as srv:
+        served = serving.replay(srv, items, pool, nv_per_nb=6)
+        assert not any(s.result["warm"] or s.result["kept"] for s in served)
+        # one at a time: each admission waits for the previous output
+        adm = sorted((s.result["t_admit"], s.result["t_done"]) for s in served)
+        assert all(adm[i + 1][0] >= adm[i][1] - 1e-4 for i in range(len(adm) - 1))
+        check_same(served)
+
+
+def test_small_budget_queues_and_evicts():
+    items = small_stream(16, 0.5, scale=0.15)
+    pool = serving.volume_pool(40_000, "cuda")
+    budget = 48 << 20
+    with gcb.Server(0, hbm_budget=budget, max_active=8) as srv:
+        served = serving.replay(srv, items, pool, nv_per_nb=4, iterations=8)
+        used, resident = srv.memory()
+        assert resident <= len({s.req.key for s in served})
+        # idle resident meshes were evicted to stay within the budget
+        assert used <= budget or resident == 1, (used, resident)
+        check_same(served)
+
+
+def test_bad_request_rejected():
+    with gcb.Server(0, hbm_budget=1 << 30, max_active=2) as srv:
+        with pytest.raises(gcb.GcbError) as e:
+            srv.submit(np.zeros((2, 3)), np.zeros((2, 3)), 1.0, 1, 0.0)
+        assert e.value.code == gcb.GCB_E_INVALID
+        assert srv.progress(4) == 0
