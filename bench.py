@@ -41,6 +41,9 @@ def parse():
                     help="also time Eq. 6 for this many deformation modes on the wing supports (0: skip)")
     ap.add_argument("--surfaces", type=int, default=32,
                     help="also time this many uneven independent surfaces, batched vs one at a time (0: skip)")
+    ap.add_argument("--requests", type=int, default=250,
+                    help="also replay a Poisson stream of this many deformation requests (20 req/s), served "
+                         "with continuous batching and resident meshes vs one at a time (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, one device-to-device copy of this many MiB (the known-size "
                          "kernel that scales FETCH_SIZE / WRITE_SIZE counter readings)")
@@ -141,6 +144,28 @@ def multi_surface(count, dev):
     batch.close()
     for c in ctxs:
         c.close()
+    return res
+
+
+def serving_section(n_requests, dev, warmup_requests=25, rate=20.0):
+    """Poisson stream (sizes of the uneven batch, 20 % repeats with new fields),
+    latency arrival -> output complete: served (continuous batching, resident
+    meshes, warm starts) vs plain FP64 one at a time (FIFO)."""
+    import synth
+    import paper_2004_04817_amd as gcb
+    from paper_2004_04817_amd import serving
+    stream = synth.config_requests(n_requests, rate=rate, repeat_p=0.2)
+    items = serving.materialise(stream)
+    max_nv = 25 * max(i[1].nb for i in items)
+    pool = serving.volume_pool(max_nv, dev)
+    res = {"requests": n_requests, "warmup_requests": warmup_requests, "rate_per_s": rate, "repeat_p": 0.2,
+           "nv_per_nb": 25, "precision": "fp64"}
+    for name, kw in (("served", dict(max_active=32, flags=gcb.GCB_SERVE_BATCH | gcb.GCB_SERVE_CACHE)),
+                     ("one_at_a_time", dict(max_active=1, flags=0))):
+        with gcb.Server(0, hbm_budget=64 << 30, **kw) as srv:
+            served = serving.replay(srv, items, pool, nv_per_nb=25, iterations=48)
+            res[name] = serving.latency_summary(served, skip=warmup_requests)
+    del pool
     return res
 
 
@@ -256,6 +281,12 @@ def main():
         del mout, modes
     if a.surfaces > 0:
         rec["multi_surface"] = multi_surface(a.surfaces, dev)
+    if a.requests > 0:
+        rec["serving"] = serving_section(a.requests, dev)
+        rec["latency_ms"] = {"p50": rec["serving"]["served"]["p50_ms"], "p99": rec["serving"]["served"]["p99_ms"],
+                             "p50_one_at_a_time_fp64": rec["serving"]["one_at_a_time"]["p50_ms"],
+                             "p99_one_at_a_time_fp64": rec["serving"]["one_at_a_time"]["p99_ms"],
+                             "what": "deformation request latency, arrival to output complete"}
     if not a.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(p, min(a.cpu_sample_volume, nv))
     print(json.dumps(rec), flush=True)
