@@ -63,6 +63,8 @@ def load(path: str):
     L.orc_solve_on_support.restype = C.c_int
     L.orc_solve_on_support.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_int32,
                                        C.c_void_p, C.c_void_p]
+    L.orc_inverse_factor.restype = C.c_int
+    L.orc_inverse_factor.argtypes = [C.c_int64, C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_void_p]
     L.orc_validate.restype = C.c_int64
     L.orc_validate.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
@@ -261,6 +263,17 @@ def validate(xyz, disp, radius, m, tol_abs, S_init, group, node, appended, tau, 
                              float(tau), C.byref(reason), C.byref(gap))
     del keep
     return int(bad), int(reason.value), float(gap.value)
+
+
+def inverse_factor(xyz, S, radius) -> np.ndarray:
+    """M = L^-1 (n, n) with L L^T = Phi_S for the support set S in its order."""
+    xyz = _f64(xyz)
+    S = np.ascontiguousarray(S, dtype=np.int64)
+    M = np.empty((max(len(S), 1), max(len(S), 1)))
+    st = lib().orc_inverse_factor(xyz.shape[0], _ptr(xyz), _ptr(S), len(S), float(radius), _ptr(M))
+    if st != ORC_OK:
+        raise RuntimeError(f"orc_inverse_factor: status {st}")
+    return M[: len(S), : len(S)]
 
 
 def solve_on_support(xyz, S, radius, D) -> np.ndarray:

@@ -491,6 +491,37 @@ int orc_solve_on_support(int64_t nb, const double *xyz, const int64_t *S, int64_
     return status;
 }
 
+int orc_inverse_factor(int64_t nb, const double *xyz, const int64_t *S, int64_t n, double radius, double *M_out) {
+    (void)nb;
+    orc_rc *rc = orc_rc_create(1);
+    double *b = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double zero = 0.0;
+    int status = ORC_OK;
+    for (int64_t t = 0; t < n && status == ORC_OK; ++t) {
+        for (int64_t s = 0; s < t; ++s) b[s] = orc_phi(dist3(xyz + 3 * S[s], xyz + 3 * S[t]) / radius);
+        status = orc_rc_append(rc, b, orc_phi(0.0), &zero);
+    }
+    free(b);
+    if (status != ORC_OK) {
+        orc_rc_destroy(rc);
+        return status;
+    }
+    double *L = (double *)malloc(sizeof(double) * (size_t)(n * n));
+    orc_rc_factor(rc, L);
+    orc_rc_destroy(rc);
+    memset(M_out, 0, sizeof(double) * (size_t)(n * n));
+    /* column c of M solves L x = e_c: x_i = 0 for i < c, then forward substitution */
+    for (int64_t col = 0; col < n; ++col) {
+        for (int64_t i = col; i < n; ++i) {
+            double acc = i == col ? 1.0 : 0.0;
+            for (int64_t k = col; k < i; ++k) acc -= L[i * n + k] * M_out[k * n + col];
+            M_out[i * n + col] = acc / L[i * n + i];
+        }
+    }
+    free(L);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------ follow-mode replay */
 int64_t orc_validate(const orc_problem *p, const int64_t S_init[3], int64_t n_iter,
                      const int32_t *group, const int64_t *node, const int8_t *appended,

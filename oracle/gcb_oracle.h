@@ -117,6 +117,13 @@ int orc_select(const orc_problem *p, int64_t *S_out, double *W_out, orc_log *log
 int orc_solve_on_support(int64_t nb, const double *xyz, const int64_t *S, int64_t n, double radius, int32_t K,
                          const double *D, double *W_out);
 
+/* Inverse Cholesky factor of the support system: L L^T = Phi_S (Eq. 5
+ * restricted to S, in the given order; L from the same row recurrence as the
+ * selection), then M = L^-1 by forward substitution, column by column.
+ * M_out (n,n) row-major, zero above the diagonal.  Returns ORC_OK or
+ * ORC_E_SINGULAR. */
+int orc_inverse_factor(int64_t nb, const double *xyz, const int64_t *S, int64_t n, double radius, double *M_out);
+
 /* Replays a foreign selection (per iteration: group, node, appended) and
  * checks each step against FP64 errors computed here, following the foreign
  * choice afterwards: the group is k mod m; an appended node lies in G_i \ S,

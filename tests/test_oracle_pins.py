@@ -390,3 +390,29 @@ def test_warm_start_validation_and_replay():
     # claiming that the kept set already meets E* is rejected (reason 6)
     none = oracle.validate(p.xyz, d2, p.radius, 3, tol, r.S, [], [], [], 1e-12, seed=p.seed, warm_S=r.S)
     assert none[0] == 0 and none[1] == 6
+
+
+@pytest.mark.parametrize("n", [3, 17, 120])
+def test_inverse_factor_against_library_cholesky(n):
+    """M = L^-1: M L = I and L L^T = Phi_S, checked with numpy's Cholesky and inverse
+    (an independent factorisation, not the oracle's recurrence)."""
+    p = synth.config_small_ellipsoid(with_volume=False)
+    r = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed)
+    S = r.S[:n]
+    M = oracle.inverse_factor(p.xyz, S, p.radius)
+    Phi = brute.rbf_matrix(p.xyz[S], p.xyz[S], p.radius)
+    L = np.linalg.cholesky(Phi)
+    assert np.allclose(np.triu(M, 1), 0.0)
+    assert np.abs(M @ L - np.eye(n)).max() <= 1e-10
+    Minv = np.linalg.inv(L)
+    assert np.abs(M - Minv).max() <= 1e-9 * np.abs(Minv).max()
+    # the weights M^T M d equal the oracle's RC solve on S
+    W = M.T @ (M @ p.disp[S])
+    assert np.abs(W - oracle.solve_on_support(p.xyz, S, p.radius, p.disp)).max() <= 1e-8 * np.abs(W).max()
+
+
+def test_inverse_factor_singular():
+    p = synth.tiny_problem(nb=12, seed=1)
+    xyz = np.concatenate([p.xyz, p.xyz[:1]])
+    with pytest.raises(RuntimeError):
+        oracle.inverse_factor(xyz, [0, 3, 12], p.radius)
