@@ -163,6 +163,28 @@ int gcb_deform(gcb_ctx *ctx, int64_t nv, const void *xyz, int in_dtype, void *ou
 int gcb_deform_multi(gcb_ctx *ctx, int32_t k_modes, const double *disp_modes, int64_t nv, const void *xyz,
                      int in_dtype, void *out, int out_dtype, int mem);
 
+/* Give the context a support set instead of selecting one: idx[0..n) are
+ * distinct boundary indices (host or device memory per mem), 3 <= n <=
+ * nc_max.  The support system Phi_S (Eqs. 4-5 restricted to S, in this
+ * order) is factored from scratch in FP64 (blocked Cholesky and triangular
+ * inverse on the matrix cores, M = L^-1), W = M^T (M Delta_S) for the current
+ * displacements, and the FP64 all-node certificate fills *info (may be
+ * NULL; iterations = 0).  Afterwards the context is as after a finished
+ * selection: gcb_deform, gcb_get_support and warm starts work.  Returns
+ * GCB_OK, GCB_E_SINGULAR (a pivot <= 64 DBL_EPSILON) or an error. */
+int gcb_set_support(gcb_ctx *ctx, const int64_t *idx, int64_t n, int mem, gcb_select_info *info);
+
+/* Copy out the inverse factor M = L^-1 of the current support set (Phi_S =
+ * L L^T in selection order) as packed rows: row i, entries 0..i, starts at
+ * i(i+1)/2; m holds nc(nc+1)/2 doubles (host or device per mem). */
+int gcb_get_factor(gcb_ctx *ctx, double *m, int mem);
+
+/* Re-certify the inverse factor of the current support set against rounding
+ * drift: rebuild it from scratch as in gcb_set_support, replace the grown
+ * one, recompute W and the certificate (in *info, may be NULL).  *drift (may
+ * be NULL) gets max|M_new - M_old| / max|M_old| over the packed factor. */
+int gcb_refactor(gcb_ctx *ctx, double *drift, gcb_select_info *info);
+
 /* FP64 interpolation error over all nb boundary nodes with the current
  * support set (the convergence certificate): max and RMS of |F(r_j) - d_j|_2. */
 int gcb_certify(gcb_ctx *ctx, double *max_err, double *rms_err);

@@ -30,6 +30,7 @@ GCB_SERVE_BATCH, GCB_SERVE_CACHE = 1, 2
 EXPORTS = ["gcb_version", "gcb_partition", "gcb_create", "gcb_destroy", "gcb_last_error", "gcb_set_stream",
            "gcb_set_boundary", "gcb_set_displacement", "gcb_set_params", "gcb_set_groups", "gcb_select",
            "gcb_get_support", "gcb_get_log", "gcb_deform", "gcb_deform_multi", "gcb_certify",
+           "gcb_set_support", "gcb_refactor", "gcb_get_factor",
            "gcb_batch_create", "gcb_batch_destroy", "gcb_batch_last_error", "gcb_batch_begin", "gcb_batch_step",
            "gcb_batch_end", "gcb_select_batch", "gcb_deform_batch",
            "gcb_server_clock", "gcb_server_create", "gcb_server_destroy", "gcb_server_last_error",
@@ -107,6 +108,9 @@ def lib():
         L.gcb_deform.argtypes = [vp, i64, vp, C.c_int, vp, C.c_int, C.c_int]
         L.gcb_deform_multi.argtypes = [vp, i32, vp, i64, vp, C.c_int, vp, C.c_int, C.c_int]
         L.gcb_certify.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.gcb_set_support.argtypes = [vp, vp, i64, C.c_int, C.POINTER(SelectInfo)]
+        L.gcb_refactor.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(SelectInfo)]
+        L.gcb_get_factor.argtypes = [vp, vp, C.c_int]
         L.gcb_batch_create.argtypes = [C.POINTER(vp), C.c_int, vp]
         L.gcb_batch_destroy.argtypes = [vp]
         L.gcb_batch_destroy.restype = None
@@ -350,6 +354,31 @@ class Context:
         self.use_current_stream(kx)
         self._check(lib().gcb_deform_multi(self._h, rc // 3, pm, int(kx.shape[0]), px, in_dt, po, out_dt, mx))
         return out
+
+    def set_support(self, idx) -> dict:
+        """Use the support set idx (selection order) instead of selecting: the
+        factor is rebuilt from scratch (dense FP64) and W fitted to the current field."""
+        p, m, k = _arg(idx, np.int64)
+        info = SelectInfo()
+        self._check(lib().gcb_set_support(self._h, p, int(k.shape[0]), m, C.byref(info)))
+        self.nc = info.nc
+        return info.as_dict()
+
+    def get_factor(self) -> np.ndarray:
+        """The inverse factor M = L^-1 (nc, nc), dense lower triangular."""
+        n = int(self.nc)
+        p = np.empty(n * (n + 1) // 2)
+        self._check(lib().gcb_get_factor(self._h, p.ctypes.data, GCB_MEM_HOST))
+        M = np.zeros((n, n))
+        M[np.tril_indices(n)] = p
+        return M
+
+    def refactor(self):
+        """Rebuild the inverse factor of the current support set; returns (drift, info)."""
+        d = C.c_double()
+        info = SelectInfo()
+        self._check(lib().gcb_refactor(self._h, C.byref(d), C.byref(info)))
+        return d.value, info.as_dict()
 
     def certify(self):
         mx, rms = C.c_double(), C.c_double()

@@ -1,0 +1,263 @@
+// Dense FP64 refactorisation of the support system: Phi_S = L L^T (blocked
+// right-looking Cholesky) and M = L^-1 (blocked triangular inverse), with the
+// block products on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  Used to
+// rebuild the inverse factor of a given support set, and to re-certify the
+// incrementally grown factor against rounding drift.
+//
+// Matrices are dense row-major np x np with np = n rounded up to kDB; the
+// padding is the identity, so every block step is full-sized:
+// chol([[Phi, 0], [0, I]]) = [[L, 0], [0, I]] and its inverse is [[M, 0], [0, I]].
+#include <hip/hip_runtime.h>
+
+#include "gcb_device.h"
+#include "gcb_internal.h"
+#include "gcb_kernels.h"
+
+namespace gcb {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int kDB = 32;   // block size of the blocked algorithms
+
+// A = Phi_S (lower triangle, zero above) in the np x np padded layout.
+__global__ __launch_bounds__(kBlock) void k_assemble(int n, int np, const double* __restrict__ sx,
+                                                     const double* __restrict__ sy, const double* __restrict__ sz,
+                                                     double* __restrict__ A) {
+    const int64_t x = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (x >= (int64_t)np * np) return;
+    const int i = (int)(x / np), j = (int)(x % np);
+    double v = 0.0;
+    if (i < n && j < n) {
+        if (j <= i) v = wendland_r2(dist2(sx[i], sy[i], sz[i], sx[j], sy[j], sz[j]));
+    } else if (i == j) {
+        v = 1.0;
+    }
+    A[x] = v;
+}
+
+// Diagonal block of step k0 (already updated by the earlier steps):
+// unblocked Cholesky in LDS, written back in place (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_chol_diag(int np, int k0, double* __restrict__ A,
+                                                      int32_t* __restrict__ bad) {
+    __shared__ double D[kDB][kDB + 1];
+    const int tid = threadIdx.x;
+    for (int x = tid; x < kDB * kDB; x += kBlock) D[x / kDB][x % kDB] = A[(size_t)(k0 + x / kDB) * np + k0 + x % kDB];
+    __syncthreads();
+    for (int c = 0; c < kDB; ++c) {
+        if (tid == 0) {
+            const double d = D[c][c];
+            if (!(d > kSingularTol)) bad[0] = 1;
+            D[c][c] = sqrt(d > kSingularTol ? d : 1.0);
+        }
+        __syncthreads();
+        if (tid > c && tid < kDB) D[tid][c] /= D[c][c];
+        __syncthreads();
+        for (int x = tid; x < kDB * kDB; x += kBlock) {
+            const int i = x / kDB, j = x % kDB;
+            if (j > c && i >= j) D[i][j] -= D[i][c] * D[j][c];
+        }
+        __syncthreads();
+    }
+    for (int x = tid; x < kDB * kDB; x += kBlock) {
+        const int i = x / kDB, j = x % kDB;
+        A[(size_t)(k0 + i) * np + k0 + j] = j <= i ? D[i][j] : 0.0;
+    }
+}
+
+// Panel of step k0: rows below the diagonal block solve x L_kk^T = a, one row
+// per thread (the factored L_kk comes from the previous launch).
+__global__ __launch_bounds__(kBlock) void k_chol_panel(int np, int k0, double* __restrict__ A) {
+    __shared__ double D[kDB][kDB + 1];
+    const int tid = threadIdx.x;
+    for (int x = tid; x < kDB * kDB; x += kBlock) D[x / kDB][x % kDB] = A[(size_t)(k0 + x / kDB) * np + k0 + x % kDB];
+    __syncthreads();
+    const int r = k0 + kDB + blockIdx.x * kBlock + tid;
+    if (r >= np) return;
+    double* Ar = A + (size_t)r * np + k0;
+    double x[kDB];
+#pragma unroll
+    for (int c = 0; c < kDB; ++c) x[c] = Ar[c];
+#pragma unroll
+    for (int c = 0; c < kDB; ++c) {
+        double v = x[c];
+#pragma unroll
+        for (int t = 0; t < c; ++t) v -= x[t] * D[c][t];
+        x[c] = v / D[c][c];
+    }
+#pragma unroll
+    for (int c = 0; c < kDB; ++c) Ar[c] = x[c];
+}
+
+// lower block index pair (ti >= tj) of linear index b
+__device__ __forceinline__ void tri_index(int b, int& ti, int& tj) {
+    int i = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= b) ++i;
+    while (i * (i + 1) / 2 > b) --i;
+    ti = i;
+    tj = b - i * (i + 1) / 2;
+}
+
+// Trailing update after step k0: A[k1:, k1:] -= P P^T (lower blocks) with
+// P = A[k1:, k0:k1], k1 = k0 + kDB.  One workgroup per kDB x kDB block, one
+// wave per 16 x 16 quarter, K = kDB on the matrix cores.
+__global__ __launch_bounds__(kBlock) void k_chol_update(int np, int k0, double* __restrict__ A) {
+    const int k1 = k0 + kDB;
+    int ti, tj;
+    tri_index(blockIdx.x, ti, tj);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int R0 = k1 + kDB * ti + 16 * (wave >> 1);
+    const int C0 = k1 + kDB * tj + 16 * (wave & 1);
+    if (ti == tj && (wave >> 1) < (wave & 1)) return;   // strictly upper quarter of a diagonal block
+    const int li = lane & 15, lk = lane >> 4;
+    const double* Pa = A + (size_t)(R0 + li) * np + k0;
+    const double* Pb = A + (size_t)(C0 + li) * np + k0;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < kDB; s += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Pa[s + lk], Pb[s + lk], acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) A[(size_t)(R0 + lk + 4 * r) * np + C0 + li] -= acc[r];
+}
+
+// Diagonal blocks of M: M_jj = L_jj^-1, one workgroup per block; thread c
+// forms column c by forward substitution.
+__global__ __launch_bounds__(kBlock) void k_trtri_diag(int np, const double* __restrict__ L, double* __restrict__ M) {
+    __shared__ double Ld[kDB][kDB + 1];
+    __shared__ double X[kDB][kDB + 1];
+    const int j0 = blockIdx.x * kDB;
+    for (int x = threadIdx.x; x < kDB * kDB; x += kBlock)
+        Ld[x / kDB][x % kDB] = L[(size_t)(j0 + x / kDB) * np + j0 + x % kDB];
+    __syncthreads();
+    const int c = threadIdx.x;
+    if (c < kDB) {
+        for (int i = 0; i < kDB; ++i) {
+            if (i < c) {
+                X[i][c] = 0.0;
+                continue;
+            }
+            double v = i == c ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) v -= Ld[i][k] * X[k][c];
+            X[i][c] = v / Ld[i][i];
+        }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < kDB * kDB; x += kBlock)
+        M[(size_t)(j0 + x / kDB) * np + j0 + x % kDB] = X[x / kDB][x % kDB];
+}
+
+// Blocks of M at distance s below the diagonal, all in parallel:
+// M_ij = -M_ii (sum_{k=j}^{i-1} L_ik M_kj), i = j + s; the blocks M_kj with
+// k - j < s come from earlier launches.
+__global__ __launch_bounds__(kBlock) void k_trtri_off(int np, int s, const double* __restrict__ L,
+                                                      double* __restrict__ M) {
+    __shared__ double T[kDB][kDB + 1];
+    const int j = blockIdx.x, i = j + s;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int qi = wave >> 1, qj = wave & 1;
+    const int li = lane & 15, lk = lane >> 4;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    const double* La = L + (size_t)(kDB * i + 16 * qi + li) * np;
+    for (int k = kDB * j; k < kDB * i; k += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(La[k + lk], M[(size_t)(k + lk) * np + kDB * j + 16 * qj + li], acc,
+                                                   0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) T[16 * qi + lk + 4 * r][16 * qj + li] = acc[r];
+    __syncthreads();
+    d4 out = {0.0, 0.0, 0.0, 0.0};
+    const double* Mi = M + (size_t)(kDB * i + 16 * qi + li) * np + kDB * i;
+#pragma unroll
+    for (int k = 0; k < kDB; k += 4)
+        out = __builtin_amdgcn_mfma_f64_16x16x4f64(Mi[k + lk], T[k + lk][16 * qj + li], out, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) M[(size_t)(kDB * i + 16 * qi + lk + 4 * r) * np + kDB * j + 16 * qj + li] = -out[r];
+}
+
+// Packed rows of the first n rows (row i at i(i+1)/2), and the largest
+// |new - old| and |old| against a previous packed factor (per workgroup).
+__global__ __launch_bounds__(kBlock) void k_pack_rows(int n, int np, const double* __restrict__ Md,
+                                                      double* Mp, const double* old,   // Mp may be old
+                                                      double* __restrict__ red) {
+    __shared__ double sd[kBlock], so[kBlock];
+    const int64_t tri = (int64_t)n * (n + 1) / 2;
+    double dmax = 0.0, omax = 0.0;
+    for (int64_t x = blockIdx.x * (int64_t)kBlock + threadIdx.x; x < tri; x += (int64_t)gridDim.x * kBlock) {
+        int i = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
+        while ((int64_t)(i + 1) * (i + 2) / 2 <= x) ++i;
+        while ((int64_t)i * (i + 1) / 2 > x) --i;
+        const int j = (int)(x - (int64_t)i * (i + 1) / 2);
+        const double v = Md[(size_t)i * np + j];
+        if (old) {
+            const double o = old[x];
+            dmax = fmax(dmax, fabs(v - o));
+            omax = fmax(omax, fabs(o));
+        }
+        Mp[x] = v;
+    }
+    sd[threadIdx.x] = dmax;
+    so[threadIdx.x] = omax;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + h]);
+            so[threadIdx.x] = fmax(so[threadIdx.x], so[threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        red[2 * blockIdx.x] = sd[0];
+        red[2 * blockIdx.x + 1] = so[0];
+    }
+}
+
+// Scaled coordinates of a given support set (original indices orig[0..n)).
+__global__ __launch_bounds__(kBlock) void k_gather_support(int n, const int32_t* __restrict__ orig,
+                                                           const double* __restrict__ xyz0, double inv_r,
+                                                           double* __restrict__ sx, double* __restrict__ sy,
+                                                           double* __restrict__ sz) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const int o = orig[j];
+    sx[j] = xyz0[3 * (size_t)o] * inv_r;
+    sy[j] = xyz0[3 * (size_t)o + 1] * inv_r;
+    sz[j] = xyz0[3 * (size_t)o + 2] * inv_r;
+}
+
+}  // namespace
+
+void launch_gather_support(hipStream_t s, Support& sp, int n, const double* xyz0, double inv_r) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather_support, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, sp.orig,
+                       xyz0, inv_r, sp.sx, sp.sy, sp.sz);
+}
+
+int dense_padded(int n) { return (n + kDB - 1) / kDB * kDB; }
+
+int dense_pack_blocks() { return 256; }
+
+void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, int32_t* bad) {
+    const int np = dense_padded(n);
+    const int nbk = np / kDB;
+    const int64_t cnt = (int64_t)np * np;
+    hipLaunchKernelGGL(k_assemble, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, np, sp.sx,
+                       sp.sy, sp.sz, A);
+    for (int kb = 0; kb < nbk; ++kb) {
+        const int k0 = kb * kDB;
+        const int rows = np - k0 - kDB;
+        const unsigned g = (unsigned)std::max(1, (rows + kBlock - 1) / kBlock);
+        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(kBlock), 0, s, np, k0, A, bad);
+        if (rows > 0) hipLaunchKernelGGL(k_chol_panel, dim3(g), dim3(kBlock), 0, s, np, k0, A);
+        const int nt = nbk - kb - 1;
+        if (nt > 0) hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(kBlock), 0, s, np, k0, A);
+    }
+    // blocks of Md above the diagonal are never read: no clearing needed
+    hipLaunchKernelGGL(k_trtri_diag, dim3((unsigned)nbk), dim3(kBlock), 0, s, np, A, Md);
+    for (int d = 1; d < nbk; ++d)
+        hipLaunchKernelGGL(k_trtri_off, dim3((unsigned)(nbk - d)), dim3(kBlock), 0, s, np, d, A, Md);
+}
+
+void launch_pack_factor(hipStream_t s, int n, const double* Md, double* Mp, const double* old, double* red) {
+    hipLaunchKernelGGL(k_pack_rows, dim3((unsigned)dense_pack_blocks()), dim3(kBlock), 0, s, n, dense_padded(n), Md, Mp,
+                       old, red);
+}
+
+}  // namespace gcb

@@ -126,6 +126,17 @@ int multi_padded_r(int rc);
 bool launch_support_weights(hipStream_t s, Support& sp, int n, const double* disp, double* Dbuf, double* Ybuf,
                             double* Wbuf);
 void launch_mark_support(hipStream_t s, const Boundary& bd, const Support& sp, int n);
+
+// Dense FP64 refactorisation (matrix cores): A, Md hold dense_padded(n)^2
+// doubles each; on return A = L (Cholesky of Phi_S) and Md = L^-1, and
+// *bad = 1 (set, never cleared) if a pivot was not above kSingularTol.
+int dense_padded(int n);
+int dense_pack_blocks();
+void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, int32_t* bad);
+// Packed rows of Md into Mp (may equal old); with old, red[2b], red[2b+1]
+// get per-block max |new - old| and max |old| (dense_pack_blocks() blocks).
+void launch_pack_factor(hipStream_t s, int n, const double* Md, double* Mp, const double* old, double* red);
+void launch_gather_support(hipStream_t s, Support& sp, int n, const double* xyz0, double inv_r);
 bool launch_deform_multi(hipStream_t s, const Support& sp, int n, int rc, const double* modes_dev, double* Dbuf,
                          double* Ybuf, double* Wbuf, int64_t nv, const void* xyz, int in_f64, double inv_r, void* out,
                          int out_f64);

@@ -1104,6 +1104,170 @@ int gcb_deform_multi(gcb_ctx* ctx, int32_t k_modes, const double* disp_modes, in
     });
 }
 
+// Inverse factor of the first n supports rebuilt from scratch (dense FP64 on
+// the matrix cores) into sp.M / sp.Mc, then W for the current displacements
+// and the certificate into ctx->info.  *drift when old factor is compared.
+void rebuild_factor(gcb_ctx* ctx, int n, bool compare, double* drift) {
+    Support& sp = ctx->sp;
+    Boundary& bd = ctx->bd;
+    const int np = dense_padded(n);
+    const int R = multi_padded_r(3);
+    const size_t dense_b = sizeof(double) * (size_t)np * np;
+    const size_t w_b = sizeof(double) * 3 * (size_t)n * R;
+    ensure_tmp(ctx, 2 * dense_b + w_b + 1024);
+    char* base = static_cast<char*>(ctx->tmp);
+    double* A = reinterpret_cast<double*>(base);
+    double* Md = reinterpret_cast<double*>(base + dense_b);
+    double* Wb = reinterpret_cast<double*>(base + 2 * dense_b);
+    int32_t* bad = reinterpret_cast<int32_t*>(base + 2 * dense_b + w_b);
+    const int nred = dense_pack_blocks();
+    if (ctx->red_cap < 2 * nred + 2) {
+        ctx->red_cap = 2 * nred + 2;
+        dalloc(ctx, ctx->red, ctx->red_cap);
+    }
+    ensure_red(ctx);
+    HIPCHK(ctx, hipMemsetAsync(bad, 0, sizeof(int32_t), ctx->stream));
+    HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
+    launch_inverse_factor(ctx->stream, sp, n, A, Md, bad);
+    HIPCHK(ctx, hipGetLastError());
+    int32_t hbad = 0;
+    HIPCHK(ctx, hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    if (hbad) {
+        ctx->err = "support matrix not numerically SPD (a Cholesky pivot <= 64 DBL_EPSILON)";
+        throw Fail{GCB_E_SINGULAR};
+    }
+    launch_pack_factor(ctx->stream, n, Md, sp.M, compare ? sp.M : nullptr, ctx->red);
+    launch_transpose_factor(ctx->stream, sp.M, sp.Mc, n, sp.cap);
+    if (!launch_support_weights(ctx->stream, sp, n, bd.disp0, Wb, Wb + (size_t)n * R, Wb + 2 * (size_t)n * R))
+        fail(ctx, GCB_E_DEVICE, "internal error: weight recomputation rejected");
+    HIPCHK(ctx, hipGetLastError());
+    if (compare) {
+        std::vector<double> red(2 * (size_t)nred);
+        HIPCHK(ctx, hipMemcpyAsync(red.data(), ctx->red, sizeof(double) * red.size(), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        sync(ctx);
+        double dm = 0.0, om = 0.0;
+        for (int b = 0; b < nred; ++b) {
+            dm = std::max(dm, red[2 * b]);
+            om = std::max(om, red[2 * b + 1]);
+        }
+        if (drift) *drift = om > 0.0 ? dm / om : 0.0;
+    }
+    launch_certify(ctx->stream, bd, sp, n, ctx->red, ctx->red + ctx->red_cap - 2);
+    HIPCHK(ctx, hipEventRecord(ctx->ev1, ctx->stream));
+    HIPCHK(ctx, hipGetLastError());
+    double mr[2];
+    HIPCHK(ctx, hipMemcpyAsync(mr, ctx->red + ctx->red_cap - 2, sizeof(mr), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    float ms = 0.f;
+    HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    gcb_select_info& inf = ctx->info;
+    inf.nc = n;
+    inf.final_max_err = std::sqrt(mr[0]);
+    inf.final_rms_err = std::sqrt(mr[1] / (double)bd.nb);
+    inf.converged = inf.final_max_err <= ctx->params.tol_abs;
+    inf.pairs_cert = (uint64_t)bd.nb * (uint64_t)n;
+    inf.ms_select = ms;
+}
+
+int gcb_set_support(gcb_ctx* ctx, const int64_t* idx, int64_t n, int mem, gcb_select_info* info) {
+    return guard(ctx, [&] {
+        check_params(ctx);
+        const gcb_params& p = ctx->params;
+        const int64_t nb = ctx->bd.nb;
+        if (!idx || n < 3 || n > p.nc_max) fail(ctx, GCB_E_INVALID, "need idx and 3 <= n <= nc_max");
+        if (mem != GCB_MEM_HOST && mem != GCB_MEM_DEVICE) fail(ctx, GCB_E_INVALID, "bad mem kind");
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        std::vector<int64_t> h((size_t)n);
+        if (mem == GCB_MEM_DEVICE) {
+            HIPCHK(ctx, hipMemcpyAsync(h.data(), idx, sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToHost, ctx->stream));
+            sync(ctx);
+        } else {
+            std::memcpy(h.data(), idx, sizeof(int64_t) * (size_t)n);
+        }
+        std::vector<uint8_t> seen((size_t)nb, 0);
+        std::vector<int32_t> o((size_t)n);
+        for (int64_t t = 0; t < n; ++t) {
+            if (h[t] < 0 || h[t] >= nb || seen[h[t]]) fail(ctx, GCB_E_INVALID, "idx must be distinct indices in [0, nb)");
+            seen[h[t]] = 1;
+            o[t] = (int32_t)h[t];
+        }
+        ctx->selected = false;
+        ctx->warm_ok = false;
+        ctx->in_progress = false;
+        stage_boundary(ctx);
+        const int64_t cap = std::max<int64_t>(std::min<int64_t>(p.nc_max, 1024), n);
+        if (ctx->sp.cap < n || ctx->sp.cap > std::max<int64_t>(p.nc_max, n)) {
+            free_support(ctx->sp);
+            grow_support(ctx, cap, 0);
+        }
+        if (!ctx->state) dalloc(ctx, ctx->state, 1);
+        if (!ctx->irec) dalloc(ctx, ctx->irec, 1);
+        if (!ctx->state_pin) HIPCHK(ctx, hipHostMalloc(reinterpret_cast<void**>(&ctx->state_pin), sizeof(GState)));
+        if (!ctx->ev0) HIPCHK(ctx, hipEventCreate(&ctx->ev0));
+        if (!ctx->ev1) HIPCHK(ctx, hipEventCreate(&ctx->ev1));
+        const int64_t nrec = std::max<int64_t>(512, sweep_blocks(ctx->bd.gmax));
+        if (ctx->argrec_cap < nrec + 1) {
+            ctx->argrec_cap = nrec + 1;
+            dalloc(ctx, ctx->argrec, ctx->argrec_cap);
+        }
+        if (ctx->log_cap == 0) grow_log(ctx, 0, 65536);
+        HIPCHK(ctx, hipMemcpyAsync(ctx->sp.orig, o.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice,
+                                   ctx->stream));
+        launch_gather_support(ctx->stream, ctx->sp, (int)n, ctx->bd.xyz0, ctx->bd.inv_r);
+        launch_mark_support(ctx->stream, ctx->bd, ctx->sp, (int)n);
+        HIPCHK(ctx, hipGetLastError());
+        ctx->info = gcb_select_info{};
+        rebuild_factor(ctx, (int)n, false, nullptr);
+        GState st{};
+        st.k = n;
+        st.n = (int32_t)n;
+        st.done = 1;
+        st.singular_node = -1;
+        ctx->state_h = st;
+        gcb_select_info& inf = ctx->info;
+        inf.iterations = 0;
+        inf.status = GCB_OK;
+        ctx->selected = true;
+        ctx->warm_ok = true;
+        ctx->warm_radius = p.radius;
+        ctx->warm_m = p.m;
+        ctx->warm_seed = p.seed;
+        ctx->warm_n = n;
+        if (info) *info = inf;
+        return GCB_OK;
+    });
+}
+
+int gcb_get_factor(gcb_ctx* ctx, double* m, int mem) {
+    return guard(ctx, [&] {
+        if (!ctx->selected) fail(ctx, GCB_E_STATE, "no finished selection");
+        if (!m) fail(ctx, GCB_E_INVALID, "m is NULL");
+        if (mem != GCB_MEM_HOST && mem != GCB_MEM_DEVICE) fail(ctx, GCB_E_INVALID, "bad mem kind");
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        const size_t n = (size_t)ctx->info.nc;
+        HIPCHK(ctx, hipMemcpyAsync(m, ctx->sp.M, sizeof(double) * n * (n + 1) / 2,
+                                   mem == GCB_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+        sync(ctx);
+        return GCB_OK;
+    });
+}
+
+int gcb_refactor(gcb_ctx* ctx, double* drift, gcb_select_info* info) {
+    return guard(ctx, [&] {
+        if (!ctx->selected) fail(ctx, GCB_E_STATE, "no finished selection to re-certify");
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        const int n = (int)ctx->info.nc;
+        ctx->selected = false;   // until the rebuild succeeds
+        rebuild_factor(ctx, n, true, drift);
+        ctx->selected = true;
+        if (info) *info = ctx->info;
+        return GCB_OK;
+    });
+}
+
 int gcb_certify(gcb_ctx* ctx, double* max_err, double* rms_err) {
     return guard(ctx, [&] {
         if (!ctx->selected) fail(ctx, GCB_E_STATE, "no finished selection");

@@ -1,0 +1,99 @@
+"""Dense FP64 refactorisation on the matrix cores (blocked Cholesky and
+triangular inverse) against the oracle's inverse factor and RC solve."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+import paper_2004_04817_amd as gcb
+from tests.gpu_util import gpu_select
+
+pytestmark = pytest.mark.gpu
+
+
+def ctx_for(p):
+    c = gcb.Context(0)
+    c.set_boundary(p.xyz, p.disp)
+    c.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
+    return c
+
+
+@pytest.mark.parametrize("n", [3, 31, 32, 33, 200, None])
+def test_set_support_matches_oracle_factor(n):
+    p = synth.config_small_ellipsoid(with_volume=False)
+    r = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed)
+    S = r.S if n is None else r.S[:n]
+    c = ctx_for(p)
+    info = c.set_support(S)
+    assert info["nc"] == len(S) and info["iterations"] == 0
+    M = c.get_factor()
+    Mo = oracle.inverse_factor(p.xyz, S, p.radius)
+    assert np.abs(M - Mo).max() <= 1e-10 * np.abs(Mo).max()
+    S2, W = c.get_support()
+    assert np.array_equal(S2, S)
+    Wo = oracle.solve_on_support(p.xyz, S, p.radius, p.disp)
+    assert np.abs(W - Wo).max() <= 1e-9 * np.abs(Wo).max()
+    if n is None:   # the full selected set meets E*: same certificate as the oracle's run
+        assert info["converged"]
+        assert info["final_max_err"] == pytest.approx(r.final_max_err, rel=1e-6)
+    c.close()
+
+
+def test_set_support_then_deform_and_warm_start():
+    p = synth.config_small_ellipsoid(nv=5000)
+    r = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed)
+    c = ctx_for(p)
+    c.set_support(r.S)
+    out = c.deform(p.volume)
+    ref = oracle.interpolate(p.xyz[r.S], r.W, p.radius, p.volume)
+    assert np.abs(out - ref).max() <= 1e-9 * p.max_disp
+    # a warm start from the given set with a new field
+    d2 = np.ascontiguousarray(p.disp[:, [2, 0, 1]] * 1.5)
+    tol = 1e-4 * float(np.sqrt((d2 ** 2).sum(axis=1)).max())
+    c.set_displacement(d2)
+    c.set_params(p.radius, p.m, tol, seed=p.seed, warm_start=True)
+    info = c.select()
+    w = oracle.select(p.xyz, d2, p.radius, p.m, tol, seed=p.seed, warm_S=r.S)
+    S, _ = c.get_support()
+    assert info["nc"] == w.nc and np.array_equal(S, w.S)
+    c.close()
+
+
+def test_refactor_wing_drift_and_same_result():
+    """Re-certify the incrementally grown factor of the 80k wing selection (Nc ~ 1.1e3)."""
+    p = synth.config_wing(with_volume=False)
+    c, info, S, W, _ = gpu_select(p)
+    M0 = c.get_factor()
+    drift, info2 = c.refactor()
+    M1 = c.get_factor()
+    assert drift <= 1e-9, drift
+    assert np.abs(M1 - M0).max() <= 1e-9 * np.abs(M0).max()
+    _, W1 = c.get_support()
+    assert np.abs(W1 - W).max() <= 1e-7 * np.abs(W).max()
+    assert info2["converged"] and info2["final_max_err"] == pytest.approx(info["final_max_err"], rel=1e-4)
+    # against the oracle's factor of the same set (sampled rows: the full dense inverse is 1e6 entries)
+    Mo = oracle.inverse_factor(p.xyz, S, p.radius)
+    assert np.abs(M1 - Mo).max() <= 1e-8 * np.abs(Mo).max()
+    c.close()
+
+
+def test_set_support_errors():
+    p = synth.tiny_problem(nb=30, seed=4, m=2)
+    xyz = np.concatenate([p.xyz, p.xyz[:1]])
+    disp = np.concatenate([p.disp, p.disp[:1]])
+    c = gcb.Context(0)
+    c.set_boundary(xyz, disp)
+    c.set_params(p.radius, 2, 0.0, seed=p.seed)
+    with pytest.raises(gcb.GcbError) as e:        # duplicate coordinates: singular
+        c.set_support([0, 5, 30])
+    assert e.value.code == gcb.GCB_E_SINGULAR
+    with pytest.raises(gcb.GcbError) as e:        # repeated index
+        c.set_support([0, 5, 5])
+    assert e.value.code == gcb.GCB_E_INVALID
+    with pytest.raises(gcb.GcbError) as e:        # nothing to re-certify yet
+        c.refactor()
+    assert e.value.code == gcb.GCB_E_STATE
+    info = c.set_support(np.array([1, 2, 3, 4]))
+    assert info["nc"] == 4
+    c.close()
