@@ -92,3 +92,32 @@ def test_wing_volume_sampled_full_size():
         ref = oracle.interpolate(p.xyz[r.S], r.W, p.radius, p.volume[idx])
         assert np.abs(out[idx] - ref).max() <= 10 * p.tol_abs
     ctx.close()
+
+
+def test_wing_large_full_size():
+    """Precision-scaling case: 300,000-node wing (m = 160, R = 1.5 root chord, E* = 1e-5 max|d|)
+    and 20,000,000 volume points: selection against the oracle (identical or certified by
+    replay), Eq. (6) on 20,000 sampled points against the oracle's FP64 sum."""
+    torch = _torch()
+    from tests.test_gpu_select import assert_same_run
+    p = synth.config_wing_large()
+    ctx, info, S, W, log = gpu_select(p)
+    r = oracle_select(p)
+    print("wing-large: nc", info["nc"], "iters", info["iterations"], "ms", info["ms_select"], "oracle nc", r.nc,
+          flush=True)
+    assert info["converged"] and info["final_max_err"] <= p.tol_abs
+    assert_same_run(p, info, S, W, log, r, p.tol_abs, p.m)
+    x = torch.from_numpy(p.volume).cuda()
+    out = ctx.deform(x)
+    torch.cuda.synchronize()
+    idx = np.random.default_rng(3).choice(p.volume.shape[0], 20000, replace=False)
+    o = out[torch.from_numpy(idx).cuda()].cpu().numpy()
+    md = p.max_disp
+    ref = oracle.interpolate(p.xyz[S], W, p.radius, p.volume[idx])
+    err = np.abs(o - ref).max()
+    print("wing-large volume max err / max|d| (same supports and weights):", err / md, flush=True)
+    assert err <= 1e-9 * md
+    if list(S) == list(r.S):
+        ref_o = oracle.interpolate(p.xyz[r.S], r.W, p.radius, p.volume[idx])
+        assert np.abs(o - ref_o).max() <= 1e-6 * md
+    ctx.close()
