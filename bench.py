@@ -256,6 +256,28 @@ def main():
                      "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs_volume,
                      "launch_ms": vol_avg_ms},
     }
+    # Eq. (6) in FP32 (GCB_PREC_FP32_EVAL) on the same supports: time and error against the FP64 output
+    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed, precision=gcb.GCB_PREC_FP32_EVAL)
+    ctx.select()
+    out32 = torch.empty_like(vol)
+    ctx.deform(vol, out=out32)
+    ts = []
+    for _ in range(3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.deform(vol, out=out32)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms32 = float(np.mean(ts))
+    err32 = float((out32 - out).abs().max().item()) / p.max_disp
+    rec["volume_fp32_eval"] = {"ms": ms32, "pair_evals_per_s": pairs_volume / (ms32 * 1e-3),
+                               "speedup_vs_fp64": vol_avg_ms / ms32, "max_err_vs_fp64_rel_max_d": err32,
+                               "meets_1e-6_max_d": err32 <= 1e-6}
+    del out32
+    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
+    ctx.select()
     if a.modes > 0 and a.config == "wing":
         import synth
         modes = torch.from_numpy(synth.config_modes(p, a.modes)).to(dev)

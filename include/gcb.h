@@ -48,11 +48,13 @@ enum gcb_status {
 enum gcb_mem { GCB_MEM_HOST = 0, GCB_MEM_DEVICE = 1 };
 enum gcb_dtype { GCB_F32 = 0, GCB_F64 = 1 };
 
-/* Evaluation precision of the interpolant sweeps (Eq. 1 / Eq. 6).  The
- * support-system factor and the final all-node check are FP64 in both. */
+/* Evaluation precision of the interpolant (Eq. 1 / Eq. 6).  The support-
+ * system factor, the greedy's group sweeps and decisions, and the all-node
+ * certificate are FP64 in both. */
 enum gcb_precision {
-    GCB_PREC_FP64 = 0,       /* every sweep in FP64 */
-    GCB_PREC_FP32_EVAL = 1   /* FP32 screening sweeps, FP64 re-check of candidates */
+    GCB_PREC_FP64 = 0,       /* every evaluation in FP64 */
+    GCB_PREC_FP32_EVAL = 1   /* gcb_deform evaluates Eq. (6) in FP32 (scaled coordinates, weights and
+                              * phi in FP32; chunks of 32 supports summed in FP32, chunk sums in FP64) */
 };
 
 typedef struct {

@@ -142,6 +142,10 @@ bool launch_deform_multi(hipStream_t s, const Support& sp, int n, int rc, const 
                          int out_f64);
 void launch_transpose_factor(hipStream_t s, const double* Mr, double* Mc, int n, int64_t cap);
 void launch_certify(hipStream_t s, const Boundary& bd, const Support& sp, int n, double* red, double* out);
+// FP32 evaluation of Eq. (6) (FP32 copies of the supports and weights are
+// refreshed first; sp.fsx..fwz must hold sp.cap floats).
+void launch_volume32(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,
+                     void* out, int out_f64);
 void launch_volume(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,
                    void* out, int out_f64);
 

@@ -985,6 +985,79 @@ __global__ __launch_bounds__(kBlock) void k_volume64(int64_t nv, const TIn* __re
     }
 }
 
+// FP32 evaluation of Eq. (6): coordinates (scaled), weights and phi in FP32,
+// each chunk of kChunk32 supports summed in FP32 and the chunk sums carried
+// in FP64 (blocked compensation), so the summation adds little to the FP32
+// error of phi itself.
+constexpr int kChunk32 = 32;
+
+__device__ __forceinline__ float wendland_r2_f32(float r2) {
+    const float x = fmaxf(r2, 1e-30f);
+    const float eta = x * __builtin_amdgcn_rsqf(x);
+    const float t = fminf(fmaxf(1.0f - eta, 0.0f), 1.0f);
+    const float t2 = t * t;
+    return (t2 * t2) * fmaf(-4.0f, t, 5.0f);
+}
+
+template <typename TIn, typename TOut>
+__global__ __launch_bounds__(kBlock) void k_volume32(int64_t nv, const TIn* __restrict__ xyz, double inv_r, int n,
+                                                     const float* __restrict__ fsx, const float* __restrict__ fsy,
+                                                     const float* __restrict__ fsz, const float* __restrict__ fwx,
+                                                     const float* __restrict__ fwy, const float* __restrict__ fwz,
+                                                     TOut* __restrict__ out) {
+    const int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    const bool live = t < nv;
+    const int64_t tt = live ? t : nv - 1;
+    const float tx = (float)((double)xyz[3 * tt] * inv_r);
+    const float ty = (float)((double)xyz[3 * tt + 1] * inv_r);
+    const float tz = (float)((double)xyz[3 * tt + 2] * inv_r);
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int j0 = 0; j0 < n; j0 += kChunk32) {
+        const int j1 = min(n, j0 + kChunk32);
+        float bx = 0.0f, by = 0.0f, bz = 0.0f;
+        int j = j0;
+        for (; j + 4 <= j1; j += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float dx = tx - fsx[j + u], dy = ty - fsy[j + u], dz = tz - fsz[j + u];
+                const float phi = wendland_r2_f32(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+                bx = fmaf(fwx[j + u], phi, bx);
+                by = fmaf(fwy[j + u], phi, by);
+                bz = fmaf(fwz[j + u], phi, bz);
+            }
+        }
+        for (; j < j1; ++j) {
+            const float dx = tx - fsx[j], dy = ty - fsy[j], dz = tz - fsz[j];
+            const float phi = wendland_r2_f32(fmaf(dz, dz, fmaf(dy, dy, dx * dx)));
+            bx = fmaf(fwx[j], phi, bx);
+            by = fmaf(fwy[j], phi, by);
+            bz = fmaf(fwz[j], phi, bz);
+        }
+        ax += (double)bx;
+        ay += (double)by;
+        az += (double)bz;
+    }
+    if (live) {
+        out[3 * t] = (TOut)ax;
+        out[3 * t + 1] = (TOut)ay;
+        out[3 * t + 2] = (TOut)az;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_support_f32(int n, SupportView sv, float* __restrict__ fsx,
+                                                        float* __restrict__ fsy, float* __restrict__ fsz,
+                                                        float* __restrict__ fwx, float* __restrict__ fwy,
+                                                        float* __restrict__ fwz) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    fsx[j] = (float)sv.sx[j];
+    fsy[j] = (float)sv.sy[j];
+    fsz[j] = (float)sv.sz[j];
+    fwx[j] = (float)sv.wx[j];
+    fwy[j] = (float)sv.wy[j];
+    fwz[j] = (float)sv.wz[j];
+}
+
 // Eq. (6) for several surfaces in one launch: block b belongs to surface s
 // with map.off[s] <= b < map.off[s+1].
 template <typename TIn, typename TOut>
@@ -1190,6 +1263,24 @@ template <typename TIn, typename TOut>
 static void vol(hipStream_t s, int64_t nv, const void* xyz, double inv_r, SupportView sv, int n, void* out) {
     const unsigned g = (unsigned)((nv + kBlock - 1) / kBlock);
     GCB_LAUNCH((k_volume64<TIn, TOut>), dim3(g), dim3(kBlock), s, nv, (const TIn*)xyz, inv_r, sv, n, (TOut*)out);
+}
+
+template <typename TIn, typename TOut>
+static void vol32(hipStream_t s, int64_t nv, const void* xyz, double inv_r, const Support& sp, int n, void* out) {
+    const unsigned g = (unsigned)((nv + kBlock - 1) / kBlock);
+    GCB_LAUNCH((k_volume32<TIn, TOut>), dim3(g), dim3(kBlock), s, nv, (const TIn*)xyz, inv_r, n, sp.fsx, sp.fsy,
+               sp.fsz, sp.fwx, sp.fwy, sp.fwz, (TOut*)out);
+}
+
+void launch_volume32(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,
+                     void* out, int out_f64) {
+    if (n > 0)
+        GCB_LAUNCH(k_support_f32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), s, n, view(sp), sp.fsx,
+                   sp.fsy, sp.fsz, sp.fwx, sp.fwy, sp.fwz);
+    if (in_f64 && out_f64) vol32<double, double>(s, nv, xyz, inv_r, sp, n, out);
+    else if (in_f64) vol32<double, float>(s, nv, xyz, inv_r, sp, n, out);
+    else if (out_f64) vol32<float, double>(s, nv, xyz, inv_r, sp, n, out);
+    else vol32<float, float>(s, nv, xyz, inv_r, sp, n, out);
 }
 
 void launch_volume(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,

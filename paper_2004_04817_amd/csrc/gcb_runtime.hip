@@ -1038,8 +1038,18 @@ int gcb_deform(gcb_ctx* ctx, int64_t nv, const void* xyz, int in_dtype, void* ou
             din = ctx->tmp;
             dout = static_cast<char*>(ctx->tmp) + in_b;
         }
-        launch_volume(ctx->stream, nv, din, in_dtype == GCB_F64, ctx->bd.inv_r, ctx->sp, (int)ctx->info.nc, dout,
-                      out_dtype == GCB_F64);
+        if (ctx->params.precision == GCB_PREC_FP32_EVAL) {
+            Support& sp = ctx->sp;
+            if (!sp.fsx) {
+                dalloc(ctx, sp.fsx, sp.cap); dalloc(ctx, sp.fsy, sp.cap); dalloc(ctx, sp.fsz, sp.cap);
+                dalloc(ctx, sp.fwx, sp.cap); dalloc(ctx, sp.fwy, sp.cap); dalloc(ctx, sp.fwz, sp.cap);
+            }
+            launch_volume32(ctx->stream, nv, din, in_dtype == GCB_F64, ctx->bd.inv_r, sp, (int)ctx->info.nc, dout,
+                            out_dtype == GCB_F64);
+        } else {
+            launch_volume(ctx->stream, nv, din, in_dtype == GCB_F64, ctx->bd.inv_r, ctx->sp, (int)ctx->info.nc, dout,
+                          out_dtype == GCB_F64);
+        }
         HIPCHK(ctx, hipGetLastError());
         if (mem == GCB_MEM_HOST) {
             HIPCHK(ctx, hipMemcpyAsync(out, dout, out_b, hipMemcpyDeviceToHost, ctx->stream));

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
+import paper_2004_04817_amd as gcb
 import synth
 from tests.gpu_util import gpu_select, oracle_select
 
@@ -121,3 +122,35 @@ def test_wing_large_full_size():
         ref_o = oracle.interpolate(p.xyz[r.S], r.W, p.radius, p.volume[idx])
         assert np.abs(o - ref_o).max() <= 1e-6 * md
     ctx.close()
+
+
+def test_fp32_evaluation_accuracy_and_dtypes():
+    """GCB_PREC_FP32_EVAL: Eq. (6) in FP32 with FP64 chunk sums.  Its error is that
+    of phi and the coordinates in FP32, amplified by the weights of the
+    ill-conditioned support system: bounded here by 1e-3 max|d| (the FP64 path
+    meets 1e-11), and FP32 in / FP64 out does not change it."""
+    torch = _torch()
+    p = synth.config_small_ellipsoid(nv=20000)
+    c = gcb.Context(0)
+    c.set_boundary(p.xyz, p.disp)
+    c.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
+    c.select()
+    S, W = c.get_support()
+    ref = oracle.interpolate(p.xyz[S], W, p.radius, p.volume)
+    x = torch.from_numpy(p.volume).cuda()
+    o64 = c.deform(x).cpu().numpy()
+    c.set_params(p.radius, p.m, p.tol_abs, seed=p.seed, precision=gcb.GCB_PREC_FP32_EVAL)
+    c.select()
+    o32 = c.deform(x).cpu().numpy()
+    o32f = c.deform(x.float(), out_dtype=torch.float32).cpu().numpy().astype(np.float64)
+    md = p.max_disp
+    e64 = np.abs(o64 - ref).max() / md
+    e32 = np.abs(o32 - ref).max() / md
+    print("FP64 eval err / max|d|:", e64, " FP32 eval err / max|d|:", e32, flush=True)
+    assert e64 <= 1e-11
+    assert e32 <= 1e-3
+    assert np.abs(o32f - ref).max() / md <= 1e-3
+    # support nodes: the FP32 interpolant still reproduces the field to FP32 accuracy
+    o_s = c.deform(np.ascontiguousarray(p.xyz[S]))
+    assert np.abs(o_s - p.disp[S]).max() / md <= 1e-3
+    c.close()
