@@ -256,6 +256,15 @@ def main():
                      "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs_volume,
                      "launch_ms": vol_avg_ms},
     }
+    # dense FP64 refactorisation of the selected support system (blocked Cholesky + triangular inverse, MFMA)
+    drift, rinfo = ctx.refactor()
+    drift, rinfo = ctx.refactor()
+    rflops = 2.0 * nc ** 3 / 3.0
+    rec["refactor"] = {"nc": nc, "ms": rinfo["ms_select"], "drift": drift,
+                       "tflops": rflops / (rinfo["ms_select"] * 1e-3) / 1e12,
+                       "flops": "Nc^3/3 (Cholesky) + Nc^3/3 (triangular inverse)"}
+    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
+    ctx.select()
     # Eq. (6) in FP32 (GCB_PREC_FP32_EVAL) on the same supports: time and error against the FP64 output
     ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed, precision=gcb.GCB_PREC_FP32_EVAL)
     ctx.select()

@@ -36,41 +36,65 @@ __global__ __launch_bounds__(kBlock) void k_assemble(int n, int np, const double
     A[x] = v;
 }
 
-// Diagonal block of step k0 (already updated by the earlier steps):
-// unblocked Cholesky in LDS, written back in place (one workgroup).
-__global__ __launch_bounds__(kBlock) void k_chol_diag(int np, int k0, double* __restrict__ A,
-                                                      int32_t* __restrict__ bad) {
-    __shared__ double D[kDB][kDB + 1];
-    const int tid = threadIdx.x;
-    for (int x = tid; x < kDB * kDB; x += kBlock) D[x / kDB][x % kDB] = A[(size_t)(k0 + x / kDB) * np + k0 + x % kDB];
-    __syncthreads();
-    for (int c = 0; c < kDB; ++c) {
-        if (tid == 0) {
-            const double d = D[c][c];
-            if (!(d > kSingularTol)) bad[0] = 1;
-            D[c][c] = sqrt(d > kSingularTol ? d : 1.0);
-        }
-        __syncthreads();
-        if (tid > c && tid < kDB) D[tid][c] /= D[c][c];
-        __syncthreads();
-        for (int x = tid; x < kDB * kDB; x += kBlock) {
-            const int i = x / kDB, j = x % kDB;
-            if (j > c && i >= j) D[i][j] -= D[i][c] * D[j][c];
-        }
-        __syncthreads();
-    }
-    for (int x = tid; x < kDB * kDB; x += kBlock) {
-        const int i = x / kDB, j = x % kDB;
-        A[(size_t)(k0 + i) * np + k0 + j] = j <= i ? D[i][j] : 0.0;
-    }
+// The value of v held by lane `lane` (a constant), broadcast through scalar registers.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
 }
 
-// Panel of step k0: rows below the diagonal block solve x L_kk^T = a, one row
-// per thread (the factored L_kk comes from the previous launch).
-__global__ __launch_bounds__(kBlock) void k_chol_panel(int np, int k0, double* __restrict__ A) {
+// Step k0 of the Cholesky factorisation.  Wave 0 factors the diagonal block
+// (already updated by the earlier steps) in registers, one row per lane, with
+// the column entries broadcast across lanes; the factored block goes to LDS
+// and, from workgroup 0, to Dbuf (the diagonal blocks of L are read from there
+// later; A's own diagonal block is only read in this launch, so no workgroup
+// overwrites what another still reads).  Then each workgroup solves kBlock
+// rows of the panel below: x L_kk^T = a.
+__global__ __launch_bounds__(kBlock) void k_chol_step(int np, int k0, double* __restrict__ A,
+                                                      double* __restrict__ Dbuf, int32_t* __restrict__ bad) {
     __shared__ double D[kDB][kDB + 1];
+    __shared__ double Rd[kDB];
     const int tid = threadIdx.x;
-    for (int x = tid; x < kDB * kDB; x += kBlock) D[x / kDB][x % kDB] = A[(size_t)(k0 + x / kDB) * np + k0 + x % kDB];
+    if (tid < 64) {
+        const int lane = tid;
+        const int row = lane < kDB ? lane : kDB - 1;
+        double a[kDB];
+        const double* Ar = A + (size_t)(k0 + row) * np + k0;
+#pragma unroll
+        for (int c = 0; c < kDB; ++c) a[c] = (c <= lane && lane < kDB) ? Ar[c] : 0.0;
+        int sing = 0;
+#pragma unroll
+        for (int c = 0; c < kDB; ++c) {
+            double d = readlane_f64(a[c], c);
+            if (!(d > kSingularTol)) {
+                sing = 1;
+                d = 1.0;
+            }
+            // 1/sqrt(d) by two Newton steps on the hardware estimate; L_cc = d / sqrt(d)
+            double rs = __builtin_amdgcn_rsq(d);
+            rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
+            rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
+            if (lane == c) a[c] = d * rs;
+            if (lane > c) a[c] *= rs;
+#pragma unroll
+            for (int j = c + 1; j < kDB; ++j) {
+                const double ljc = readlane_f64(a[c], j);
+                if (lane >= j) a[j] = fma(-a[c], ljc, a[j]);
+            }
+        }
+        if (lane < kDB) {
+#pragma unroll
+            for (int c = 0; c < kDB; ++c) D[lane][c] = c <= lane ? a[c] : 0.0;
+            if (blockIdx.x == 0) {
+                double* Db = Dbuf + (size_t)(k0 / kDB) * kDB * kDB + (size_t)lane * kDB;
+#pragma unroll
+                for (int c = 0; c < kDB; ++c) Db[c] = c <= lane ? a[c] : 0.0;
+            }
+        }
+        if (lane == 0 && sing) bad[0] = 1;
+    }
+    __syncthreads();
+    if (tid < kDB) Rd[tid] = 1.0 / D[tid][tid];
     __syncthreads();
     const int r = k0 + kDB + blockIdx.x * kBlock + tid;
     if (r >= np) return;
@@ -78,12 +102,12 @@ __global__ __launch_bounds__(kBlock) void k_chol_panel(int np, int k0, double* _
     double x[kDB];
 #pragma unroll
     for (int c = 0; c < kDB; ++c) x[c] = Ar[c];
+    // right-looking: once x_c is known, every later entry is updated (independent FMAs)
 #pragma unroll
     for (int c = 0; c < kDB; ++c) {
-        double v = x[c];
+        x[c] *= Rd[c];
 #pragma unroll
-        for (int t = 0; t < c; ++t) v -= x[t] * D[c][t];
-        x[c] = v / D[c][c];
+        for (int t = c + 1; t < kDB; ++t) x[t] = fma(-x[c], D[t][c], x[t]);
     }
 #pragma unroll
     for (int c = 0; c < kDB; ++c) Ar[c] = x[c];
@@ -119,14 +143,14 @@ __global__ __launch_bounds__(kBlock) void k_chol_update(int np, int k0, double* 
     for (int r = 0; r < 4; ++r) A[(size_t)(R0 + lk + 4 * r) * np + C0 + li] -= acc[r];
 }
 
-// Diagonal blocks of M: M_jj = L_jj^-1, one workgroup per block; thread c
-// forms column c by forward substitution.
-__global__ __launch_bounds__(kBlock) void k_trtri_diag(int np, const double* __restrict__ L, double* __restrict__ M) {
+// Diagonal blocks of M: M_jj = L_jj^-1 (L_jj from Dbuf), one workgroup per
+// block; thread c forms column c by forward substitution.
+__global__ __launch_bounds__(kBlock) void k_trtri_diag(int np, const double* __restrict__ Dbuf, double* __restrict__ M) {
     __shared__ double Ld[kDB][kDB + 1];
     __shared__ double X[kDB][kDB + 1];
     const int j0 = blockIdx.x * kDB;
-    for (int x = threadIdx.x; x < kDB * kDB; x += kBlock)
-        Ld[x / kDB][x % kDB] = L[(size_t)(j0 + x / kDB) * np + j0 + x % kDB];
+    const double* Db = Dbuf + (size_t)blockIdx.x * kDB * kDB;
+    for (int x = threadIdx.x; x < kDB * kDB; x += kBlock) Ld[x / kDB][x % kDB] = Db[x];
     __syncthreads();
     const int c = threadIdx.x;
     if (c < kDB) {
@@ -155,13 +179,25 @@ __global__ __launch_bounds__(kBlock) void k_trtri_off(int np, int s, const doubl
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int qi = wave >> 1, qj = wave & 1;
     const int li = lane & 15, lk = lane >> 4;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-    const double* La = L + (size_t)(kDB * i + 16 * qi + li) * np;
-    for (int k = kDB * j; k < kDB * i; k += 4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(La[k + lk], M[(size_t)(k + lk) * np + kDB * j + 16 * qj + li], acc,
-                                                   0, 0, 0);
+    // K = 32 s in steps of 16: four independent accumulator chains, loads issued together
+    d4 acc[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) T[16 * qi + lk + 4 * r][16 * qj + li] = acc[r];
+    for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+    const double* La = L + (size_t)(kDB * i + 16 * qi + li) * np;
+    const double* Mb = M + kDB * j + 16 * qj + li;
+    for (int k = kDB * j; k < kDB * i; k += 16) {
+        double a[4], b[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a[q] = La[k + 4 * q + lk];
+            b[q] = Mb[(size_t)(k + 4 * q + lk) * np];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc[q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        T[16 * qi + lk + 4 * r][16 * qj + li] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
     __syncthreads();
     d4 out = {0.0, 0.0, 0.0, 0.0};
     const double* Mi = M + (size_t)(kDB * i + 16 * qi + li) * np + kDB * i;
@@ -234,7 +270,8 @@ int dense_padded(int n) { return (n + kDB - 1) / kDB * kDB; }
 
 int dense_pack_blocks() { return 256; }
 
-void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, int32_t* bad) {
+void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, double* Dbuf,
+                           int32_t* bad) {
     const int np = dense_padded(n);
     const int nbk = np / kDB;
     const int64_t cnt = (int64_t)np * np;
@@ -244,13 +281,12 @@ void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, d
         const int k0 = kb * kDB;
         const int rows = np - k0 - kDB;
         const unsigned g = (unsigned)std::max(1, (rows + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(kBlock), 0, s, np, k0, A, bad);
-        if (rows > 0) hipLaunchKernelGGL(k_chol_panel, dim3(g), dim3(kBlock), 0, s, np, k0, A);
+        hipLaunchKernelGGL(k_chol_step, dim3(g), dim3(kBlock), 0, s, np, k0, A, Dbuf, bad);
         const int nt = nbk - kb - 1;
         if (nt > 0) hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(kBlock), 0, s, np, k0, A);
     }
     // blocks of Md above the diagonal are never read: no clearing needed
-    hipLaunchKernelGGL(k_trtri_diag, dim3((unsigned)nbk), dim3(kBlock), 0, s, np, A, Md);
+    hipLaunchKernelGGL(k_trtri_diag, dim3((unsigned)nbk), dim3(kBlock), 0, s, np, Dbuf, Md);
     for (int d = 1; d < nbk; ++d)
         hipLaunchKernelGGL(k_trtri_off, dim3((unsigned)(nbk - d)), dim3(kBlock), 0, s, np, d, A, Md);
 }

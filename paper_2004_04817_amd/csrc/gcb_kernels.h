@@ -128,11 +128,14 @@ bool launch_support_weights(hipStream_t s, Support& sp, int n, const double* dis
 void launch_mark_support(hipStream_t s, const Boundary& bd, const Support& sp, int n);
 
 // Dense FP64 refactorisation (matrix cores): A, Md hold dense_padded(n)^2
-// doubles each; on return A = L (Cholesky of Phi_S) and Md = L^-1, and
-// *bad = 1 (set, never cleared) if a pivot was not above kSingularTol.
+// doubles each, Dbuf dense_padded(n) * 32; on return the strictly lower
+// blocks of A and the diagonal blocks in Dbuf hold L (Cholesky of Phi_S), Md
+// holds L^-1, and *bad = 1 (set, never cleared) if a pivot was not above
+// kSingularTol.
 int dense_padded(int n);
 int dense_pack_blocks();
-void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, int32_t* bad);
+void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, double* Dbuf,
+                           int32_t* bad);
 // Packed rows of Md into Mp (may equal old); with old, red[2b], red[2b+1]
 // get per-block max |new - old| and max |old| (dense_pack_blocks() blocks).
 void launch_pack_factor(hipStream_t s, int n, const double* Md, double* Mp, const double* old, double* red);

@@ -14,6 +14,14 @@ namespace gcb {
 #define GCB_LAUNCH(kern, grid, block, stream, ...) hipLaunchKernelGGL(kern, grid, block, 0, stream, __VA_ARGS__)
 
 // Accumulate sum_{j in [s0, s1)} w_j phi(|t - s_j|) for one target per lane.
+// VOL: the volume variant of phi (one square-root Newton step); otherwise the
+// full-accuracy phi of the greedy and the certificate.
+template <bool VOL>
+__device__ __forceinline__ double phi_r2(double r2) {
+    return VOL ? wendland_r2_vol(r2) : wendland_r2(r2);
+}
+
+template <bool VOL>
 __device__ __forceinline__ void accumulate64(double tx, double ty, double tz, int s0, int s1,
                                              const double* __restrict__ sx, const double* __restrict__ sy,
                                              const double* __restrict__ sz, const double* __restrict__ wx,
@@ -24,7 +32,7 @@ __device__ __forceinline__ void accumulate64(double tx, double ty, double tz, in
     for (; j + 4 <= s1; j += 4) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const double phi = wendland_r2(dist2(tx, ty, tz, sx[j + u], sy[j + u], sz[j + u]));
+            const double phi = phi_r2<VOL>(dist2(tx, ty, tz, sx[j + u], sy[j + u], sz[j + u]));
             ax = fma(wx[j + u], phi, ax);
             ay = fma(wy[j + u], phi, ay);
             az = fma(wz[j + u], phi, az);
@@ -32,7 +40,7 @@ __device__ __forceinline__ void accumulate64(double tx, double ty, double tz, in
     }
 #pragma unroll 1
     for (; j < s1; ++j) {
-        const double phi = wendland_r2(dist2(tx, ty, tz, sx[j], sy[j], sz[j]));
+        const double phi = phi_r2<VOL>(dist2(tx, ty, tz, sx[j], sy[j], sz[j]));
         ax = fma(wx[j], phi, ax);
         ay = fma(wy[j], phi, ay);
         az = fma(wz[j], phi, az);
@@ -926,7 +934,7 @@ __global__ __launch_bounds__(kBlock) void k_certify(int64_t nb, const double* __
     const bool live = t < nb;
     const int64_t tt = live ? t : nb - 1;
     double ax = 0.0, ay = 0.0, az = 0.0;
-    accumulate64(px[tt], py[tt], pz[tt], 0, n, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
+    accumulate64<false>(px[tt], py[tt], pz[tt], 0, n, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
     double e2 = 0.0;
     if (live) {
         const double ex = ax - pdx[t], ey = ay - pdy[t], ez = az - pdz[t];
@@ -977,7 +985,7 @@ __global__ __launch_bounds__(kBlock) void k_volume64(int64_t nv, const TIn* __re
     const double ty = (double)xyz[3 * tt + 1] * inv_r;
     const double tz = (double)xyz[3 * tt + 2] * inv_r;
     double ax = 0.0, ay = 0.0, az = 0.0;
-    accumulate64(tx, ty, tz, 0, n, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
+    accumulate64<true>(tx, ty, tz, 0, n, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
     if (live) {
         out[3 * t] = (TOut)ax;
         out[3 * t + 1] = (TOut)ay;
@@ -1072,7 +1080,7 @@ __global__ __launch_bounds__(kBlock) void k_volume_batch(const VolDesc* __restri
     const double ty = (double)xyz[3 * tt + 1] * d.inv_r;
     const double tz = (double)xyz[3 * tt + 2] * d.inv_r;
     double ax = 0.0, ay = 0.0, az = 0.0;
-    accumulate64(tx, ty, tz, 0, d.n, d.sv.sx, d.sv.sy, d.sv.sz, d.sv.wx, d.sv.wy, d.sv.wz, ax, ay, az);
+    accumulate64<true>(tx, ty, tz, 0, d.n, d.sv.sx, d.sv.sy, d.sv.sz, d.sv.wx, d.sv.wy, d.sv.wz, ax, ay, az);
     if (live) {
         TOut* out = static_cast<TOut*>(d.out);
         out[3 * t] = (TOut)ax;
