@@ -118,7 +118,11 @@ def multi_surface(count, dev):
             c.deform(v, out=o)
         return infos
 
+    # tile shapes of the batched launches picked by the autotuner on this device and workload
+    from paper_2004_04817_amd import autotune
+    best, times = autotune.tune_batch(ctxs)
     batch = gcb.Batch(0)
+    batch.set_layout(*best)
 
     def batched():
         infos = batch.select(ctxs)
@@ -139,6 +143,9 @@ def multi_surface(count, dev):
                      "iterations_sum": sum(i["iterations"] for i in infos),
                      "all_converged": all(bool(i["converged"]) for i in infos)}
     res["speedup"] = res["one_at_a_time"]["ms"] / res["batched"]["ms"]
+    res["autotune"] = {"chosen": {"sweep_targets_per_lane": best[0], "factor_chunks_per_wave": best[1]},
+                       "select_ms": {f"tpl{c[0]}_rpw{c[1]}": 1e3 * t for c, t in times.items()},
+                       "note": "0 = automatic (narrow layouts below 4 running surfaces, wide above)"}
     res.update({"surfaces": count, "nb_sum": sum(q.nb for q in probs), "nv_sum": sum(v.shape[0] for v in vols),
                 "precision": "fp64"})
     batch.close()

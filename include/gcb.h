@@ -208,6 +208,15 @@ int gcb_batch_create(gcb_batch **out, int device, void *hip_stream);
 void gcb_batch_destroy(gcb_batch *b);   /* NULL-safe; contexts are not touched */
 const char *gcb_batch_last_error(const gcb_batch *b);
 
+/* Launch layout (tile shapes) of the batched iterations, chosen by an
+ * autotuner or left automatic.  sweep_tpl: targets per lane in the group
+ * sweeps (1, 2 or 4 with one wave per target group; 0: automatic);
+ * factor_rpw: 16-row chunks of M per factor wave (1 or 4; 0: automatic);
+ * lone_graph: 1 (default) lets a step with a single running context replay
+ * that context's captured chunk of iterations.  factor_rpw changes no result;
+ * sweep_tpl changes only the summation order of the group errors. */
+int gcb_batch_set_layout(gcb_batch *b, int32_t sweep_tpl, int32_t factor_rpw, int32_t lone_graph);
+
 /* Start the selection of ctx (boundary and parameters set, same device as
  * the batch): partition and staging, the three starting nodes.  ctx is
  * switched to the batch's stream.  Errors are those of gcb_select; the

@@ -32,7 +32,7 @@ EXPORTS = ["gcb_version", "gcb_partition", "gcb_create", "gcb_destroy", "gcb_las
            "gcb_get_support", "gcb_get_log", "gcb_deform", "gcb_deform_multi", "gcb_certify",
            "gcb_set_support", "gcb_refactor", "gcb_get_factor",
            "gcb_batch_create", "gcb_batch_destroy", "gcb_batch_last_error", "gcb_batch_begin", "gcb_batch_step",
-           "gcb_batch_end", "gcb_select_batch", "gcb_deform_batch",
+           "gcb_batch_end", "gcb_select_batch", "gcb_deform_batch", "gcb_batch_set_layout",
            "gcb_server_clock", "gcb_server_create", "gcb_server_destroy", "gcb_server_last_error",
            "gcb_server_submit", "gcb_server_progress", "gcb_server_result", "gcb_server_memory"]
 
@@ -122,6 +122,7 @@ def lib():
         L.gcb_batch_end.argtypes = [vp, vp, C.POINTER(SelectInfo)]
         L.gcb_select_batch.argtypes = [vp, vp, i32, vp]
         L.gcb_deform_batch.argtypes = [vp, vp, i32, vp, vp, C.c_int, vp, C.c_int]
+        L.gcb_batch_set_layout.argtypes = [vp, i32, i32, i32]
         L.gcb_server_clock.restype = C.c_double
         L.gcb_server_create.argtypes = [C.POINTER(vp), C.c_int, vp, C.c_uint64, i32, i32]
         L.gcb_server_destroy.argtypes = [vp]
@@ -432,6 +433,12 @@ class Batch:
     @staticmethod
     def _handles(ctxs):
         return (C.c_void_p * len(ctxs))(*[c._h.value for c in ctxs])
+
+    def set_layout(self, sweep_tpl: int = 0, factor_rpw: int = 0, lone_graph: bool = True):
+        """Tile shapes of the batched iterations (0: automatic); see paper_2004_04817_amd.autotune."""
+        rc = lib().gcb_batch_set_layout(self._h, int(sweep_tpl), int(factor_rpw), 1 if lone_graph else 0)
+        if rc != GCB_OK:
+            self._raise(rc)
 
     def begin(self, ctx: Context):
         rc = lib().gcb_batch_begin(self._h, ctx._h)

@@ -422,6 +422,44 @@ void select_end(gcb_ctx* ctx, gcb_select_info* info) {
     if (info) *info = inf;
 }
 
+// Iterations per captured chunk: a multiple of m (every chunk starts at the same
+// phase of k mod m), about 64; 0 when chunks are not captured.
+int graph_chunk(const gcb_ctx* ctx) {
+    const int m = ctx->params.m;
+    return (g_tuning.use_graph && m <= 256) ? m * ((64 + m - 1) / m) : 0;
+}
+
+// Enqueue `chunk` iterations from ctx->k_host as one captured graph (captured
+// again when anything it baked in has changed).
+void launch_chunk(gcb_ctx* ctx, int chunk) {
+    const gcb_params& p = ctx->params;
+    const int m = p.m;
+    const int64_t k = ctx->k_host;
+    const IterCtx ic = make_ic(ctx);
+    int64_t tol_bits;
+    std::memcpy(&tol_bits, &p.tol_abs, sizeof(tol_bits));
+    // everything the captured launches baked in: phase, capacities, buffers, parameters
+    const std::vector<int64_t> full = {k % m, m, chunk, ctx->sp.cap, ctx->log_cap, p.nc_max, tol_bits,
+                                       (int64_t)ctx->alloc_gen, (int64_t)(intptr_t)ctx->stream};
+    if (!ctx->chunk_exec || ctx->chunk_key != full) {
+        if (ctx->chunk_exec) (void)hipGraphExecDestroy(ctx->chunk_exec);
+        ctx->chunk_exec = nullptr;
+        if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        hipGraph_t graph;
+        HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        const int n_ub = (int)std::min<int64_t>(p.nc_max, ctx->sp.cap);
+        for (int it = 0; it < chunk; ++it) launch_iteration(ctx->cap_stream, ic, (int)((k + it) % m), n_ub);
+        HIPCHK(ctx, hipStreamEndCapture(ctx->cap_stream, &graph));
+        hipError_t e = hipGraphInstantiate(&ctx->chunk_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(ctx, e);
+        ctx->chunk_key = full;
+    }
+    HIPCHK(ctx, hipGraphLaunch(ctx->chunk_exec, ctx->stream));
+    HIPCHK(ctx, hipGetLastError());
+    ctx->k_host = k + chunk;
+}
+
 void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     select_begin(ctx);
     const gcb_params& p = ctx->params;
@@ -429,43 +467,24 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     // launch.  A chunk of C iterations with C a multiple of m starts at the
     // same phase of k mod m every time and is captured once into a graph.
     const int m = p.m;
-    const bool use_graph = g_tuning.use_graph && m <= 256;
-    const int chunk = use_graph ? m * ((64 + m - 1) / m) : 64;
+    const int gchunk = graph_chunk(ctx);
+    const int chunk = gchunk > 0 ? gchunk : 64;
     for (;;) {
         HIPCHK(ctx, hipMemcpyAsync(ctx->state_pin, ctx->state, sizeof(GState), hipMemcpyDeviceToHost, ctx->stream));
         sync(ctx);
         if (!select_poll(ctx, chunk)) break;
-        const int64_t k = ctx->k_host;
-        const IterCtx ic = make_ic(ctx);
-        if (use_graph) {
-            int64_t tol_bits;
-            std::memcpy(&tol_bits, &p.tol_abs, sizeof(tol_bits));
-            // everything the captured launches baked in: phase, capacities, buffers, parameters
-            const std::vector<int64_t> full = {k % m, m, chunk, ctx->sp.cap, ctx->log_cap, p.nc_max, tol_bits,
-                                               (int64_t)ctx->alloc_gen, (int64_t)(intptr_t)ctx->stream};
-            if (!ctx->chunk_exec || ctx->chunk_key != full) {
-                if (ctx->chunk_exec) (void)hipGraphExecDestroy(ctx->chunk_exec);
-                ctx->chunk_exec = nullptr;
-                if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
-                hipGraph_t graph;
-                HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
-                const int n_ub = (int)std::min<int64_t>(p.nc_max, ctx->sp.cap);
-                for (int it = 0; it < chunk; ++it) launch_iteration(ctx->cap_stream, ic, (int)((k + it) % m), n_ub);
-                HIPCHK(ctx, hipStreamEndCapture(ctx->cap_stream, &graph));
-                hipError_t e = hipGraphInstantiate(&ctx->chunk_exec, graph, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(graph);
-                HIPCHK(ctx, e);
-                ctx->chunk_key = full;
-            }
-            HIPCHK(ctx, hipGraphLaunch(ctx->chunk_exec, ctx->stream));
+        if (gchunk > 0) {
+            launch_chunk(ctx, chunk);
         } else {
+            const int64_t k = ctx->k_host;
+            const IterCtx ic = make_ic(ctx);
             for (int it = 0; it < chunk; ++it) {
                 const int n_ub = (int)n_upper(ctx, ctx->state_h.n, it + 1);
                 launch_iteration(ctx->stream, ic, (int)((k + it) % m), n_ub);
             }
+            HIPCHK(ctx, hipGetLastError());
+            ctx->k_host = k + chunk;
         }
-        HIPCHK(ctx, hipGetLastError());
-        ctx->k_host = k + chunk;
     }
     select_end(ctx, info);
 }
@@ -511,6 +530,9 @@ struct gcb_batch {
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    bool lone_graph = true;   // a step with one running context replays its captured chunk
+    int sweep_tpl = 0;        // 0: automatic
+    int factor_rpw = 0;       // 0: automatic
     // per-iteration argument tables (device) and their pinned staging
     void* dtab = nullptr;
     size_t dtab_cap = 0;
@@ -603,6 +625,16 @@ int32_t batch_step(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, int32_t it
     }
     const int L = (int)run.size();
     if (L == 0) return 0;
+    if (L == 1 && b->lone_graph) {
+        // a lone running selection replays its own captured chunk (a multiple of m iterations)
+        gcb_ctx* c = run[0];
+        const int chunk = graph_chunk(c);
+        if (chunk > 0) {
+            if (chunk > iterations) (void)select_poll(c, chunk);   // capacity for the longer chunk
+            launch_chunk(c, chunk);
+            return 1;
+        }
+    }
     if (L > kMaxBatch) bfail(b, GCB_E_INVALID, "at most 64 running contexts per step");
     const size_t s_b = align_up(sizeof(SweepArgs) * (size_t)L);
     const size_t l_b = align_up(sizeof(FactorLArgs) * (size_t)L);
@@ -611,8 +643,8 @@ int32_t batch_step(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, int32_t it
     ensure_tables(b, per_it * (size_t)iterations);
     // With several running contexts the batch supplies the parallelism: blocks take more
     // targets (sweep) and more rows of M (factor), so one launch needs fewer block rounds.
-    const bool wide = L >= 4;
-    const int rpw = wide ? kMaxRowsPerWave : 1;
+    const bool wide = b->sweep_tpl > 0 || L >= 4;
+    const int rpw = b->factor_rpw > 0 ? b->factor_rpw : (L >= 4 ? kMaxRowsPerWave : 1);
     std::vector<BlockMap> smaps((size_t)iterations), fmaps((size_t)iterations);
     char* h = static_cast<char*>(b->htab);
     std::vector<IterCtx> ics;
@@ -632,7 +664,10 @@ int32_t batch_step(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, int32_t it
             // at most one append per iteration: |S| <= n_poll + it here
             const int64_t n_ub = std::min<int64_t>(c->sp.cap, c->state_h.n + it + 1);
             sa[j] = make_sweep_args(ics[j], g);
-            if (wide) sweep_layout_batch(sa[j].T, sa[j].lpt, sa[j].tpl);
+            if (wide) {
+                sweep_layout_batch(sa[j].T, sa[j].lpt, sa[j].tpl);
+                if (b->sweep_tpl > 0) sa[j].tpl = b->sweep_tpl;
+            }
             sa[j].nub = n_ub;
             la[j] = make_factor_l_args(ics[j], g, sweep_records(sa[j]), -1);
             ua[j] = make_factor_u_args(ics[j]);
@@ -692,6 +727,19 @@ void gcb_batch_destroy(gcb_batch* b) {
 }
 
 const char* gcb_batch_last_error(const gcb_batch* b) { return b ? b->err.c_str() : g_create_err.c_str(); }
+
+int gcb_batch_set_layout(gcb_batch* b, int32_t sweep_tpl, int32_t factor_rpw, int32_t lone_graph) {
+    return bguard(b, [&] {
+        if (!(sweep_tpl == 0 || sweep_tpl == 1 || sweep_tpl == 2 || sweep_tpl == 4))
+            bfail(b, GCB_E_INVALID, "sweep_tpl must be 0, 1, 2 or 4");
+        if (!(factor_rpw == 0 || factor_rpw == 1 || factor_rpw == kMaxRowsPerWave))
+            bfail(b, GCB_E_INVALID, "factor_rpw must be 0, 1 or 4");
+        b->sweep_tpl = sweep_tpl;
+        b->factor_rpw = factor_rpw;
+        b->lone_graph = lone_graph != 0;
+        return GCB_OK;
+    });
+}
 
 int gcb_batch_begin(gcb_batch* b, gcb_ctx* ctx) {
     return bguard(b, [&] {

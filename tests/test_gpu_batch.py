@@ -144,3 +144,40 @@ def test_batch_errors():
         assert info["converged"]
     c.close()
     fresh.close()
+
+
+@pytest.mark.parametrize("layout", [(1, 1), (2, 4), (4, 4), (4, 1)])
+def test_every_layout_gives_the_same_selection(layout):
+    """The autotuner's candidates: the factor's sums do not depend on the layout and the
+    sweep layout changes only rounding, so each candidate reproduces the single selections."""
+    probs = synth.config_multi_surface(8, with_volume=False, size_scale=0.3)
+    singles = [gpu_select(p) for p in probs]
+    ctxs = [make_ctx(p) for p in probs]
+    with gcb.Batch(0) as b:
+        b.set_layout(*layout)
+        b.select(ctxs)
+    for c, s in zip(ctxs, singles):
+        assert_equal_runs(c, s)
+        c.close()
+
+
+def test_autotune_picks_a_candidate():
+    from paper_2004_04817_amd import autotune
+    probs = synth.config_multi_surface(6, with_volume=False, size_scale=0.2)
+    ctxs = [make_ctx(p) for p in probs]
+    best, times = autotune.tune_batch(ctxs, repeats=1)
+    assert best in autotune.CANDIDATES and set(times) == set(autotune.CANDIDATES)
+    assert all(t > 0 for t in times.values())
+    for c in ctxs:
+        c.close()
+
+
+def test_lone_context_uses_its_graph_and_matches():
+    """A batch with one running context replays that context's captured chunk."""
+    p = synth.config_small_ellipsoid(with_volume=False)
+    single = gpu_select(p)
+    c = make_ctx(p)
+    with gcb.Batch(0) as b:
+        b.select([c])
+    assert_equal_runs(c, single)
+    c.close()
