@@ -50,6 +50,15 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_hash(kernel_src: str) -> str:
+    """sha256 prefix of the volume kernel's sources (the kernel file and its device header)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in (kernel_src, os.path.join(os.path.dirname(kernel_src), "gcb_device.h")):
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic(kernel_src: str) -> float | None:
     """Per-launch HBM bytes of the volume sweep from the committed rocprofv3 summary,
     or None when the kernel source has changed since the counters were taken."""
@@ -61,7 +70,7 @@ def measured_traffic(kernel_src: str) -> float | None:
         return None
     vals = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:",
                                                                            "kernel_source_sha256_prefix:")))
-    cur = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    cur = kernel_source_hash(kernel_src)
     if vals.get("kernel_source_sha256_prefix", "").strip() != cur:
         return None
     return float(vals["traffic_bytes_per_launch"])
