@@ -69,7 +69,9 @@ typedef struct {
     int32_t warm_start;  /* 1: start from the support set of the context's last finished selection
                           * (an extension of Algorithm 1 for a mesh whose boundary stays while its
                           * displacements change, see gcb_select); 0: from three starting nodes */
-    int32_t reserved;    /* 0 */
+    int32_t monitor_every; /* > 0: after every that many loop iterations record the all-node max and RMS
+                            * error with the current W (gcb_get_monitor); never alters the selection,
+                            * and turns off captured chunks; not with batches.  0: off */
 } gcb_params;
 
 typedef struct {
@@ -175,6 +177,15 @@ int gcb_deform_multi(gcb_ctx *ctx, int32_t k_modes, const double *disp_modes, in
  * selection: gcb_deform, gcb_get_support and warm starts work.  Returns
  * GCB_OK, GCB_E_SINGULAR (a pivot <= 64 DBL_EPSILON) or an error. */
 int gcb_set_support(gcb_ctx *ctx, const int64_t *idx, int64_t n, int mem, gcb_select_info *info);
+
+/* Monitor samples of the last selection (params.monitor_every = E > 0):
+ * sample s was taken after loop iteration (s + 1) E (counted from the loop
+ * start), with the weights of that moment: iteration[s] = (s + 1) E,
+ * max_err[s] / rms_err[s] = max / RMS over all nb nodes of |F(r_j) - d_j|_2
+ * (Section 3: after m iterations every node has been checked once).  Any
+ * array may be NULL; up to cap samples are written.  Returns the number of
+ * samples, or a negative status. */
+int64_t gcb_get_monitor(gcb_ctx *ctx, int64_t *iteration, double *max_err, double *rms_err, int64_t cap);
 
 /* Copy out the inverse factor M = L^-1 of the current support set (Phi_S =
  * L L^T in selection order) as packed rows: row i, entries 0..i, starts at

@@ -35,7 +35,8 @@ class _Info(C.Structure):
 
 class _Log(C.Structure):
     _fields_ = [("cap", C.c_int64), ("group", C.c_void_p), ("node", C.c_void_p), ("err", C.c_void_p),
-                ("appended", C.c_void_p)]
+                ("appended", C.c_void_p), ("monitor_every", C.c_int32), ("mon_max", C.c_void_p),
+                ("mon_rms", C.c_void_p), ("n_monitor", C.c_int64)]
 
 
 def load(path: str):
@@ -196,6 +197,8 @@ class SelectResult:
     log_node: np.ndarray
     log_err: np.ndarray
     log_appended: np.ndarray
+    mon_max: np.ndarray = None
+    mon_rms: np.ndarray = None
 
 
 def _problem(xyz, disp, radius, m, seed, tol_abs, nc_max, group_of=None, init_idx=None, nthreads=0, warm_S=None):
@@ -209,12 +212,13 @@ def _problem(xyz, disp, radius, m, seed, tol_abs, nc_max, group_of=None, init_id
 
 
 def select(xyz, disp, radius, m, tol_abs, nc_max=None, seed=0, group_of=None, init_idx=None,
-           nthreads: int = 0, log_cap: int | None = None, warm_S=None) -> SelectResult:
+           nthreads: int = 0, log_cap: int | None = None, warm_S=None, monitor_every: int = 0) -> SelectResult:
     """Algorithm 1 (GCB greedy) in FP64 with the RC solve.
 
     warm_S: a kept support set (>= 3 distinct nodes, in order) to start from
     instead of the three starting nodes; the selection ends at once when it
-    already meets E* for these displacements, else the loop runs from k = len(warm_S)."""
+    already meets E* for these displacements, else the loop runs from k = len(warm_S).
+    monitor_every: record the all-node max / RMS error after every that many iterations."""
     xyz, disp = _f64(xyz), _f64(disp)
     nb = xyz.shape[0]
     nc_max = nb if nc_max is None else int(nc_max)
@@ -229,7 +233,9 @@ def select(xyz, disp, radius, m, tol_abs, nc_max=None, seed=0, group_of=None, in
     ln = np.empty(log_cap, dtype=np.int64)
     le = np.empty(log_cap, dtype=np.float64)
     la = np.empty(log_cap, dtype=np.int8)
-    log = _Log(log_cap, _ptr(lg), _ptr(ln), _ptr(le), _ptr(la))
+    mmx = np.empty(log_cap, dtype=np.float64)
+    mrm = np.empty(log_cap, dtype=np.float64)
+    log = _Log(log_cap, _ptr(lg), _ptr(ln), _ptr(le), _ptr(la), int(monitor_every), _ptr(mmx), _ptr(mrm), 0)
     S = np.empty(max(nc_max, 3), dtype=np.int64)
     W = np.empty((max(nc_max, 3), 3))
     info = _Info()
@@ -239,7 +245,8 @@ def select(xyz, disp, radius, m, tol_abs, nc_max=None, seed=0, group_of=None, in
     return SelectResult(st, S[: info.nc].copy(), W[: info.nc].copy(), info.nc, info.iterations,
                         bool(info.converged), info.final_max_err, info.final_rms_err, info.pairs_group,
                         info.pairs_append, info.pairs_cert, info.t_error, info.t_solve, info.singular_node,
-                        lg[:it].copy(), ln[:it].copy(), le[:it].copy(), la[:it].copy())
+                        lg[:it].copy(), ln[:it].copy(), le[:it].copy(), la[:it].copy(),
+                        mmx[: log.n_monitor].copy(), mrm[: log.n_monitor].copy())
 
 
 def validate(xyz, disp, radius, m, tol_abs, S_init, group, node, appended, tau, nc_max=None, seed=0,

@@ -398,6 +398,7 @@ int orc_select(const orc_problem *p, int64_t *S_out, double *W_out, orc_log *log
     memset(info, 0, sizeof(*info));
     info->singular_node = -1;
     if (!validate_problem(p)) { info->status = ORC_E_INVALID; return ORC_E_INVALID; }
+    if (log) log->n_monitor = 0;
     orc_state st;
     state_init(&st, p);
     double t0 = now_s();
@@ -459,6 +460,17 @@ int orc_select(const orc_problem *p, int64_t *S_out, double *W_out, orc_log *log
             if (log->node) log->node[it] = n;
             if (log->err) log->err[it] = E;
             if (log->appended) log->appended[it] = app;
+        }
+        if (log && log->monitor_every > 0 && (it + 1) % log->monitor_every == 0) {
+            int64_t s = (it + 1) / log->monitor_every - 1;
+            if (s < log->cap) {
+                orc_info mi;
+                memset(&mi, 0, sizeof(mi));
+                certificate(&st, &mi);
+                if (log->mon_max) log->mon_max[s] = mi.final_max_err;
+                if (log->mon_rms) log->mon_rms[s] = mi.final_rms_err;
+                log->n_monitor = s + 1;
+            }
         }
         k++;
         if (stop) break;

@@ -103,6 +103,14 @@ typedef struct {
     int64_t *node;            /* argmax node in G_i \ S (-1 if empty) */
     double *err;              /* E, its error */
     int8_t *appended;         /* 1 if appended */
+    /* Monitor (never alters the selection): after every monitor_every-th loop
+     * iteration (iterations it with (it + 1) % monitor_every == 0, counted
+     * from 0), the all-node max and RMS of |F(r_j) - d_j| with the current W.
+     * Sample s goes to mon_max[s], mon_rms[s] (s < cap).  0: no monitor. */
+    int32_t monitor_every;
+    double *mon_max;
+    double *mon_rms;
+    int64_t n_monitor;        /* samples written (output) */
 } orc_log;
 
 /* Algorithm 1 (GCB greedy; m = 1 is the traditional greedy).  S_out (nc_max)

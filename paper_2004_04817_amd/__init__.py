@@ -30,7 +30,7 @@ GCB_SERVE_BATCH, GCB_SERVE_CACHE = 1, 2
 EXPORTS = ["gcb_version", "gcb_partition", "gcb_create", "gcb_destroy", "gcb_last_error", "gcb_set_stream",
            "gcb_set_boundary", "gcb_set_displacement", "gcb_set_params", "gcb_set_groups", "gcb_select",
            "gcb_get_support", "gcb_get_log", "gcb_deform", "gcb_deform_multi", "gcb_certify",
-           "gcb_set_support", "gcb_refactor", "gcb_get_factor",
+           "gcb_set_support", "gcb_refactor", "gcb_get_factor", "gcb_get_monitor",
            "gcb_batch_create", "gcb_batch_destroy", "gcb_batch_last_error", "gcb_batch_begin", "gcb_batch_step",
            "gcb_batch_end", "gcb_select_batch", "gcb_deform_batch", "gcb_batch_set_layout",
            "gcb_server_clock", "gcb_server_create", "gcb_server_destroy", "gcb_server_last_error",
@@ -46,7 +46,7 @@ class GcbError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("radius", C.c_double), ("m", C.c_int32), ("seed", C.c_uint64), ("tol_abs", C.c_double),
                 ("nc_max", C.c_int64), ("precision", C.c_int32), ("use_init", C.c_int32),
-                ("init_idx", C.c_int64 * 3), ("warm_start", C.c_int32), ("reserved", C.c_int32)]
+                ("init_idx", C.c_int64 * 3), ("warm_start", C.c_int32), ("monitor_every", C.c_int32)]
 
 
 class SelectInfo(C.Structure):
@@ -111,6 +111,8 @@ def lib():
         L.gcb_set_support.argtypes = [vp, vp, i64, C.c_int, C.POINTER(SelectInfo)]
         L.gcb_refactor.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(SelectInfo)]
         L.gcb_get_factor.argtypes = [vp, vp, C.c_int]
+        L.gcb_get_monitor.argtypes = [vp, vp, vp, vp, i64]
+        L.gcb_get_monitor.restype = i64
         L.gcb_batch_create.argtypes = [C.POINTER(vp), C.c_int, vp]
         L.gcb_batch_destroy.argtypes = [vp]
         L.gcb_batch_destroy.restype = None
@@ -249,7 +251,7 @@ class Context:
         self._check(lib().gcb_set_displacement(self._h, pd, md))
 
     def set_params(self, radius: float, m: int, tol_abs: float, nc_max: int | None = None, seed: int = 0,
-                   precision: int = GCB_PREC_FP64, init_idx=None, warm_start: bool = False):
+                   precision: int = GCB_PREC_FP64, init_idx=None, warm_start: bool = False, monitor_every: int = 0):
         """warm_start: start from the support set of the last finished selection (same
         boundary, radius, m and seed; new displacements via set_displacement)."""
         p = Params()
@@ -264,6 +266,7 @@ class Context:
             for t in range(3):
                 p.init_idx[t] = int(init_idx[t])
         p.warm_start = 1 if warm_start else 0
+        p.monitor_every = int(monitor_every)
         self._check(lib().gcb_set_params(self._h, C.byref(p)))
 
     def set_groups(self, group_of):
@@ -295,6 +298,18 @@ class Context:
         a = np.empty(n, np.int8)
         lib().gcb_get_log(self._h, g.ctypes.data, nd.ctypes.data, e.ctypes.data, a.ctypes.data, n)
         return Log(g, nd, e, a)
+
+    def get_monitor(self):
+        """(iteration, max_err, rms_err) arrays of the monitor samples of the last selection."""
+        n = lib().gcb_get_monitor(self._h, None, None, None, 0)
+        if n < 0:
+            self._check(int(n))
+        it = np.empty(n, np.int64)
+        mx = np.empty(n)
+        rm = np.empty(n)
+        if n:
+            lib().gcb_get_monitor(self._h, it.ctypes.data, mx.ctypes.data, rm.ctypes.data, n)
+        return it, mx, rm
 
     def deform(self, xyz, out=None, out_dtype=None):
         """Eq. (6) at the points xyz (nv, 3): numpy (host) or torch (host/device)."""

@@ -128,6 +128,7 @@ struct gcb_ctx {
     double *log_err = nullptr;
     int8_t *log_app = nullptr;
     int64_t log_cap = 0;
+    double *mon = nullptr;             // monitor samples (max e^2, sum e^2), log_cap pairs
     bool selected = false;
     gcb_select_info info{};
     // captured chunk of greedy iterations (replayed while its key is unchanged)

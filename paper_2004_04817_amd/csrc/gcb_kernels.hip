@@ -974,6 +974,62 @@ __global__ __launch_bounds__(kBlock) void k_certify_final(int nblk, const double
     }
 }
 
+// Monitor sample (never alters the selection): the all-node error with the
+// current W after the loop iteration that brings the log to `need` entries;
+// nothing is written if the selection stopped before that iteration ran.
+__global__ __launch_bounds__(kBlock) void k_monitor(int64_t nb, const double* __restrict__ px,
+                                                    const double* __restrict__ py, const double* __restrict__ pz,
+                                                    const double* __restrict__ pdx, const double* __restrict__ pdy,
+                                                    const double* __restrict__ pdz, SupportView sv,
+                                                    const GState* __restrict__ st, int64_t need,
+                                                    double* __restrict__ red) {
+    const GState s = *st;
+    if (s.log_len < need) return;
+    const int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    const bool live = t < nb;
+    const int64_t tt = live ? t : nb - 1;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    accumulate64<false>(px[tt], py[tt], pz[tt], 0, s.n, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
+    double e2 = 0.0;
+    if (live) {
+        const double ex = ax - pdx[t], ey = ay - pdy[t], ez = az - pdz[t];
+        e2 = fma(ez, ez, fma(ey, ey, ex * ex));
+    }
+    Best b{live ? e2 : -1.0, (int32_t)t, 0};
+    b = block_best(b);
+    const double sum = block_sum<kBlock>(e2);
+    if (threadIdx.x == 0) {
+        red[2 * blockIdx.x] = b.v;
+        red[2 * blockIdx.x + 1] = sum;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_monitor_final(int nblk, const double* __restrict__ red,
+                                                          const GState* __restrict__ st, int64_t need,
+                                                          double* __restrict__ out) {
+    if (st->log_len < need) return;
+    double mx = 0.0, s = 0.0;
+    const int per = (nblk + kBlock - 1) / kBlock;
+    const int i0 = threadIdx.x * per, i1 = min(nblk, i0 + per);
+    for (int i = i0; i < i1; ++i) {
+        mx = fmax(mx, red[2 * i]);
+        s += red[2 * i + 1];
+    }
+    __shared__ double smx[kBlock], ss[kBlock];
+    smx[threadIdx.x] = mx;
+    ss[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double M = 0.0, S = 0.0;
+        for (int i = 0; i < kBlock; ++i) {
+            M = fmax(M, smx[i]);
+            S += ss[i];
+        }
+        out[0] = M;
+        out[1] = S;
+    }
+}
+
 // ---------------------------------------------------------------- volume (a7)
 template <typename TIn, typename TOut>
 __global__ __launch_bounds__(kBlock) void k_volume64(int64_t nv, const TIn* __restrict__ xyz, double inv_r,
@@ -1259,6 +1315,14 @@ void launch_transpose_factor(hipStream_t s, const double* Mr, double* Mc, int n,
     const int64_t cnt = (int64_t)n * (n + 1) / 2;
     if (cnt == 0) return;
     GCB_LAUNCH(k_transpose_factor, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock), s, Mr, Mc, n, cap);
+}
+
+void launch_monitor(hipStream_t s, const Boundary& bd, const Support& sp, const GState* st, int64_t need,
+                    double* red, double* out) {
+    const unsigned g = (unsigned)((bd.nb + kBlock - 1) / kBlock);
+    GCB_LAUNCH(k_monitor, dim3(g), dim3(kBlock), s, bd.nb, bd.px, bd.py, bd.pz, bd.pdx, bd.pdy, bd.pdz, view(sp), st,
+               need, red);
+    GCB_LAUNCH(k_monitor_final, dim3(1), dim3(kBlock), s, (int)g, red, st, need, out);
 }
 
 void launch_certify(hipStream_t s, const Boundary& bd, const Support& sp, int n, double* red, double* out) {

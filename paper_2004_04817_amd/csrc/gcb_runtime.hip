@@ -163,6 +163,7 @@ void grow_log(gcb_ctx* ctx, int64_t used, int64_t cap) {
     grow_log_array(ctx, ctx->log_node, used, cap);
     grow_log_array(ctx, ctx->log_err, used, cap);
     grow_log_array(ctx, ctx->log_app, used, cap);
+    grow_log_array(ctx, ctx->mon, 2 * used, 2 * cap);   // at most one monitor sample per iteration
     ctx->log_cap = cap;
 }
 
@@ -178,6 +179,7 @@ void check_params(gcb_ctx* ctx) {
     if (p.nc_max > (int64_t)1 << 30) fail(ctx, GCB_E_INVALID, "nc_max too large");
     if (p.precision != GCB_PREC_FP64 && p.precision != GCB_PREC_FP32_EVAL)
         fail(ctx, GCB_E_INVALID, "unknown precision");
+    if (p.monitor_every < 0) fail(ctx, GCB_E_INVALID, "monitor_every must be >= 0");
     if (p.use_init) {
         for (int t = 0; t < 3; ++t)
             if (p.init_idx[t] < 0 || p.init_idx[t] >= nb) fail(ctx, GCB_E_INVALID, "init_idx out of range");
@@ -467,8 +469,11 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     // launch.  A chunk of C iterations with C a multiple of m starts at the
     // same phase of k mod m every time and is captured once into a graph.
     const int m = p.m;
-    const int gchunk = graph_chunk(ctx);
+    const int every = p.monitor_every;
+    const int gchunk = every > 0 ? 0 : graph_chunk(ctx);
     const int chunk = gchunk > 0 ? gchunk : 64;
+    const int64_t k0 = ctx->k_host;   // loop start (3, or |S0| for a warm start)
+    if (every > 0) ensure_red(ctx);
     for (;;) {
         HIPCHK(ctx, hipMemcpyAsync(ctx->state_pin, ctx->state, sizeof(GState), hipMemcpyDeviceToHost, ctx->stream));
         sync(ctx);
@@ -481,6 +486,12 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
             for (int it = 0; it < chunk; ++it) {
                 const int n_ub = (int)n_upper(ctx, ctx->state_h.n, it + 1);
                 launch_iteration(ctx->stream, ic, (int)((k + it) % m), n_ub);
+                const int64_t done_iters = k + it + 1 - k0;   // loop iterations launched so far
+                if (every > 0 && done_iters % every == 0) {
+                    const int64_t s = done_iters / every - 1;
+                    launch_monitor(ctx->stream, ctx->bd, ctx->sp, ctx->state, done_iters, ctx->red,
+                                   ctx->mon + 2 * s);
+                }
             }
             HIPCHK(ctx, hipGetLastError());
             ctx->k_host = k + chunk;
@@ -744,6 +755,7 @@ int gcb_batch_set_layout(gcb_batch* b, int32_t sweep_tpl, int32_t factor_rpw, in
 int gcb_batch_begin(gcb_batch* b, gcb_ctx* ctx) {
     return bguard(b, [&] {
         BHIPCHK(b, hipSetDevice(b->device));
+        if (ctx && ctx->params.monitor_every > 0) bfail(b, GCB_E_INVALID, "monitor samples are not taken in batches");
         attach(b, ctx);
         return guard(ctx, [&] {
             select_begin(ctx);
@@ -1054,6 +1066,31 @@ int64_t gcb_get_log(gcb_ctx* ctx, int32_t* group, int64_t* node, double* err, in
             sync(ctx);
             if (node)
                 for (int64_t i = 0; i < n; ++i) node[i] = nd[i];
+        }
+        return GCB_OK;
+    });
+    return rc < 0 ? rc : total;
+}
+
+int64_t gcb_get_monitor(gcb_ctx* ctx, int64_t* iteration, double* max_err, double* rms_err, int64_t cap) {
+    if (!ctx) return GCB_E_INVALID;
+    int64_t total = 0;
+    int rc = guard(ctx, [&] {
+        if (!ctx->selected) fail(ctx, GCB_E_STATE, "no finished selection");
+        if (cap < 0) fail(ctx, GCB_E_INVALID, "cap < 0");
+        const int every = ctx->params.monitor_every;
+        total = every > 0 ? std::min<int64_t>(ctx->state_h.log_len, ctx->log_cap) / every : 0;
+        const int64_t n = std::min(cap, total);
+        if (n > 0) {
+            HIPCHK(ctx, hipSetDevice(ctx->device));
+            std::vector<double> h(2 * (size_t)n);
+            HIPCHK(ctx, hipMemcpyAsync(h.data(), ctx->mon, sizeof(double) * h.size(), hipMemcpyDeviceToHost, ctx->stream));
+            sync(ctx);
+            for (int64_t s = 0; s < n; ++s) {
+                if (iteration) iteration[s] = (s + 1) * (int64_t)every;
+                if (max_err) max_err[s] = std::sqrt(h[2 * s]);
+                if (rms_err) rms_err[s] = std::sqrt(h[2 * s + 1] / (double)ctx->bd.nb);
+            }
         }
         return GCB_OK;
     });

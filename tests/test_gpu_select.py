@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+import paper_2004_04817_amd as gcb
 import synth
 from oracle import brute
 from tests.gpu_util import first_divergence, gpu_select, oracle_select
@@ -110,3 +111,33 @@ def test_wing_full_size_selection():
     assert info["converged"] and info["final_max_err"] <= p.tol_abs
     assert_same_run(p, info, S, W, log, r, p.tol_abs, p.m)
     ctx.close()
+
+
+def test_monitor_samples_match_oracle():
+    """Monitor every m iterations (Section 3: all nodes checked once per m iterations):
+    the selection is unchanged and every sample equals the oracle's."""
+    p = synth.config_small_ellipsoid(with_volume=False)
+    _, info0, S0, _, _ = gpu_select(p)
+    c = gcb.Context(0)
+    c.set_boundary(p.xyz, p.disp)
+    c.set_params(p.radius, p.m, p.tol_abs, seed=p.seed, monitor_every=p.m)
+    info = c.select()
+    S, _ = c.get_support()
+    assert np.array_equal(S, S0) and info["iterations"] == info0["iterations"]
+    it, mx, rm = c.get_monitor()
+    r = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed, monitor_every=p.m)
+    assert len(mx) == len(r.mon_max) == info["iterations"] // p.m
+    assert np.array_equal(it, p.m * np.arange(1, len(mx) + 1))
+    assert np.abs(mx - r.mon_max).max() <= 1e-10 * p.max_disp
+    assert np.abs(rm - r.mon_rms).max() <= 1e-10 * p.max_disp
+    # m = 1 with a sample every iteration
+    c.set_params(p.radius, 1, p.tol_abs, seed=p.seed, monitor_every=1)
+    info1 = c.select()
+    it1, mx1, _ = c.get_monitor()
+    log = c.get_log()
+    assert len(mx1) == info1["iterations"]
+    assert np.abs(mx1[:-1] - log.err[1:]).max() <= 1e-12 * p.max_disp
+    with gcb.Batch(0) as b:
+        with pytest.raises(gcb.GcbError):
+            b.begin(c)
+    c.close()

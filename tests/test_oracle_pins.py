@@ -416,3 +416,35 @@ def test_inverse_factor_singular():
     xyz = np.concatenate([p.xyz, p.xyz[:1]])
     with pytest.raises(RuntimeError):
         oracle.inverse_factor(xyz, [0, 3, 12], p.radius)
+
+
+def test_monitor_is_passive_and_agrees_with_the_greedy():
+    """The monitor never alters the selection; with m = 1 its all-node maximum after
+    iteration i is the maximum error the next iteration finds (nodes in S have zero error)."""
+    p = synth.config_small_ellipsoid(with_volume=False)
+    r0 = oracle.select(p.xyz, p.disp, p.radius, 1, p.tol_abs, seed=p.seed)
+    r1 = oracle.select(p.xyz, p.disp, p.radius, 1, p.tol_abs, seed=p.seed, monitor_every=1)
+    assert np.array_equal(r0.S, r1.S) and np.array_equal(r0.log_err, r1.log_err)
+    assert len(r1.mon_max) == r1.iterations
+    assert np.array_equal(r1.mon_max[:-1], r1.log_err[1:])
+    assert r1.mon_max[-1] == r1.final_max_err
+    rm = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed, monitor_every=p.m)
+    assert len(rm.mon_max) == rm.iterations // p.m
+    assert np.all(rm.mon_rms <= rm.mon_max)
+
+
+def test_monitor_brute_force():
+    """Monitor samples against dense solves on the support prefix of each sample."""
+    p = synth.tiny_problem(nb=40, seed=11, m=3)
+    tol = 0.01 * p.max_disp
+    every = 2
+    r = oracle.select(p.xyz, p.disp, p.radius, 3, tol, seed=p.seed, monitor_every=every)
+    for s in range(len(r.mon_max)):
+        it = (s + 1) * every                         # iterations done
+        nS = 3 + int(r.log_appended[:it].sum())
+        S = r.S[:nS]
+        W = brute.solve_weights(p.xyz[S], p.disp[S], p.radius)
+        F = brute.rbf_matrix(p.xyz, p.xyz[S], p.radius) @ W
+        e = np.sqrt(((F - p.disp) ** 2).sum(axis=1))
+        assert abs(r.mon_max[s] - e.max()) <= 1e-10 * p.max_disp
+        assert abs(r.mon_rms[s] - np.sqrt((e ** 2).mean())) <= 1e-10 * p.max_disp
