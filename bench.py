@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=250,
                     help="also replay a Poisson stream of this many deformation requests (20 req/s), served "
                          "with continuous batching and resident meshes vs one at a time (0: skip)")
+    ap.add_argument("--m-sweep", default="1,5,10,20,40,80,107,160",
+                    help="also select the wing at these group counts m (the paper's m-sweep, free Nc; '' skips)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, one device-to-device copy of this many MiB (the known-size "
                          "kernel that scales FETCH_SIZE / WRITE_SIZE counter readings)")
@@ -326,6 +328,22 @@ def main():
                                      "achieved": flops / (ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
                                      "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}}
         del mout, modes
+    if a.m_sweep and a.config == "wing":
+        # GCB group count m against the traditional greedy (m = 1), free Nc, same E* (Tables 3 and 6 protocol)
+        rows = []
+        for m in [int(x) for x in a.m_sweep.split(",")]:
+            ctx.set_params(p.radius, m, p.tol_abs, seed=p.seed)
+            ctx.select()
+            inf = ctx.select()
+            rows.append({"m": m, "nc": inf["nc"], "iterations": inf["iterations"], "select_ms": inf["ms_select"],
+                         "pairs_greedy": inf["pairs_group"] + inf["pairs_append"],
+                         "converged": bool(inf["converged"])})
+        base = next((r["select_ms"] for r in rows if r["m"] == 1), None)
+        for r in rows:
+            r["speedup_vs_m1"] = base / r["select_ms"] if base else None
+        rec["m_sweep"] = rows
+        ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
+        ctx.select()
     if a.surfaces > 0:
         rec["multi_surface"] = multi_surface(a.surfaces, dev)
     if a.requests > 0:
