@@ -88,20 +88,21 @@ def problem(name):
 
 
 def cpu_baseline(p, nv_sample):
-    """The FP64 oracle as it stands, on all host cores: full greedy + a volume sample."""
+    """The FP64 oracle as it stands, on all host cores: full greedy + a volume sample.
+    Returns the baseline record and the oracle's results (support set, sampled displacements)."""
     import oracle
     threads = os.cpu_count() or 1
     t0 = time.perf_counter()
     r = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed, nthreads=threads)
     t1 = time.perf_counter()
     vol = p.volume[:nv_sample]
-    oracle.interpolate(p.xyz[r.S], r.W, p.radius, vol, nthreads=threads)
+    ref = oracle.interpolate(p.xyz[r.S], r.W, p.radius, vol, nthreads=threads)
     t2 = time.perf_counter()
     pairs = r.pairs_group + r.pairs_append + vol.shape[0] * r.nc
     return {"value": pairs / (t2 - t0), "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
             "sample": f"full greedy (Nb={p.nb}, m={p.m}, Nc={r.nc}, {r.iterations} iterations, {t1 - t0:.2f} s) "
                       f"+ Eq. 6 at {vol.shape[0]} volume points ({t2 - t1:.2f} s)",
-            "seconds": t2 - t0}
+            "seconds": t2 - t0}, r, ref
 
 
 def multi_surface(count, dev):
@@ -353,7 +354,18 @@ def main():
                              "p99_one_at_a_time_fp64": rec["serving"]["one_at_a_time"]["p99_ms"],
                              "what": "deformation request latency, arrival to output complete"}
     if not a.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(p, min(a.cpu_sample_volume, nv))
+        base, r_orc, ref = cpu_baseline(p, min(a.cpu_sample_volume, nv))
+        rec["cpu_baseline"] = base
+        # the benchmark's own outputs against the FP64 oracle (same inputs)
+        S_gpu, _ = ctx.get_support()
+        o = out[: ref.shape[0]].cpu().numpy()
+        err = np.sqrt(((o - ref) ** 2).sum(axis=1))
+        rec["accuracy"]["vs_oracle"] = {
+            "same_support_sequence": bool(np.array_equal(S_gpu, r_orc.S)),
+            "volume_points_compared": int(ref.shape[0]),
+            "volume_max_err_rel_max_d": float(err.max() / p.max_disp),
+            "volume_rms_err_rel_max_d": float(np.sqrt((err ** 2).mean()) / p.max_disp),
+            "oracle_final_max_err": r_orc.final_max_err}
     print(json.dumps(rec), flush=True)
     ctx.close()
 

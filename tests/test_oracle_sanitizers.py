@@ -1,0 +1,25 @@
+"""The oracle under AddressSanitizer and UndefinedBehaviorSanitizer (host code, CPU):
+a C driver calls every entry point on a small seeded problem."""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+def test_oracle_clean_under_sanitizers(tmp_path):
+    exe = tmp_path / "oracle_driver"
+    cmd = ["gcc", "-std=c11", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-ffp-contract=off", "-D_GNU_SOURCE",
+           "-I", os.path.join(ROOT, "oracle"), os.path.join(ROOT, "oracle", "gcb_oracle.c"),
+           os.path.join(ROOT, "tests", "native", "oracle_driver.c"), "-o", str(exe), "-lm"]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+    env.pop("LD_PRELOAD", None)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "ok nc=" in r.stdout
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr
