@@ -654,8 +654,10 @@ int32_t batch_step(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, int32_t it
     ensure_tables(b, per_it * (size_t)iterations);
     // With several running contexts the batch supplies the parallelism: blocks take more
     // targets (sweep) and more rows of M (factor), so one launch needs fewer block rounds.
+    // automatic layout (measured on 32 uneven surfaces): wide sweeps from four running contexts on,
+    // one 16-row chunk per factor wave
     const bool wide = b->sweep_tpl > 0 || L >= 4;
-    const int rpw = b->factor_rpw > 0 ? b->factor_rpw : (L >= 4 ? kMaxRowsPerWave : 1);
+    const int rpw = b->factor_rpw > 0 ? b->factor_rpw : 1;
     std::vector<BlockMap> smaps((size_t)iterations), fmaps((size_t)iterations);
     char* h = static_cast<char*>(b->htab);
     std::vector<IterCtx> ics;
