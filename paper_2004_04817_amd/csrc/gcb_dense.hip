@@ -171,21 +171,44 @@ __global__ __launch_bounds__(kBlock) void k_trtri_diag(int np, const double* __r
 
 // Blocks of M at distance s below the diagonal, all in parallel:
 // M_ij = -M_ii (sum_{k=j}^{i-1} L_ik M_kj), i = j + s; the blocks M_kj with
-// k - j < s come from earlier launches.
-__global__ __launch_bounds__(kBlock) void k_trtri_off(int np, int s, const double* __restrict__ L,
-                                                      double* __restrict__ M) {
+// k - j < s come from earlier launches.  16 waves per block: four per 16 x 16
+// quarter of the tile, each summing every fourth 16-wide slice of the K range
+// (four accumulator chains), the slices added in order through LDS.
+constexpr int kTriWaves = 16;
+
+__global__ __launch_bounds__(kTriWaves * 64) void k_trtri_off(int np, int s, const double* __restrict__ L,
+                                                              double* __restrict__ M) {
+    __shared__ double part[4][kDB][kDB + 1];
     __shared__ double T[kDB][kDB + 1];
     const int j = blockIdx.x, i = j + s;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int qi = wave >> 1, qj = wave & 1;
+    const int quarter = wave & 3, slice = wave >> 2;
+    const int qi = quarter >> 1, qj = quarter & 1;
     const int li = lane & 15, lk = lane >> 4;
-    // K = 32 s in steps of 16: four independent accumulator chains, loads issued together
     d4 acc[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
     const double* La = L + (size_t)(kDB * i + 16 * qi + li) * np;
     const double* Mb = M + kDB * j + 16 * qj + li;
-    for (int k = kDB * j; k < kDB * i; k += 16) {
+    // four 16-wide slices in flight per round (loads first, then their products)
+    const int kend = kDB * i;
+    int k = kDB * j + 16 * slice;
+    for (; k + 192 < kend; k += 256) {
+        double a[4][4], b[4][4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[c][q] = La[k + 64 * c + 4 * q + lk];
+                b[c][q] = Mb[(size_t)(k + 64 * c + 4 * q + lk) * np];
+            }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][q], b[c][q], acc[q], 0, 0, 0);
+    }
+    for (; k < kend; k += 64) {
         double a[4], b[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -197,8 +220,14 @@ __global__ __launch_bounds__(kBlock) void k_trtri_off(int np, int s, const doubl
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        T[16 * qi + lk + 4 * r][16 * qj + li] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
+        part[slice][16 * qi + lk + 4 * r][16 * qj + li] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
     __syncthreads();
+    for (int x = threadIdx.x; x < kDB * kDB; x += kTriWaves * 64) {
+        const int r = x / kDB, c = x % kDB;
+        T[r][c] = (part[0][r][c] + part[1][r][c]) + (part[2][r][c] + part[3][r][c]);
+    }
+    __syncthreads();
+    if (wave >= 4) return;
     d4 out = {0.0, 0.0, 0.0, 0.0};
     const double* Mi = M + (size_t)(kDB * i + 16 * qi + li) * np + kDB * i;
 #pragma unroll
@@ -288,7 +317,7 @@ void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, d
     // blocks of Md above the diagonal are never read: no clearing needed
     hipLaunchKernelGGL(k_trtri_diag, dim3((unsigned)nbk), dim3(kBlock), 0, s, np, Dbuf, Md);
     for (int d = 1; d < nbk; ++d)
-        hipLaunchKernelGGL(k_trtri_off, dim3((unsigned)(nbk - d)), dim3(kBlock), 0, s, np, d, A, Md);
+        hipLaunchKernelGGL(k_trtri_off, dim3((unsigned)(nbk - d)), dim3(kTriWaves * 64), 0, s, np, d, A, Md);
 }
 
 void launch_pack_factor(hipStream_t s, int n, const double* Md, double* Mp, const double* old, double* red) {
