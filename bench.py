@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=250,
                     help="also replay a Poisson stream of this many deformation requests (20 req/s), served "
                          "with continuous batching and resident meshes vs one at a time (0: skip)")
+    ap.add_argument("--saturation-rate", type=float, default=80.0,
+                    help="also replay the stream at this arrival rate (req/s), above one-at-a-time capacity (0: skip)")
     ap.add_argument("--m-sweep", default="1,5,10,20,40,80,107,160",
                     help="also select the wing at these group counts m (the paper's m-sweep, free Nc; '' skips)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -166,7 +168,7 @@ def multi_surface(count, dev):
     return res
 
 
-def serving_section(n_requests, dev, warmup_requests=25, rate=20.0):
+def serving_section(n_requests, dev, warmup_requests=25, rate=20.0, sat_rate=0.0):
     """Poisson stream (sizes of the uneven batch, 20 % repeats with new fields),
     latency arrival -> output complete: served (continuous batching, resident
     meshes, warm starts) vs plain FP64 one at a time (FIFO)."""
@@ -179,11 +181,22 @@ def serving_section(n_requests, dev, warmup_requests=25, rate=20.0):
     pool = serving.volume_pool(max_nv, dev)
     res = {"requests": n_requests, "warmup_requests": warmup_requests, "rate_per_s": rate, "repeat_p": 0.2,
            "nv_per_nb": 25, "precision": "fp64"}
-    for name, kw in (("served", dict(max_active=32, flags=gcb.GCB_SERVE_BATCH | gcb.GCB_SERVE_CACHE)),
-                     ("one_at_a_time", dict(max_active=1, flags=0))):
+    modes = (("served", dict(max_active=32, flags=gcb.GCB_SERVE_BATCH | gcb.GCB_SERVE_CACHE)),
+             ("one_at_a_time", dict(max_active=1, flags=0)))
+    for name, kw in modes:
         with gcb.Server(0, hbm_budget=64 << 30, **kw) as srv:
             served = serving.replay(srv, items, pool, nv_per_nb=25, iterations=48)
             res[name] = serving.latency_summary(served, skip=warmup_requests)
+    if sat_rate > 0:
+        # the same requests arriving faster than one-at-a-time service can keep up with
+        scale = rate / sat_rate
+        fast = [(type(i[0])(i[0].t * scale, i[0].key, i[0].nb, i[0].field_seed),) + tuple(i[1:]) for i in items]
+        sat = {"rate_per_s": sat_rate}
+        for name, kw in modes:
+            with gcb.Server(0, hbm_budget=64 << 30, **kw) as srv:
+                served = serving.replay(srv, fast, pool, nv_per_nb=25, iterations=48)
+                sat[name] = serving.latency_summary(served, skip=warmup_requests)
+        res["saturation"] = sat
     del pool
     return res
 
@@ -348,7 +361,7 @@ def main():
     if a.surfaces > 0:
         rec["multi_surface"] = multi_surface(a.surfaces, dev)
     if a.requests > 0:
-        rec["serving"] = serving_section(a.requests, dev)
+        rec["serving"] = serving_section(a.requests, dev, sat_rate=a.saturation_rate)
         rec["latency_ms"] = {"p50": rec["serving"]["served"]["p50_ms"], "p99": rec["serving"]["served"]["p99_ms"],
                              "p50_one_at_a_time_fp64": rec["serving"]["one_at_a_time"]["p50_ms"],
                              "p99_one_at_a_time_fp64": rec["serving"]["one_at_a_time"]["p99_ms"],
