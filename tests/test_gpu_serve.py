@@ -100,3 +100,33 @@ def test_bad_request_rejected():
             srv.submit(np.zeros((2, 3)), np.zeros((2, 3)), 1.0, 1, 0.0)
         assert e.value.code == gcb.GCB_E_INVALID
         assert srv.progress(4) == 0
+
+
+def test_mixed_dtypes_in_one_round():
+    """Requests with FP32 and FP64 volume arrays finishing together: one batched volume launch
+    per dtype pair; each output equals its own deformation alone."""
+    items = small_stream(8, 0.0)
+    pool64 = serving.volume_pool(20_000, "cuda")
+    with gcb.Server(0, hbm_budget=4 << 30, max_active=8) as srv:
+        served = []
+        for n, (req, base, disp, tol) in enumerate(items):
+            dt = torch.float32 if n % 2 else torch.float64
+            vol = pool64[req.key % 2][: 4 * base.nb].to(dt).contiguous()
+            out = torch.empty_like(vol)
+            tk = srv.submit(base.xyz, disp, base.radius, base.m, tol, seed=base.seed, mesh_key=-1, vol=vol, out=out)
+            served.append((tk, base, disp, tol, vol, out))
+        while srv.progress(16):
+            pass
+        torch.cuda.synchronize()
+        for tk, base, disp, tol, vol, out in served:
+            r = srv.result(tk)
+            assert r["state"] == 3 and not r["warm"] and not r["kept"]
+            c = gcb.Context(0)
+            c.set_boundary(base.xyz, disp)
+            c.set_params(base.radius, base.m, tol, seed=base.seed)
+            c.select()
+            ref = c.deform(vol, out_dtype=vol.dtype)
+            torch.cuda.synchronize()
+            md = float(np.sqrt((disp ** 2).sum(axis=1)).max())
+            assert (out.double() - ref.double()).abs().max().item() <= TOL_SAME * md
+            c.close()
