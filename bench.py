@@ -355,7 +355,28 @@ def main():
         base = next((r["select_ms"] for r in rows if r["m"] == 1), None)
         for r in rows:
             r["speedup_vs_m1"] = base / r["select_ms"] if base else None
-        rec["m_sweep"] = rows
+        # fixed Nc (Tables 2 and 5 protocol): E* = 0, every m selects exactly Nc^max supports
+        nc_fixed = 1100
+        fixed = []
+        for m in [int(x) for x in a.m_sweep.split(",")]:
+            ctx.set_params(p.radius, m, 0.0, nc_max=nc_fixed, seed=p.seed)
+            ctx.select()
+            inf = ctx.select()
+            fixed.append({"m": m, "nc": inf["nc"], "iterations": inf["iterations"], "select_ms": inf["ms_select"],
+                          "final_max_err_rel": inf["final_max_err"] / p.max_disp})
+        fbase = next((r["select_ms"] for r in fixed if r["m"] == 1), None)
+        for r in fixed:
+            r["speedup_vs_m1"] = fbase / r["select_ms"] if fbase else None
+        # error history of the benchmark selection (all-node max and RMS every m iterations; Figs. 4-7 analog)
+        ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed, monitor_every=p.m)
+        ctx.select()
+        it_h, mx_h, rm_h = ctx.get_monitor()
+        log_h = ctx.get_log()
+        nc_at = np.cumsum(log_h.appended.astype(np.int64)) + 3
+        pick = np.unique(np.linspace(0, len(it_h) - 1, 8).astype(int)) if len(it_h) else []
+        history = [{"iteration": int(it_h[i]), "nc": int(nc_at[it_h[i] - 1]), "max_err_rel": float(mx_h[i] / p.max_disp),
+                    "rms_err_rel": float(rm_h[i] / p.max_disp)} for i in pick]
+        rec["m_sweep"] = {"free_nc": rows, "fixed_nc": {"nc": nc_fixed, "rows": fixed}, "history_m107": history}
         ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
         ctx.select()
     if a.surfaces > 0:
