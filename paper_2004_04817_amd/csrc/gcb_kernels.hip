@@ -273,8 +273,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
         cz = pz[t0 + tc];
         corig = perm[t0 + tc];
     }
-    const int w0end = (int)min((int64_t)STAGE, nub);
-    for (int j = threadIdx.x; j < w0end; j += kBlock) {
+    // the first 256 supports are staged with the state load; the rest of the first window once |S| is
+    // known (a window of up to STAGE supports staged before |S| is known wastes bandwidth while |S| is small)
+    const int w0eager = (int)min((int64_t)min(STAGE, 256), nub);
+    for (int j = threadIdx.x; j < w0eager; j += kBlock) {
         ls[0][j] = sv.sx[j];
         ls[1][j] = sv.sy[j];
         ls[2][j] = sv.sz[j];
@@ -285,6 +287,18 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
     __syncthreads();
     if (s_done) return;
     const int n = s_n;
+    const int w0end = min(STAGE, n);
+    if (w0end > w0eager) {
+        for (int j = w0eager + threadIdx.x; j < w0end; j += kBlock) {
+            ls[0][j] = sv.sx[j];
+            ls[1][j] = sv.sy[j];
+            ls[2][j] = sv.sz[j];
+            ls[3][j] = sv.wx[j];
+            ls[4][j] = sv.wy[j];
+            ls[5][j] = sv.wz[j];
+        }
+        __syncthreads();
+    }
     double ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0}, az[4] = {0, 0, 0, 0};
     for (int w0 = 0; w0 < n; w0 += STAGE) {
         const int w1 = min(n, w0 + STAGE);
