@@ -474,7 +474,7 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
         }
     }
     // support coordinates of the first b window and of this block's b.W slice, loaded early
-    constexpr int kBPre = 2;
+    constexpr int kBPre = 1;
     double pbx[kBPre], pby[kBPre], pbz[kBPre];
 #pragma unroll
     for (int u = 0; u < kBPre; ++u) {
