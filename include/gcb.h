@@ -54,7 +54,8 @@ enum gcb_dtype { GCB_F32 = 0, GCB_F64 = 1 };
 enum gcb_precision {
     GCB_PREC_FP64 = 0,       /* every evaluation in FP64 */
     GCB_PREC_FP32_EVAL = 1   /* gcb_deform evaluates Eq. (6) in FP32 (scaled coordinates, weights and
-                              * phi in FP32; chunks of 32 supports summed in FP32, chunk sums in FP64) */
+                              * phi in FP32; chunks of 32 supports summed in FP32, chunk sums in FP64).
+                              * gcb_deform_batch and gcb_deform_multi stay FP64 */
 };
 
 typedef struct {
