@@ -141,3 +141,32 @@ def test_monitor_samples_match_oracle():
         with pytest.raises(gcb.GcbError):
             b.begin(c)
     c.close()
+
+
+def test_empty_and_uneven_groups_single_and_batched():
+    """An explicit partition with empty groups (their iterations find nothing: E = 0, quiet)
+    and very uneven sizes, single and in a batch, against the oracle."""
+    p = synth.config_small_ellipsoid(nb=1200, with_volume=False)
+    m = 9
+    rng = np.random.default_rng(5)
+    g = rng.choice([0, 2, 3, 7], size=p.nb, p=[0.55, 0.3, 0.1, 0.05]).astype(np.int32)   # groups 1,4,5,6,8 empty
+    r = oracle_select(p, m=m, group_of=g)
+    ctx, info, S, W, log = gpu_select(p, m=m, group_of=g)
+    assert_same_run(p, info, S, W, log, r, p.tol_abs, m)
+    assert np.all(log.node[np.isin(log.group, [1, 4, 5, 6, 8])] == -1)
+    c2 = gcb.Context(0)
+    c2.set_boundary(p.xyz, p.disp)
+    c2.set_params(p.radius, m, p.tol_abs, seed=p.seed)
+    c2.set_groups(g)
+    other = [gcb.Context(0) for _ in range(4)]
+    for j, c in enumerate(other):
+        q = synth.tiny_problem(nb=60 + j, seed=40 + j, m=2)
+        c.set_boundary(q.xyz, q.disp)
+        c.set_params(q.radius, 2, 0.01 * q.max_disp, seed=q.seed)
+    with gcb.Batch(0) as b:
+        b.select([c2] + other)
+    S2, W2 = c2.get_support()
+    assert np.array_equal(S2, S)
+    assert np.abs(W2 - W).max() <= 1e-12 * max(1.0, np.abs(W).max())
+    for c in [ctx, c2] + other:
+        c.close()
