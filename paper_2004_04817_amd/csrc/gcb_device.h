@@ -23,19 +23,21 @@ __device__ __forceinline__ double wendland_r2(double r2) {
     return (t2 * t2) * fma(-4.0, t, 5.0);
 }
 
-// The same phi with one coupled (Goldschmidt) Newton step for the square root
-// instead of two: relative error of eta about 1.5 e^2 for a hardware estimate
-// of relative error e (below 1e-13 for e <= 2^-22), so |phi - phi_exact| stays
-// below 1e-12 and the volume sum below kappa * 1e-12 max|d|.  Used where only
-// the displacement tolerance matters (Eq. 6), not in the greedy's sweeps.
-__device__ __forceinline__ double wendland_r2_vol(double r2) {
-    const double x = fmax(r2, 1e-200);
-    const double r = __builtin_amdgcn_rsq(x);
-    const double g = x * r;
-    const double h = 0.5 * r;
-    const double e = fma(-g, h, 0.5);
-    const double y = fma(g, e, g);
-    const double t = fmin(fmax(1.0 - y, 0.0), 1.0);
+// Wendland C2 for the volume sweep (Eq. 6) from d = (|r - r_i| / (2R))^2, the
+// squared distance of points scaled by 1/(2R).  With h = rsq(d) ~ 2/eta and
+// q = d h ~ eta/2, one Newton step for the square root gives
+// eta = q (3 - q h) (relative error about 1.5 e^2 for a hardware estimate of
+// relative error e; e is about 5e-8, so eta is good to 1e-14), and
+// phi = t^4 (5 - 4 t) with t = clamp(1 - eta, 0, 1).  d may come out slightly
+// negative from the cancellation in |u|^2 + |v|^2 - 2 u.v; |d| plus a tiny
+// bias keeps the square root real and away from rsq(0).  Used where only the
+// displacement tolerance matters, not in the greedy's sweeps.
+__device__ __forceinline__ double wendland_quarter(double d) {
+    const double x = fabs(d) + 1e-200;
+    const double h = __builtin_amdgcn_rsq(x);
+    const double q = x * h;
+    const double e = fma(-q, h, 3.0);
+    const double t = fmin(fmax(fma(-q, e, 1.0), 0.0), 1.0);
     const double t2 = t * t;
     return (t2 * t2) * fma(-4.0, t, 5.0);
 }

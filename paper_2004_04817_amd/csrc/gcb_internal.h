@@ -88,6 +88,9 @@ struct Support {
     double *sx = nullptr, *sy = nullptr, *sz = nullptr;   // scaled coordinates, selection order
     double *wx = nullptr, *wy = nullptr, *wz = nullptr;   // weights (FP64 master)
     float *fsx = nullptr, *fsy = nullptr, *fsz = nullptr, *fwx = nullptr, *fwy = nullptr, *fwz = nullptr;
+    // volume-sweep table (allocated by the first FP64 deformation): coordinates scaled by 1/(2R) and
+    // centred at the first support, and their squared norms
+    double *qx = nullptr, *qy = nullptr, *qz = nullptr, *qq = nullptr;
     int32_t *orig = nullptr;     // original index of support s
     double *M = nullptr;         // packed lower-triangular inverse factor, row i at i(i+1)/2
     double *Mc = nullptr;        // the same factor by columns: column j (rows j..cap-1) at j*cap - j(j-1)/2

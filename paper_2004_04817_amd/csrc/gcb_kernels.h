@@ -13,6 +13,11 @@ struct SupportMut {
     double* M;
 };
 inline SupportView view(const Support& s) { return SupportView{s.sx, s.sy, s.sz, s.wx, s.wy, s.wz}; }
+// Volume-sweep table: supports scaled by 1/(2R), centred at the first support, and their squared norms.
+struct VolTable {
+    double *qx, *qy, *qz, *qq;
+};
+inline VolTable vtable(const Support& s) { return VolTable{s.qx, s.qy, s.qz, s.qq}; }
 inline SupportMut mut(Support& s) { return SupportMut{s.sx, s.sy, s.sz, s.wx, s.wy, s.wz, s.orig, s.M}; }
 
 void launch_stage(hipStream_t s, int64_t nb, const double* xyz, const double* disp, const int32_t* perm,
@@ -82,6 +87,7 @@ struct VolDesc {
     void* out;
     int64_t nv;
     SupportView sv;
+    VolTable vt;   // filled by the batched launch itself
     int n;
     double inv_r;
 };
@@ -112,7 +118,9 @@ void sweep_layout_batch(int T, int& lpt, int& tpl);
 SweepArgs make_sweep_args(const IterCtx& ic, int g);
 FactorLArgs make_factor_l_args(const IterCtx& ic, int g, int nrec, int init_t);
 FactorUArgs make_factor_u_args(const IterCtx& ic);
-void launch_volume_batch(hipStream_t s, const VolDesc* tab, const BlockMap& map, int in_f64, int out_f64);
+// table_map: blocks of kBlock supports per surface for the volume tables; map: blocks of kBlock targets.
+void launch_volume_batch(hipStream_t s, const VolDesc* tab, const BlockMap& map, const BlockMap& table_map,
+                         int in_f64, int out_f64);
 // One greedy iteration of every context of a batch: three launches.  rpw
 // (1 or kMaxRowsPerWave) is the rows of M per factor wave; it must match the
 // block maps, and does not change any result.
@@ -153,6 +161,7 @@ void launch_certify(hipStream_t s, const Boundary& bd, const Support& sp, int n,
 // refreshed first; sp.fsx..fwz must hold sp.cap floats).
 void launch_volume32(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,
                      void* out, int out_f64);
+// FP64 Eq. (6); the volume table is refreshed first (sp.qx..qq must hold sp.cap doubles).
 void launch_volume(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,
                    void* out, int out_f64);
 

@@ -13,15 +13,8 @@ namespace gcb {
 
 #define GCB_LAUNCH(kern, grid, block, stream, ...) hipLaunchKernelGGL(kern, grid, block, 0, stream, __VA_ARGS__)
 
-// Accumulate sum_{j in [s0, s1)} w_j phi(|t - s_j|) for one target per lane.
-// VOL: the volume variant of phi (one square-root Newton step); otherwise the
-// full-accuracy phi of the greedy and the certificate.
-template <bool VOL>
-__device__ __forceinline__ double phi_r2(double r2) {
-    return VOL ? wendland_r2_vol(r2) : wendland_r2(r2);
-}
-
-template <bool VOL>
+// Accumulate sum_{j in [s0, s1)} w_j phi(|t - s_j|) for one target per lane
+// (full-accuracy phi: the greedy's certificate and monitor).
 __device__ __forceinline__ void accumulate64(double tx, double ty, double tz, int s0, int s1,
                                              const double* __restrict__ sx, const double* __restrict__ sy,
                                              const double* __restrict__ sz, const double* __restrict__ wx,
@@ -32,7 +25,7 @@ __device__ __forceinline__ void accumulate64(double tx, double ty, double tz, in
     for (; j + 4 <= s1; j += 4) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const double phi = phi_r2<VOL>(dist2(tx, ty, tz, sx[j + u], sy[j + u], sz[j + u]));
+            const double phi = wendland_r2(dist2(tx, ty, tz, sx[j + u], sy[j + u], sz[j + u]));
             ax = fma(wx[j + u], phi, ax);
             ay = fma(wy[j + u], phi, ay);
             az = fma(wz[j + u], phi, az);
@@ -40,11 +33,57 @@ __device__ __forceinline__ void accumulate64(double tx, double ty, double tz, in
     }
 #pragma unroll 1
     for (; j < s1; ++j) {
-        const double phi = phi_r2<VOL>(dist2(tx, ty, tz, sx[j], sy[j], sz[j]));
+        const double phi = wendland_r2(dist2(tx, ty, tz, sx[j], sy[j], sz[j]));
         ax = fma(wx[j], phi, ax);
         ay = fma(wy[j], phi, ay);
         az = fma(wz[j], phi, az);
     }
+}
+
+// Volume form of the same sum (Eq. 6).  Points are scaled by 1/(2R) and
+// centred at the first support; with u the target and v_j the supports
+// (table vt), d = |u|^2 + |v_j|^2 - 2 u.v_j = |u - v_j|^2 costs three FMAs
+// and an add per pair, the phi of wendland_quarter eleven more operations and
+// the quarter-rate rsq, and the three weights three FMAs.  m = -2 u, uu = |u|^2.
+__device__ __forceinline__ void accumulate_vol(double mx, double my, double mz, double uu, int n, const VolTable& vt,
+                                               const double* __restrict__ wx, const double* __restrict__ wy,
+                                               const double* __restrict__ wz, double& ax, double& ay, double& az) {
+    const double* __restrict__ qx = vt.qx;
+    const double* __restrict__ qy = vt.qy;
+    const double* __restrict__ qz = vt.qz;
+    const double* __restrict__ qq = vt.qq;
+    int j = 0;
+#pragma unroll 1
+    for (; j + 4 <= n; j += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double d = fma(mx, qx[j + u], fma(my, qy[j + u], fma(mz, qz[j + u], uu + qq[j + u])));
+            const double phi = wendland_quarter(d);
+            ax = fma(wx[j + u], phi, ax);
+            ay = fma(wy[j + u], phi, ay);
+            az = fma(wz[j + u], phi, az);
+        }
+    }
+#pragma unroll 1
+    for (; j < n; ++j) {
+        const double d = fma(mx, qx[j], fma(my, qy[j], fma(mz, qz[j], uu + qq[j])));
+        const double phi = wendland_quarter(d);
+        ax = fma(wx[j], phi, ax);
+        ay = fma(wy[j], phi, ay);
+        az = fma(wz[j], phi, az);
+    }
+}
+
+// Target of a volume sweep: scaled by 1/(2R), centred at the first support
+// (whose coordinates are kept scaled by 1/R).
+struct VolTarget {
+    double mx, my, mz, uu;
+};
+
+__device__ __forceinline__ VolTarget vol_target(double x, double y, double z, double inv_r, const SupportView& sv) {
+    const double h = 0.5 * inv_r;
+    const double ux = fma(x, h, -0.5 * sv.sx[0]), uy = fma(y, h, -0.5 * sv.sy[0]), uz = fma(z, h, -0.5 * sv.sz[0]);
+    return VolTarget{-2.0 * ux, -2.0 * uy, -2.0 * uz, fma(uz, uz, fma(uy, uy, ux * ux))};
 }
 
 // ---------------------------------------------------------------- reductions
@@ -948,7 +987,7 @@ __global__ __launch_bounds__(kBlock) void k_certify(int64_t nb, const double* __
     const bool live = t < nb;
     const int64_t tt = live ? t : nb - 1;
     double ax = 0.0, ay = 0.0, az = 0.0;
-    accumulate64<false>(px[tt], py[tt], pz[tt], 0, n, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
+    accumulate64(px[tt], py[tt], pz[tt], 0, n, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
     double e2 = 0.0;
     if (live) {
         const double ex = ax - pdx[t], ey = ay - pdy[t], ez = az - pdz[t];
@@ -1003,7 +1042,7 @@ __global__ __launch_bounds__(kBlock) void k_monitor(int64_t nb, const double* __
     const bool live = t < nb;
     const int64_t tt = live ? t : nb - 1;
     double ax = 0.0, ay = 0.0, az = 0.0;
-    accumulate64<false>(px[tt], py[tt], pz[tt], 0, s.n, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
+    accumulate64(px[tt], py[tt], pz[tt], 0, s.n, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
     double e2 = 0.0;
     if (live) {
         const double ex = ax - pdx[t], ey = ay - pdy[t], ez = az - pdz[t];
@@ -1045,17 +1084,28 @@ __global__ __launch_bounds__(kBlock) void k_monitor_final(int nblk, const double
 }
 
 // ---------------------------------------------------------------- volume (a7)
+// Half-scaled supports centred at the first one, and their squared norms.
+__global__ __launch_bounds__(kBlock) void k_volume_table(int n, SupportView sv, VolTable vt) {
+    const int j = blockIdx.x * kBlock + threadIdx.x;
+    if (j >= n) return;
+    const double x = fma(sv.sx[j], 0.5, -0.5 * sv.sx[0]);
+    const double y = fma(sv.sy[j], 0.5, -0.5 * sv.sy[0]);
+    const double z = fma(sv.sz[j], 0.5, -0.5 * sv.sz[0]);
+    vt.qx[j] = x;
+    vt.qy[j] = y;
+    vt.qz[j] = z;
+    vt.qq[j] = fma(z, z, fma(y, y, x * x));
+}
+
 template <typename TIn, typename TOut>
 __global__ __launch_bounds__(kBlock) void k_volume64(int64_t nv, const TIn* __restrict__ xyz, double inv_r,
-                                                     SupportView sv, int n, TOut* __restrict__ out) {
+                                                     SupportView sv, VolTable vt, int n, TOut* __restrict__ out) {
     const int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     const bool live = t < nv;
     const int64_t tt = live ? t : nv - 1;
-    const double tx = (double)xyz[3 * tt] * inv_r;
-    const double ty = (double)xyz[3 * tt + 1] * inv_r;
-    const double tz = (double)xyz[3 * tt + 2] * inv_r;
+    const VolTarget u = vol_target((double)xyz[3 * tt], (double)xyz[3 * tt + 1], (double)xyz[3 * tt + 2], inv_r, sv);
     double ax = 0.0, ay = 0.0, az = 0.0;
-    accumulate64<true>(tx, ty, tz, 0, n, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
+    accumulate_vol(u.mx, u.my, u.mz, u.uu, n, vt, sv.wx, sv.wy, sv.wz, ax, ay, az);
     if (live) {
         out[3 * t] = (TOut)ax;
         out[3 * t + 1] = (TOut)ay;
@@ -1138,6 +1188,20 @@ __global__ __launch_bounds__(kBlock) void k_support_f32(int n, SupportView sv, f
 
 // Eq. (6) for several surfaces in one launch: block b belongs to surface s
 // with map.off[s] <= b < map.off[s+1].
+__global__ __launch_bounds__(kBlock) void k_volume_table_batch(const VolDesc* __restrict__ tab, BlockMap map) {
+    const int s = batch_surface(map, blockIdx.x);
+    const VolDesc& d = tab[s];
+    const int j = (blockIdx.x - map.off[s]) * kBlock + threadIdx.x;
+    if (j >= d.n) return;
+    const double x = fma(d.sv.sx[j], 0.5, -0.5 * d.sv.sx[0]);
+    const double y = fma(d.sv.sy[j], 0.5, -0.5 * d.sv.sy[0]);
+    const double z = fma(d.sv.sz[j], 0.5, -0.5 * d.sv.sz[0]);
+    d.vt.qx[j] = x;
+    d.vt.qy[j] = y;
+    d.vt.qz[j] = z;
+    d.vt.qq[j] = fma(z, z, fma(y, y, x * x));
+}
+
 template <typename TIn, typename TOut>
 __global__ __launch_bounds__(kBlock) void k_volume_batch(const VolDesc* __restrict__ tab, BlockMap map) {
     const int s = batch_surface(map, blockIdx.x);
@@ -1146,11 +1210,10 @@ __global__ __launch_bounds__(kBlock) void k_volume_batch(const VolDesc* __restri
     const bool live = t < d.nv;
     const int64_t tt = live ? t : d.nv - 1;
     const TIn* xyz = static_cast<const TIn*>(d.xyz);
-    const double tx = (double)xyz[3 * tt] * d.inv_r;
-    const double ty = (double)xyz[3 * tt + 1] * d.inv_r;
-    const double tz = (double)xyz[3 * tt + 2] * d.inv_r;
+    const VolTarget u =
+        vol_target((double)xyz[3 * tt], (double)xyz[3 * tt + 1], (double)xyz[3 * tt + 2], d.inv_r, d.sv);
     double ax = 0.0, ay = 0.0, az = 0.0;
-    accumulate64<true>(tx, ty, tz, 0, d.n, d.sv.sx, d.sv.sy, d.sv.sz, d.sv.wx, d.sv.wy, d.sv.wz, ax, ay, az);
+    accumulate_vol(u.mx, u.my, u.mz, u.uu, d.n, d.vt, d.sv.wx, d.sv.wy, d.sv.wz, ax, ay, az);
     if (live) {
         TOut* out = static_cast<TOut*>(d.out);
         out[3 * t] = (TOut)ax;
@@ -1159,7 +1222,11 @@ __global__ __launch_bounds__(kBlock) void k_volume_batch(const VolDesc* __restri
     }
 }
 
-void launch_volume_batch(hipStream_t s, const VolDesc* tab, const BlockMap& map, int in_f64, int out_f64) {
+void launch_volume_batch(hipStream_t s, const VolDesc* tab, const BlockMap& map, const BlockMap& table_map,
+                         int in_f64, int out_f64) {
+    if (table_map.off[table_map.count] > 0)
+        GCB_LAUNCH(k_volume_table_batch, dim3((unsigned)table_map.off[table_map.count]), dim3(kBlock), s, tab,
+                   table_map);
     const dim3 g((unsigned)map.off[map.count]);
     if (in_f64 && out_f64) GCB_LAUNCH((k_volume_batch<double, double>), g, dim3(kBlock), s, tab, map);
     else if (in_f64) GCB_LAUNCH((k_volume_batch<double, float>), g, dim3(kBlock), s, tab, map);
@@ -1347,9 +1414,10 @@ void launch_certify(hipStream_t s, const Boundary& bd, const Support& sp, int n,
 }
 
 template <typename TIn, typename TOut>
-static void vol(hipStream_t s, int64_t nv, const void* xyz, double inv_r, SupportView sv, int n, void* out) {
+static void vol(hipStream_t s, int64_t nv, const void* xyz, double inv_r, SupportView sv, VolTable vt, int n,
+                void* out) {
     const unsigned g = (unsigned)((nv + kBlock - 1) / kBlock);
-    GCB_LAUNCH((k_volume64<TIn, TOut>), dim3(g), dim3(kBlock), s, nv, (const TIn*)xyz, inv_r, sv, n, (TOut*)out);
+    GCB_LAUNCH((k_volume64<TIn, TOut>), dim3(g), dim3(kBlock), s, nv, (const TIn*)xyz, inv_r, sv, vt, n, (TOut*)out);
 }
 
 template <typename TIn, typename TOut>
@@ -1373,10 +1441,12 @@ void launch_volume32(hipStream_t s, int64_t nv, const void* xyz, int in_f64, dou
 void launch_volume(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,
                    void* out, int out_f64) {
     SupportView sv = view(sp);
-    if (in_f64 && out_f64) vol<double, double>(s, nv, xyz, inv_r, sv, n, out);
-    else if (in_f64) vol<double, float>(s, nv, xyz, inv_r, sv, n, out);
-    else if (out_f64) vol<float, double>(s, nv, xyz, inv_r, sv, n, out);
-    else vol<float, float>(s, nv, xyz, inv_r, sv, n, out);
+    VolTable vt = vtable(sp);
+    if (n > 0) GCB_LAUNCH(k_volume_table, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), s, n, sv, vt);
+    if (in_f64 && out_f64) vol<double, double>(s, nv, xyz, inv_r, sv, vt, n, out);
+    else if (in_f64) vol<double, float>(s, nv, xyz, inv_r, sv, vt, n, out);
+    else if (out_f64) vol<float, double>(s, nv, xyz, inv_r, sv, vt, n, out);
+    else vol<float, float>(s, nv, xyz, inv_r, sv, vt, n, out);
 }
 
 }  // namespace gcb

@@ -97,6 +97,7 @@ void copy_out(gcb_ctx* ctx, void* dst, const void* src, size_t bytes, int mem) {
 void free_support(Support& sp) {
     dfree(sp.sx); dfree(sp.sy); dfree(sp.sz); dfree(sp.wx); dfree(sp.wy); dfree(sp.wz);
     dfree(sp.fsx); dfree(sp.fsy); dfree(sp.fsz); dfree(sp.fwx); dfree(sp.fwy); dfree(sp.fwz);
+    dfree(sp.qx); dfree(sp.qy); dfree(sp.qz); dfree(sp.qq);
     dfree(sp.orig); dfree(sp.M); dfree(sp.Mc); dfree(sp.l);
     sp.cap = 0;
 }
@@ -109,6 +110,13 @@ void free_boundary(Boundary& bd) {
     bd.m = 0;
     bd.alloc_nb = 0;
     bd.alloc_m = 0;
+}
+
+// The FP64 volume sweep's table, allocated on first use (sp.cap doubles each).
+void ensure_volume_table(gcb_ctx* ctx) {
+    Support& sp = ctx->sp;
+    if (sp.qx) return;
+    dalloc(ctx, sp.qx, sp.cap); dalloc(ctx, sp.qy, sp.cap); dalloc(ctx, sp.qz, sp.cap); dalloc(ctx, sp.qq, sp.cap);
 }
 
 // (Re)allocate the support arrays for capacity `cap`, keeping the first n
@@ -530,6 +538,8 @@ size_t ctx_device_bytes(const gcb_ctx* ctx) {
     b += sizeof(int32_t) * ((size_t)bd.alloc_m + 1);
     const size_t tri = (size_t)sp.cap * (size_t)(sp.cap + 1) / 2;
     b += (size_t)sp.cap * (7 * sizeof(double) + sizeof(int32_t)) + 2 * sizeof(double) * tri;
+    if (sp.fsx) b += 6 * sizeof(float) * (size_t)sp.cap;   // FP32 evaluation copies
+    if (sp.qx) b += 4 * sizeof(double) * (size_t)sp.cap;   // volume table
     b += sizeof(double) * (size_t)ctx->Pb_cap + sizeof(ArgRec) * (size_t)ctx->argrec_cap;
     b += (size_t)ctx->log_cap * (2 * sizeof(int32_t) + sizeof(double) + 1);
     b += sizeof(double) * (size_t)ctx->red_cap + ctx->tmp_cap + sizeof(GState) + sizeof(IterRec);
@@ -825,19 +835,24 @@ int gcb_deform_batch(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, const in
         ensure_tables(b, bytes);
         BHIPCHK(b, hipStreamSynchronize(b->stream));   // the tables may still be read by earlier launches
         VolDesc* t = static_cast<VolDesc*>(b->htab);
-        BlockMap map{};
+        BlockMap map{}, tmap{};
         map.count = count;
+        tmap.count = count;
         for (int32_t i = 0; i < count; ++i) {
             gcb_ctx* c = ctxs[i];
             attach(b, c);
             if (!c->selected) bfail(b, GCB_E_STATE, "context without a finished selection");
             if (nv[i] < 0 || (nv[i] > 0 && (!xyz[i] || !out[i]))) bfail(b, GCB_E_INVALID, "bad volume arguments");
-            t[i] = VolDesc{xyz[i], out[i], nv[i], view(c->sp), (int)c->info.nc, c->bd.inv_r};
+            const int n = nv[i] > 0 ? (int)c->info.nc : 0;   // a surface without targets needs no table
+            if (n > 0) ensure_volume_table(c);
+            t[i] = VolDesc{xyz[i], out[i], nv[i], view(c->sp), vtable(c->sp), n, c->bd.inv_r};
             map.off[i + 1] = map.off[i] + (int)((nv[i] + kBlock - 1) / kBlock);
+            tmap.off[i + 1] = tmap.off[i] + (n + kBlock - 1) / kBlock;
         }
         if (map.off[count] == 0) return GCB_OK;
         BHIPCHK(b, hipMemcpyAsync(b->dtab, b->htab, bytes, hipMemcpyHostToDevice, b->stream));
-        launch_volume_batch(b->stream, static_cast<VolDesc*>(b->dtab), map, in_dtype == GCB_F64, out_dtype == GCB_F64);
+        launch_volume_batch(b->stream, static_cast<VolDesc*>(b->dtab), map, tmap, in_dtype == GCB_F64,
+                            out_dtype == GCB_F64);
         BHIPCHK(b, hipGetLastError());
         return GCB_OK;
     });
@@ -1134,6 +1149,7 @@ int gcb_deform(gcb_ctx* ctx, int64_t nv, const void* xyz, int in_dtype, void* ou
             launch_volume32(ctx->stream, nv, din, in_dtype == GCB_F64, ctx->bd.inv_r, sp, (int)ctx->info.nc, dout,
                             out_dtype == GCB_F64);
         } else {
+            ensure_volume_table(ctx);
             launch_volume(ctx->stream, nv, din, in_dtype == GCB_F64, ctx->bd.inv_r, ctx->sp, (int)ctx->info.nc, dout,
                           out_dtype == GCB_F64);
         }
