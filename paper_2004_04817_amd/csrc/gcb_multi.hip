@@ -77,8 +77,9 @@ __global__ __launch_bounds__(kMWaves * 64) void k_volume_multi(int64_t nv, const
     const int nt = R / 16;
     const int64_t tbase = ((int64_t)blockIdx.x * kMWaves + wave) * 16;
     const int64_t tgt = min(tbase + (lane & 15), nv - 1);
-    const double tx = (double)xyz[3 * tgt] * inv_r, ty = (double)xyz[3 * tgt + 1] * inv_r,
-                 tz = (double)xyz[3 * tgt + 2] * inv_r;
+    // points scaled by 1/(2R): phi from the quarter squared distance (one square-root Newton step)
+    const double h = 0.5 * inv_r;
+    const double tx = (double)xyz[3 * tgt] * h, ty = (double)xyz[3 * tgt + 1] * h, tz = (double)xyz[3 * tgt + 2] * h;
     d4 acc[kMaxR / 16];
 #pragma unroll
     for (int t = 0; t < kMaxR / 16; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
@@ -93,15 +94,15 @@ __global__ __launch_bounds__(kMWaves * 64) void k_volume_multi(int64_t nv, const
         }
         if (threadIdx.x < kMChunk) {
             const int s = threadIdx.x;
-            lc[0][s] = s < cn ? sx[c0 + s] : 1e3;
-            lc[1][s] = s < cn ? sy[c0 + s] : 1e3;
-            lc[2][s] = s < cn ? sz[c0 + s] : 1e3;
+            lc[0][s] = s < cn ? 0.5 * sx[c0 + s] : 1e3;
+            lc[1][s] = s < cn ? 0.5 * sy[c0 + s] : 1e3;
+            lc[2][s] = s < cn ? 0.5 * sz[c0 + s] : 1e3;
         }
         __syncthreads();
 #pragma unroll 1
         for (int s0 = 0; s0 < kMChunk; s0 += 4) {
             const int s = s0 + kq;
-            const double a = wendland_r2(dist2(tx, ty, tz, lc[0][s], lc[1][s], lc[2][s]));
+            const double a = wendland_quarter(dist2(tx, ty, tz, lc[0][s], lc[1][s], lc[2][s]));
 #pragma unroll
             for (int t = 0; t < kMaxR / 16; ++t) {
                 if (t < nt) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, lw[s][16 * t + jl], acc[t], 0, 0, 0);
