@@ -154,3 +154,27 @@ def test_fp32_evaluation_accuracy_and_dtypes():
     o_s = c.deform(np.ascontiguousarray(p.xyz[S]))
     assert np.abs(o_s - p.disp[S]).max() / md <= 1e-3
     c.close()
+
+
+def test_volume_far_points_and_translation():
+    """Eq. 6 is exactly zero beyond the radius of every support, and the volume
+    sweep's centred distances keep the parity bar when the whole problem sits
+    far from the origin (the centring removes the offset before any square)."""
+    import dataclasses
+    p = synth.config_small_ellipsoid(nv=5003)
+    ctx, info, S, W, log = gpu_select(p)
+    md = p.max_disp
+    far = p.volume + np.array([10.0, 0.0, 0.0]) * p.radius + 3.0
+    assert np.all(ctx.deform(far) == 0.0)
+    ctx.close()
+    off = np.array([1.0e3, -2.0e3, 5.0e2]) * p.radius
+    q = dataclasses.replace(p, xyz=p.xyz + off, volume=p.volume + off)
+    ctx, info, S, W, log = gpu_select(q)
+    ref = oracle.interpolate(q.xyz[S], W, q.radius, q.volume)
+    err = np.abs(ctx.deform(q.volume) - ref).max()
+    print("translated volume max err / max|d|:", err / md)
+    assert err <= 1e-11 * md
+    # the supports themselves: the interpolation condition of Eq. 3
+    osup = ctx.deform(q.xyz[S])
+    assert np.abs(osup - q.disp[S]).max() <= 1e-9 * md
+    ctx.close()
