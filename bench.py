@@ -48,6 +48,8 @@ def parse():
                     help="also replay the stream at this arrival rate (req/s), above one-at-a-time capacity (0: skip)")
     ap.add_argument("--m-sweep", default="1,5,10,20,40,80,107,160",
                     help="also select the wing at these group counts m (the paper's m-sweep, free Nc; '' skips)")
+    ap.add_argument("--no-host-buffers", dest="host_buffers", action="store_false",
+                    help="skip the PCIe-inclusive step with host inputs and output")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="before timing, one device-to-device copy of this many MiB (the known-size "
                          "kernel that scales FETCH_SIZE / WRITE_SIZE counter readings)")
@@ -63,21 +65,36 @@ def kernel_source_hash(kernel_src: str) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_src: str) -> float | None:
-    """Per-launch HBM bytes of the volume sweep from the committed rocprofv3 summary,
-    or None when the kernel source has changed since the counters were taken."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "volume_wing80k_traffic.md")
+def profile_values(name: str, kernel_src: str, keys: tuple) -> dict | None:
+    """`key: value` lines of a committed rocprofv3 summary under profiles/, or None when
+    the kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name)
     try:
         text = open(path).read()
     except OSError:
         return None
-    vals = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:",
-                                                                           "kernel_source_sha256_prefix:")))
-    cur = kernel_source_hash(kernel_src)
-    if vals.get("kernel_source_sha256_prefix", "").strip() != cur:
+    vals = {k.strip(): v.strip() for k, v in (l.split(":", 1) for l in text.splitlines()
+                                              if l.startswith(keys + ("kernel_source_sha256_prefix:",)))}
+    if vals.get("kernel_source_sha256_prefix", "") != kernel_source_hash(kernel_src):
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    return vals
+
+
+def measured_traffic(kernel_src: str) -> float | None:
+    """Per-launch HBM bytes of the volume sweep (FETCH_SIZE + WRITE_SIZE, calibrated)."""
+    vals = profile_values("volume_wing80k_traffic.md", kernel_src, ("traffic_bytes_per_launch:",))
+    return float(vals["traffic_bytes_per_launch"]) if vals else None
+
+
+def measured_valu(kernel_src: str) -> dict | None:
+    """Issue slots per pair, the op-mix ceiling and VALUBusy of the volume sweep."""
+    vals = profile_values("volume_wing80k_valu.md", kernel_src,
+                          ("issue_slots_per_pair:", "op_mix_ceiling_frac:", "valu_busy_pct:"))
+    if not vals:
+        return None
+    return {"issue_slots_per_pair": float(vals["issue_slots_per_pair"]),
+            "op_mix_ceiling_frac": float(vals["op_mix_ceiling_frac"]),
+            "valu_busy_pct": float(vals["valu_busy_pct"])}
 
 
 def problem(name):
@@ -288,6 +305,11 @@ def main():
                      "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs_volume,
                      "launch_ms": vol_avg_ms},
     }
+    valu = measured_valu(os.path.join(ROOT, "paper_2004_04817_amd", "csrc", "gcb_kernels.hip"))
+    if valu and a.config == "wing":
+        # the instruction mix caps the fraction of peak: 21 flops per pair over 2 flops per issue slot
+        valu["frac_of_op_mix_ceiling"] = (achieved / FP64_PEAK_TFLOPS) / valu["op_mix_ceiling_frac"]
+        rec["roofline"]["instruction_mix"] = valu
     # dense FP64 refactorisation of the selected support system (blocked Cholesky + triangular inverse, MFMA)
     drift, rinfo = ctx.refactor()
     drift, rinfo = ctx.refactor()
@@ -319,6 +341,30 @@ def main():
     del out32
     ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
     ctx.select()
+    if a.host_buffers:
+        # the same step with the inputs and the output in host memory (pageable numpy arrays): boundary copied in,
+        # selection, volume points copied in and displacements copied out; never the headline value
+        hctx = gcb.Context(0)
+        hout = np.empty_like(p.volume)
+        hs = []
+        for r in range(3):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            hctx.set_boundary(p.xyz, p.disp)
+            hctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
+            hinfo = hctx.select()
+            hctx.deform(p.volume, out=hout)
+            torch.cuda.synchronize()
+            if r > 0:
+                hs.append(time.perf_counter() - ts)
+        hsec = float(np.mean(hs))
+        rec["host_buffers"] = {"ms_per_step": 1e3 * hsec,
+                               "pair_evals_per_s": (hinfo["pairs_group"] + hinfo["pairs_append"] + nv * nc) / hsec,
+                               "bytes_in": int(p.xyz.nbytes + p.disp.nbytes + p.volume.nbytes),
+                               "bytes_out": int(hout.nbytes),
+                               "what": "PCIe-inclusive step: host boundary and volume in, host displacements out"}
+        hctx.close()
+        del hout
     if a.modes > 0 and a.config == "wing":
         import synth
         modes = torch.from_numpy(synth.config_modes(p, a.modes)).to(dev)
