@@ -157,7 +157,11 @@ int64_t gcb_get_log(gcb_ctx *ctx, int32_t *group, int64_t *node, double *err, in
 /* Eq. (6): displacements of nv arbitrary points from the selected supports:
  * out[k] = sum_{s in S} w_s phi(|r_k - r_s| / R).  xyz (nv, 3) of in_dtype,
  * out (nv, 3) of out_dtype (GCB_F32 or GCB_F64), both in `mem`.  Arithmetic
- * is FP64; nv = 0 is a no-op.  Requires a finished gcb_select. */
+ * is FP64 (unless GCB_PREC_FP32_EVAL): squared distances from coordinates
+ * centred at the first support, the square root to about 1e-14 relative, so
+ * each phi is within about 1e-13 of its exact value.  The first FP64 call
+ * allocates a device table of 32 bytes per support capacity, kept by the
+ * context.  nv = 0 is a no-op.  Requires a finished gcb_select. */
 int gcb_deform(gcb_ctx *ctx, int64_t nv, const void *xyz, int in_dtype, void *out, int out_dtype, int mem);
 
 /* Multiple right-hand sides on one support set: k_modes displacement fields
