@@ -1119,9 +1119,10 @@ __global__ __launch_bounds__(kBlock) void k_volume64(int64_t nv, const TIn* __re
 // error of phi itself.
 constexpr int kChunk32 = 32;
 
+// phi in FP32 from r2 >= 0: the hardware square root (about 1 ulp) needs no
+// guard at r2 = 0, unlike r2 * rsq(r2).
 __device__ __forceinline__ float wendland_r2_f32(float r2) {
-    const float x = fmaxf(r2, 1e-30f);
-    const float eta = x * __builtin_amdgcn_rsqf(x);
+    const float eta = __builtin_amdgcn_sqrtf(r2);
     const float t = fminf(fmaxf(1.0f - eta, 0.0f), 1.0f);
     const float t2 = t * t;
     return (t2 * t2) * fmaf(-4.0f, t, 5.0f);
