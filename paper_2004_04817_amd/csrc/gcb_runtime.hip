@@ -50,6 +50,15 @@ void dalloc(gcb_ctx* ctx, T*& p, size_t count) {
     ctx->alloc_gen++;   // captured graphs bake in buffer addresses
 }
 
+// Grow p to at least `need` elements; the recorded capacity changes only once the allocation succeeded.
+template <typename T, typename C>
+void dalloc_cap(gcb_ctx* ctx, T*& p, C& cap, C need) {
+    if (cap >= need && p) return;
+    cap = 0;
+    dalloc(ctx, p, (size_t)need);
+    cap = need;
+}
+
 template <typename T>
 void dfree(T*& p) {
     if (p) (void)hipFree(p);
@@ -113,10 +122,19 @@ void free_boundary(Boundary& bd) {
 }
 
 // The FP64 volume sweep's table, allocated on first use (sp.cap doubles each).
+// (A failed allocation leaves some of the arrays unset: all are allocated again on the next call.)
 void ensure_volume_table(gcb_ctx* ctx) {
     Support& sp = ctx->sp;
-    if (sp.qx) return;
+    if (sp.qx && sp.qy && sp.qz && sp.qq) return;
     dalloc(ctx, sp.qx, sp.cap); dalloc(ctx, sp.qy, sp.cap); dalloc(ctx, sp.qz, sp.cap); dalloc(ctx, sp.qq, sp.cap);
+}
+
+// The FP32 evaluation copies, allocated on first use (sp.cap floats each).
+void ensure_fp32_copies(gcb_ctx* ctx) {
+    Support& sp = ctx->sp;
+    if (sp.fsx && sp.fsy && sp.fsz && sp.fwx && sp.fwy && sp.fwz) return;
+    dalloc(ctx, sp.fsx, sp.cap); dalloc(ctx, sp.fsy, sp.cap); dalloc(ctx, sp.fsz, sp.cap);
+    dalloc(ctx, sp.fwx, sp.cap); dalloc(ctx, sp.fwy, sp.cap); dalloc(ctx, sp.fwz, sp.cap);
 }
 
 // (Re)allocate the support arrays for capacity `cap`, keeping the first n
@@ -126,12 +144,17 @@ void grow_support(gcb_ctx* ctx, int64_t cap, int64_t n) {
     Support nw;
     nw.cap = cap;
     const size_t tri = (size_t)cap * (size_t)(cap + 1) / 2;
-    dalloc(ctx, nw.sx, cap); dalloc(ctx, nw.sy, cap); dalloc(ctx, nw.sz, cap);
-    dalloc(ctx, nw.wx, cap); dalloc(ctx, nw.wy, cap); dalloc(ctx, nw.wz, cap);
-    dalloc(ctx, nw.orig, cap);
-    dalloc(ctx, nw.M, tri);
-    dalloc(ctx, nw.Mc, tri);
-    dalloc(ctx, nw.l, cap);
+    try {
+        dalloc(ctx, nw.sx, cap); dalloc(ctx, nw.sy, cap); dalloc(ctx, nw.sz, cap);
+        dalloc(ctx, nw.wx, cap); dalloc(ctx, nw.wy, cap); dalloc(ctx, nw.wz, cap);
+        dalloc(ctx, nw.orig, cap);
+        dalloc(ctx, nw.M, tri);
+        dalloc(ctx, nw.Mc, tri);
+        dalloc(ctx, nw.l, cap);
+    } catch (...) {
+        free_support(nw);   // the current arrays stay as they were
+        throw;
+    }
     if (n > 0 && sp.cap > 0) {
         const size_t b8 = sizeof(double) * (size_t)n;
         HIPCHK(ctx, hipMemcpyAsync(nw.sx, sp.sx, b8, hipMemcpyDeviceToDevice, ctx->stream));
@@ -150,10 +173,7 @@ void grow_support(gcb_ctx* ctx, int64_t cap, int64_t n) {
     free_support(sp);
     sp = nw;
     const int64_t nbl = (cap + kRowsL - 1) / kRowsL + 1;
-    if (ctx->Pb_cap < 4 * nbl) {
-        ctx->Pb_cap = 4 * nbl;
-        dalloc(ctx, ctx->Pb, ctx->Pb_cap);
-    }
+    dalloc_cap(ctx, ctx->Pb, ctx->Pb_cap, (decltype(ctx->Pb_cap))(4 * nbl));
 }
 
 template <typename T>
@@ -263,10 +283,7 @@ IterCtx make_ic(gcb_ctx* ctx) {
 
 void ensure_red(gcb_ctx* ctx) {
     const int64_t need = 2 * (ctx->bd.nb / kBlock + 2) + 2;
-    if (ctx->red_cap < need) {
-        ctx->red_cap = need;
-        dalloc(ctx, ctx->red, ctx->red_cap);
-    }
+    dalloc_cap(ctx, ctx->red, ctx->red_cap, (decltype(ctx->red_cap))need);
 }
 
 void ensure_tmp(gcb_ctx* ctx, size_t need) {
@@ -339,10 +356,8 @@ void select_begin(gcb_ctx* ctx) {
         grow_support(ctx, cap0, 0);
     }
     const int64_t nrec = std::max<int64_t>(512, sweep_blocks(bd.gmax));
-    if (ctx->argrec_cap < nrec + 1) {
-        ctx->argrec_cap = nrec + 1;   // the last record holds the three starting nodes
-        dalloc(ctx, ctx->argrec, ctx->argrec_cap);
-    }
+    // the last record holds the three starting nodes
+    dalloc_cap(ctx, ctx->argrec, ctx->argrec_cap, (decltype(ctx->argrec_cap))(nrec + 1));
     if (!ctx->state) dalloc(ctx, ctx->state, 1);
     if (!ctx->irec) dalloc(ctx, ctx->irec, 1);
     if (!ctx->state_pin) HIPCHK(ctx, hipHostMalloc(reinterpret_cast<void**>(&ctx->state_pin), sizeof(GState)));
@@ -941,10 +956,10 @@ int gcb_set_boundary(gcb_ctx* ctx, int64_t nb, const double* xyz, const double* 
         HIPCHK(ctx, hipSetDevice(ctx->device));
         ctx->selected = false;
         ctx->warm_ok = false;
-        free_boundary(ctx->bd);
-        ctx->bd.nb = nb;
+        free_boundary(ctx->bd);   // nb = 0 until both copies exist
         dalloc(ctx, ctx->bd.xyz0, 3 * (size_t)nb);
         dalloc(ctx, ctx->bd.disp0, 3 * (size_t)nb);
+        ctx->bd.nb = nb;
         copy_in(ctx, ctx->bd.xyz0, xyz, sizeof(double) * 3 * nb, mem);
         copy_in(ctx, ctx->bd.disp0, disp, sizeof(double) * 3 * nb, mem);
         if (mem == GCB_MEM_DEVICE) {
@@ -1142,10 +1157,7 @@ int gcb_deform(gcb_ctx* ctx, int64_t nv, const void* xyz, int in_dtype, void* ou
         }
         if (ctx->params.precision == GCB_PREC_FP32_EVAL) {
             Support& sp = ctx->sp;
-            if (!sp.fsx) {
-                dalloc(ctx, sp.fsx, sp.cap); dalloc(ctx, sp.fsy, sp.cap); dalloc(ctx, sp.fsz, sp.cap);
-                dalloc(ctx, sp.fwx, sp.cap); dalloc(ctx, sp.fwy, sp.cap); dalloc(ctx, sp.fwz, sp.cap);
-            }
+            ensure_fp32_copies(ctx);
             launch_volume32(ctx->stream, nv, din, in_dtype == GCB_F64, ctx->bd.inv_r, sp, (int)ctx->info.nc, dout,
                             out_dtype == GCB_F64);
         } else {
@@ -1236,10 +1248,7 @@ void rebuild_factor(gcb_ctx* ctx, int n, bool compare, double* drift) {
     double* Wb = reinterpret_cast<double*>(base + 2 * dense_b + diag_b);
     int32_t* bad = reinterpret_cast<int32_t*>(base + 2 * dense_b + diag_b + w_b);
     const int nred = dense_pack_blocks();
-    if (ctx->red_cap < 2 * nred + 2) {
-        ctx->red_cap = 2 * nred + 2;
-        dalloc(ctx, ctx->red, ctx->red_cap);
-    }
+    dalloc_cap(ctx, ctx->red, ctx->red_cap, (decltype(ctx->red_cap))(2 * nred + 2));
     ensure_red(ctx);
     HIPCHK(ctx, hipMemsetAsync(bad, 0, sizeof(int32_t), ctx->stream));
     HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
@@ -1323,10 +1332,7 @@ int gcb_set_support(gcb_ctx* ctx, const int64_t* idx, int64_t n, int mem, gcb_se
         if (!ctx->ev0) HIPCHK(ctx, hipEventCreate(&ctx->ev0));
         if (!ctx->ev1) HIPCHK(ctx, hipEventCreate(&ctx->ev1));
         const int64_t nrec = std::max<int64_t>(512, sweep_blocks(ctx->bd.gmax));
-        if (ctx->argrec_cap < nrec + 1) {
-            ctx->argrec_cap = nrec + 1;
-            dalloc(ctx, ctx->argrec, ctx->argrec_cap);
-        }
+        dalloc_cap(ctx, ctx->argrec, ctx->argrec_cap, (decltype(ctx->argrec_cap))(nrec + 1));
         if (ctx->log_cap == 0) grow_log(ctx, 0, 65536);
         HIPCHK(ctx, hipMemcpyAsync(ctx->sp.orig, o.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice,
                                    ctx->stream));
