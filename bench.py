@@ -87,14 +87,21 @@ def measured_traffic(kernel_src: str) -> float | None:
 
 
 def measured_valu(kernel_src: str) -> dict | None:
-    """Issue slots per pair, the op-mix ceiling and VALUBusy of the volume sweep."""
+    """Issue slots per pair, the op-mix ceiling and VALUBusy of the volume sweep, and VALUBusy of the
+    greedy's three kernels."""
     vals = profile_values("volume_wing80k_valu.md", kernel_src,
-                          ("issue_slots_per_pair:", "op_mix_ceiling_frac:", "valu_busy_pct:"))
+                          ("issue_slots_per_pair:", "op_mix_ceiling_frac:", "valu_busy_pct:",
+                           "greedy_valu_busy_pct:"))
     if not vals:
         return None
+    greedy = {}
+    for item in vals.get("greedy_valu_busy_pct", "").split(","):
+        if item.strip():
+            k, v = item.split()
+            greedy[k] = float(v)
     return {"issue_slots_per_pair": float(vals["issue_slots_per_pair"]),
             "op_mix_ceiling_frac": float(vals["op_mix_ceiling_frac"]),
-            "valu_busy_pct": float(vals["valu_busy_pct"])}
+            "valu_busy_pct": float(vals["valu_busy_pct"]), "greedy_valu_busy_pct": greedy}
 
 
 def problem(name):
@@ -306,13 +313,18 @@ def main():
                      "launch_ms": vol_avg_ms},
     }
     valu = measured_valu(os.path.join(ROOT, "paper_2004_04817_amd", "csrc", "gcb_kernels.hip"))
+    greedy_busy = valu.pop("greedy_valu_busy_pct") if valu else None
     if valu and a.config == "wing":
         # the instruction mix caps the fraction of peak: 21 flops per pair over 2 flops per issue slot
         valu["frac_of_op_mix_ceiling"] = (achieved / FP64_PEAK_TFLOPS) / valu["op_mix_ceiling_frac"]
         rec["roofline"]["instruction_mix"] = valu
+    # the greedy phase: one iteration is three dependent launches; the VALUs are nearly idle in them
+    rec["greedy_iteration"] = {"bound": "latency", "kernels_per_iteration": 3,
+                               "us_per_iteration": 1e3 * rec["phases_ms"]["select"] / info["iterations"],
+                               "valu_busy_pct": greedy_busy if a.config == "wing" else None}
     # dense FP64 refactorisation of the selected support system (blocked Cholesky + triangular inverse, MFMA)
-    drift, rinfo = ctx.refactor()
-    drift, rinfo = ctx.refactor()
+    drift, rinfo = ctx.refactor()        # against the incrementally grown factor
+    _, rinfo = ctx.refactor()            # timed again with warm caches
     rflops = 2.0 * nc ** 3 / 3.0
     rec["refactor"] = {"nc": nc, "ms": rinfo["ms_select"], "drift": drift,
                        "tflops": rflops / (rinfo["ms_select"] * 1e-3) / 1e12,

@@ -1,8 +1,14 @@
 // Dense FP64 refactorisation of the support system: Phi_S = L L^T (blocked
-// right-looking Cholesky) and M = L^-1 (blocked triangular inverse), with the
+// right-looking Cholesky) and, in the same block steps, M = L^-1, with the
 // block products on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  Used to
 // rebuild the inverse factor of a given support set, and to re-certify the
 // incrementally grown factor against rounding drift.
+//
+// The inverse follows from L M = I by blocks: M_kk = L_kk^-1 and, for j < k,
+// M_kj = -M_kk T_kj with T_kj = sum_{l=j}^{k-1} L_kl M_lj.  Step k of the
+// Cholesky produces the panel L_{.,k}; the same step's update adds
+// L_ik M_kj to T_ij for every i > k and j <= k, so T_kj is complete when
+// step k starts and the inverse costs no launches of its own.
 //
 // Matrices are dense row-major np x np with np = n rounded up to kDB; the
 // padding is the identity, so every block step is full-sized:
@@ -45,13 +51,14 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 
 // Step k0 of the Cholesky factorisation.  Wave 0 factors the diagonal block
 // (already updated by the earlier steps) in registers, one row per lane, with
-// the column entries broadcast across lanes; the factored block goes to LDS
-// and, from workgroup 0, to Dbuf (the diagonal blocks of L are read from there
-// later; A's own diagonal block is only read in this launch, so no workgroup
-// overwrites what another still reads).  Then each workgroup solves kBlock
-// rows of the panel below: x L_kk^T = a.
+// the column entries broadcast across lanes; the factored block goes to LDS.
+// A's diagonal block is only read in this launch and never written, so no
+// workgroup overwrites what another still reads.  In workgroup 0, 32 lanes of
+// wave 1 then form M_kk = L_kk^-1 (lane c: column c by forward substitution)
+// into Md.  Each workgroup solves kBlock rows of the panel below:
+// x L_kk^T = a.
 __global__ __launch_bounds__(kBlock) void k_chol_step(int np, int k0, double* __restrict__ A,
-                                                      double* __restrict__ Dbuf, int32_t* __restrict__ bad) {
+                                                      double* __restrict__ Md, int32_t* __restrict__ bad) {
     __shared__ double D[kDB][kDB + 1];
     __shared__ double Rd[kDB];
     const int tid = threadIdx.x;
@@ -85,17 +92,27 @@ __global__ __launch_bounds__(kBlock) void k_chol_step(int np, int k0, double* __
         if (lane < kDB) {
 #pragma unroll
             for (int c = 0; c < kDB; ++c) D[lane][c] = c <= lane ? a[c] : 0.0;
-            if (blockIdx.x == 0) {
-                double* Db = Dbuf + (size_t)(k0 / kDB) * kDB * kDB + (size_t)lane * kDB;
-#pragma unroll
-                for (int c = 0; c < kDB; ++c) Db[c] = c <= lane ? a[c] : 0.0;
-            }
         }
         if (lane == 0 && sing) bad[0] = 1;
     }
     __syncthreads();
     if (tid < kDB) Rd[tid] = 1.0 / D[tid][tid];
     __syncthreads();
+    if (blockIdx.x == 0 && tid >= 64 && tid < 64 + kDB) {
+        const int c = tid - 64;
+        double x[kDB];
+#pragma unroll
+        for (int i = 0; i < kDB; ++i) x[i] = i == c ? 1.0 : 0.0;
+        // L_kk x = e_c, right-looking: x_t is final once the earlier columns are applied
+#pragma unroll
+        for (int t = 0; t < kDB; ++t) {
+            x[t] *= Rd[t];
+#pragma unroll
+            for (int i = t + 1; i < kDB; ++i) x[i] = fma(-D[i][t], x[t], x[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < kDB; ++i) Md[(size_t)(k0 + i) * np + k0 + c] = x[i];
+    }
     const int r = k0 + kDB + blockIdx.x * kBlock + tid;
     if (r >= np) return;
     double* Ar = A + (size_t)r * np + k0;
@@ -122,18 +139,66 @@ __device__ __forceinline__ void tri_index(int b, int& ti, int& tj) {
     tj = b - i * (i + 1) / 2;
 }
 
-// Trailing update after step k0: A[k1:, k1:] -= P P^T (lower blocks) with
-// P = A[k1:, k0:k1], k1 = k0 + kDB.  One workgroup per kDB x kDB block, one
-// wave per 16 x 16 quarter, K = kDB on the matrix cores.
-__global__ __launch_bounds__(kBlock) void k_chol_update(int np, int k0, double* __restrict__ A) {
+// M_kj = -M_kk T_kj (j < k) or M_kk (j = k) into Ms, one 16 x 16 quarter per
+// wave (K = kDB on the matrix cores); block row k starts at k0.
+__device__ __forceinline__ void inverse_row_block(int np, int k0, int jb, const double* __restrict__ Tb,
+                                                  const double* __restrict__ Md, double (*Ms)[kDB + 1]) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int qi = wave >> 1, qj = wave & 1, li = lane & 15, lk = lane >> 4;
+    if (jb * kDB == k0) {
+        for (int x = threadIdx.x; x < kDB * kDB; x += kBlock) Ms[x / kDB][x % kDB] = Md[(size_t)(k0 + x / kDB) * np + k0 + x % kDB];
+        return;
+    }
+    const double* Mkk = Md + (size_t)(k0 + 16 * qi + li) * np + k0;
+    const double* Tkj = Tb + (size_t)k0 * np + kDB * jb + 16 * qj + li;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < kDB; s += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Mkk[s + lk], Tkj[(size_t)(s + lk) * np], acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Ms[16 * qi + lk + 4 * r][16 * qj + li] = -acc[r];
+}
+
+// Update after step k0 (k1 = k0 + kDB), one workgroup per kDB x kDB block,
+// one wave per 16 x 16 quarter, K = kDB on the matrix cores:
+//   blocks [0, nA): A[k1:, k1:] -= P P^T (lower blocks), P = A[k1:, k0:k1];
+//   blocks [nA, ...): T_ij += L_ik M_kj for block rows i > k and columns
+//   j <= k, with M_kj formed from T_kj first; the blocks of row k + 1 also
+//   store M_kj into Md (T_kj is read by other blocks of this launch, so M
+//   lives apart from T).
+__global__ __launch_bounds__(kBlock) void k_chol_update(int np, int k0, int nA, double* __restrict__ A,
+                                                        double* __restrict__ Tb, double* __restrict__ Md) {
     const int k1 = k0 + kDB;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    if ((int)blockIdx.x >= nA) {
+        __shared__ double Ms[kDB][kDB + 1];
+        const int kb = k0 / kDB;
+        const int b = (int)blockIdx.x - nA;
+        const int ti = b / (kb + 1), jb = b % (kb + 1);
+        inverse_row_block(np, k0, jb, Tb, Md, Ms);
+        __syncthreads();
+        if (ti == 0 && jb < kb)
+            for (int x = threadIdx.x; x < kDB * kDB; x += kBlock)
+                Md[(size_t)(k0 + x / kDB) * np + kDB * jb + x % kDB] = Ms[x / kDB][x % kDB];
+        const int qi = wave >> 1, qj = wave & 1;
+        const int R0 = k1 + kDB * ti + 16 * qi, C0 = kDB * jb + 16 * qj;
+        d4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = Tb[(size_t)(R0 + lk + 4 * r) * np + C0 + li];
+        const double* Lik = A + (size_t)(R0 + li) * np + k0;
+#pragma unroll
+        for (int s = 0; s < kDB; s += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Lik[s + lk], Ms[s + lk][16 * qj + li], acc, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Tb[(size_t)(R0 + lk + 4 * r) * np + C0 + li] = acc[r];
+        return;
+    }
     int ti, tj;
     tri_index(blockIdx.x, ti, tj);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int R0 = k1 + kDB * ti + 16 * (wave >> 1);
     const int C0 = k1 + kDB * tj + 16 * (wave & 1);
     if (ti == tj && (wave >> 1) < (wave & 1)) return;   // strictly upper quarter of a diagonal block
-    const int li = lane & 15, lk = lane >> 4;
     const double* Pa = A + (size_t)(R0 + li) * np + k0;
     const double* Pb = A + (size_t)(C0 + li) * np + k0;
     d4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -143,98 +208,15 @@ __global__ __launch_bounds__(kBlock) void k_chol_update(int np, int k0, double* 
     for (int r = 0; r < 4; ++r) A[(size_t)(R0 + lk + 4 * r) * np + C0 + li] -= acc[r];
 }
 
-// Diagonal blocks of M: M_jj = L_jj^-1 (L_jj from Dbuf), one workgroup per
-// block; thread c forms column c by forward substitution.
-__global__ __launch_bounds__(kBlock) void k_trtri_diag(int np, const double* __restrict__ Dbuf, double* __restrict__ M) {
-    __shared__ double Ld[kDB][kDB + 1];
-    __shared__ double X[kDB][kDB + 1];
-    const int j0 = blockIdx.x * kDB;
-    const double* Db = Dbuf + (size_t)blockIdx.x * kDB * kDB;
-    for (int x = threadIdx.x; x < kDB * kDB; x += kBlock) Ld[x / kDB][x % kDB] = Db[x];
-    __syncthreads();
-    const int c = threadIdx.x;
-    if (c < kDB) {
-        for (int i = 0; i < kDB; ++i) {
-            if (i < c) {
-                X[i][c] = 0.0;
-                continue;
-            }
-            double v = i == c ? 1.0 : 0.0;
-            for (int k = c; k < i; ++k) v -= Ld[i][k] * X[k][c];
-            X[i][c] = v / Ld[i][i];
-        }
-    }
+// The last block row of M (no update follows the last step): M_kj for j < k.
+__global__ __launch_bounds__(kBlock) void k_inverse_last_row(int np, int k0, const double* __restrict__ Tb,
+                                                             double* __restrict__ Md) {
+    __shared__ double Ms[kDB][kDB + 1];
+    const int jb = blockIdx.x;
+    inverse_row_block(np, k0, jb, Tb, Md, Ms);
     __syncthreads();
     for (int x = threadIdx.x; x < kDB * kDB; x += kBlock)
-        M[(size_t)(j0 + x / kDB) * np + j0 + x % kDB] = X[x / kDB][x % kDB];
-}
-
-// Blocks of M at distance s below the diagonal, all in parallel:
-// M_ij = -M_ii (sum_{k=j}^{i-1} L_ik M_kj), i = j + s; the blocks M_kj with
-// k - j < s come from earlier launches.  16 waves per block: four per 16 x 16
-// quarter of the tile, each summing every fourth 16-wide slice of the K range
-// (four accumulator chains), the slices added in order through LDS.
-constexpr int kTriWaves = 16;
-
-__global__ __launch_bounds__(kTriWaves * 64) void k_trtri_off(int np, int s, const double* __restrict__ L,
-                                                              double* __restrict__ M) {
-    __shared__ double part[4][kDB][kDB + 1];
-    __shared__ double T[kDB][kDB + 1];
-    const int j = blockIdx.x, i = j + s;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int quarter = wave & 3, slice = wave >> 2;
-    const int qi = quarter >> 1, qj = quarter & 1;
-    const int li = lane & 15, lk = lane >> 4;
-    d4 acc[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
-    const double* La = L + (size_t)(kDB * i + 16 * qi + li) * np;
-    const double* Mb = M + kDB * j + 16 * qj + li;
-    // four 16-wide slices in flight per round (loads first, then their products)
-    const int kend = kDB * i;
-    int k = kDB * j + 16 * slice;
-    for (; k + 192 < kend; k += 256) {
-        double a[4][4], b[4][4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[c][q] = La[k + 64 * c + 4 * q + lk];
-                b[c][q] = Mb[(size_t)(k + 64 * c + 4 * q + lk) * np];
-            }
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][q], b[c][q], acc[q], 0, 0, 0);
-    }
-    for (; k < kend; k += 64) {
-        double a[4], b[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            a[q] = La[k + 4 * q + lk];
-            b[q] = Mb[(size_t)(k + 4 * q + lk) * np];
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc[q], 0, 0, 0);
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-        part[slice][16 * qi + lk + 4 * r][16 * qj + li] = (acc[0][r] + acc[1][r]) + (acc[2][r] + acc[3][r]);
-    __syncthreads();
-    for (int x = threadIdx.x; x < kDB * kDB; x += kTriWaves * 64) {
-        const int r = x / kDB, c = x % kDB;
-        T[r][c] = (part[0][r][c] + part[1][r][c]) + (part[2][r][c] + part[3][r][c]);
-    }
-    __syncthreads();
-    if (wave >= 4) return;
-    d4 out = {0.0, 0.0, 0.0, 0.0};
-    const double* Mi = M + (size_t)(kDB * i + 16 * qi + li) * np + kDB * i;
-#pragma unroll
-    for (int k = 0; k < kDB; k += 4)
-        out = __builtin_amdgcn_mfma_f64_16x16x4f64(Mi[k + lk], T[k + lk][16 * qj + li], out, 0, 0, 0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) M[(size_t)(kDB * i + 16 * qi + lk + 4 * r) * np + kDB * j + 16 * qj + li] = -out[r];
+        Md[(size_t)(k0 + x / kDB) * np + kDB * jb + x % kDB] = Ms[x / kDB][x % kDB];
 }
 
 // Packed rows of the first n rows (row i at i(i+1)/2), and the largest
@@ -299,7 +281,7 @@ int dense_padded(int n) { return (n + kDB - 1) / kDB * kDB; }
 
 int dense_pack_blocks() { return 256; }
 
-void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, double* Dbuf,
+void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, double* Tb,
                            int32_t* bad) {
     const int np = dense_padded(n);
     const int nbk = np / kDB;
@@ -310,14 +292,16 @@ void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, d
         const int k0 = kb * kDB;
         const int rows = np - k0 - kDB;
         const unsigned g = (unsigned)std::max(1, (rows + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(k_chol_step, dim3(g), dim3(kBlock), 0, s, np, k0, A, Dbuf, bad);
+        hipLaunchKernelGGL(k_chol_step, dim3(g), dim3(kBlock), 0, s, np, k0, A, Md, bad);
         const int nt = nbk - kb - 1;
-        if (nt > 0) hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(kBlock), 0, s, np, k0, A);
+        if (nt > 0) {
+            const int nA = nt * (nt + 1) / 2, nT = nt * (kb + 1);
+            hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(nA + nT)), dim3(kBlock), 0, s, np, k0, nA, A, Tb, Md);
+        }
     }
-    // blocks of Md above the diagonal are never read: no clearing needed
-    hipLaunchKernelGGL(k_trtri_diag, dim3((unsigned)nbk), dim3(kBlock), 0, s, np, Dbuf, Md);
-    for (int d = 1; d < nbk; ++d)
-        hipLaunchKernelGGL(k_trtri_off, dim3((unsigned)(nbk - d)), dim3(kTriWaves * 64), 0, s, np, d, A, Md);
+    if (nbk > 1)
+        hipLaunchKernelGGL(k_inverse_last_row, dim3((unsigned)(nbk - 1)), dim3(kBlock), 0, s, np, (nbk - 1) * kDB,
+                           Tb, Md);
 }
 
 void launch_pack_factor(hipStream_t s, int n, const double* Md, double* Mp, const double* old, double* red) {

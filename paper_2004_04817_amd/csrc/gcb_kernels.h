@@ -135,14 +135,14 @@ bool launch_support_weights(hipStream_t s, Support& sp, int n, const double* dis
                             double* Wbuf);
 void launch_mark_support(hipStream_t s, const Boundary& bd, const Support& sp, int n);
 
-// Dense FP64 refactorisation (matrix cores): A, Md hold dense_padded(n)^2
-// doubles each, Dbuf dense_padded(n) * 32; on return the strictly lower
-// blocks of A and the diagonal blocks in Dbuf hold L (Cholesky of Phi_S), Md
-// holds L^-1, and *bad = 1 (set, never cleared) if a pivot was not above
-// kSingularTol.
+// Dense FP64 refactorisation (matrix cores): A, Md, Tb hold dense_padded(n)^2
+// doubles each, Tb zero on entry; on return the strictly lower blocks of A hold L (Cholesky of
+// Phi_S) below the diagonal blocks, the lower triangle of Md holds L^-1 (its
+// blocks above the diagonal are not written), Tb is scratch, and *bad = 1
+// (set, never cleared) if a pivot was not above kSingularTol.
 int dense_padded(int n);
 int dense_pack_blocks();
-void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, double* Dbuf,
+void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, double* Tb,
                            int32_t* bad);
 // Packed rows of Md into Mp (may equal old); with old, red[2b], red[2b+1]
 // get per-block max |new - old| and max |old| (dense_pack_blocks() blocks).

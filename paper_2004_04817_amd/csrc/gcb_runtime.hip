@@ -1239,20 +1239,20 @@ void rebuild_factor(gcb_ctx* ctx, int n, bool compare, double* drift) {
     const int R = multi_padded_r(3);
     const size_t dense_b = sizeof(double) * (size_t)np * np;
     const size_t w_b = sizeof(double) * 3 * (size_t)n * R;
-    const size_t diag_b = sizeof(double) * (size_t)np * 32;
-    ensure_tmp(ctx, 2 * dense_b + diag_b + w_b + 1024);
+    ensure_tmp(ctx, 3 * dense_b + w_b + 1024);
     char* base = static_cast<char*>(ctx->tmp);
     double* A = reinterpret_cast<double*>(base);
     double* Md = reinterpret_cast<double*>(base + dense_b);
-    double* Dbuf = reinterpret_cast<double*>(base + 2 * dense_b);
-    double* Wb = reinterpret_cast<double*>(base + 2 * dense_b + diag_b);
-    int32_t* bad = reinterpret_cast<int32_t*>(base + 2 * dense_b + diag_b + w_b);
+    double* Tb = reinterpret_cast<double*>(base + 2 * dense_b);
+    double* Wb = reinterpret_cast<double*>(base + 3 * dense_b);
+    int32_t* bad = reinterpret_cast<int32_t*>(base + 3 * dense_b + w_b);
     const int nred = dense_pack_blocks();
     dalloc_cap(ctx, ctx->red, ctx->red_cap, (decltype(ctx->red_cap))(2 * nred + 2));
     ensure_red(ctx);
     HIPCHK(ctx, hipMemsetAsync(bad, 0, sizeof(int32_t), ctx->stream));
     HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    launch_inverse_factor(ctx->stream, sp, n, A, Md, Dbuf, bad);
+    HIPCHK(ctx, hipMemsetAsync(Tb, 0, dense_b, ctx->stream));   // the inverse's block sums start at zero
+    launch_inverse_factor(ctx->stream, sp, n, A, Md, Tb, bad);
     HIPCHK(ctx, hipGetLastError());
     int32_t hbad = 0;
     HIPCHK(ctx, hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, ctx->stream));
