@@ -153,10 +153,12 @@ bool launch_deform_multi(hipStream_t s, const Support& sp, int n, int rc, const 
                          int out_f64);
 void launch_transpose_factor(hipStream_t s, const double* Mr, double* Mc, int n, int64_t cap);
 // Monitor sample: out[0] = max e^2, out[1] = sum e^2 over all nodes with the current W,
-// written only if st->log_len >= need when the kernels run (red: 2 * ceil(nb / kBlock) doubles).
+// written only if st->log_len >= need when the kernels run (red: 2 * certify_blocks(nb) doubles).
 void launch_monitor(hipStream_t s, const Boundary& bd, const Support& sp, const GState* st, int64_t need,
                     double* red, double* out);
 void launch_certify(hipStream_t s, const Boundary& bd, const Support& sp, int n, double* red, double* out);
+// Blocks of the all-node sweeps (certificate, monitor): red needs 2 doubles per block.
+int64_t certify_blocks(int64_t nb);
 // FP32 evaluation of Eq. (6) (FP32 copies of the supports and weights are
 // refreshed first; sp.fsx..fwz must hold sp.cap floats).
 void launch_volume32(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,

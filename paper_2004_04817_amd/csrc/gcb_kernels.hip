@@ -978,28 +978,55 @@ __global__ __launch_bounds__(kBlock) void k_init_final(int mode, int nrec, const
 
 // ---------------------------------------------------------------- certificate (a6)
 // e_j^2 over all boundary nodes; per block: max and sum.
+// All-node error sweep (a6): kCertTargets targets per block, the supports
+// split into four contiguous quarters over the block's four waves (four times
+// the waves of one target per thread, for occupancy), the quarter sums added
+// in a fixed order; one (max e^2, sum e^2) pair per block into red.
+constexpr int kCertTargets = kBlock / 4;
+
+int64_t certify_blocks(int64_t nb) { return (nb + kCertTargets - 1) / kCertTargets; }
+
+__device__ __forceinline__ void all_node_block(int64_t nb, const double* __restrict__ px,
+                                               const double* __restrict__ py, const double* __restrict__ pz,
+                                               const double* __restrict__ pdx, const double* __restrict__ pdy,
+                                               const double* __restrict__ pdz, const SupportView& sv, int n,
+                                               double* __restrict__ red) {
+    __shared__ double part[3][4][kCertTargets];
+    const int q = threadIdx.x / kCertTargets, tl = threadIdx.x % kCertTargets;
+    const int64_t t = blockIdx.x * (int64_t)kCertTargets + tl;
+    const bool live = t < nb;
+    const int64_t tt = live ? t : nb - 1;
+    const int s0 = (int)((int64_t)n * q / 4), s1 = (int)((int64_t)n * (q + 1) / 4);
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    accumulate64(px[tt], py[tt], pz[tt], s0, s1, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
+    part[0][q][tl] = ax;
+    part[1][q][tl] = ay;
+    part[2][q][tl] = az;
+    __syncthreads();
+    const bool mine = q == 0 && live;
+    double e2 = 0.0;
+    if (mine) {
+        const double fx = (part[0][0][tl] + part[0][1][tl]) + (part[0][2][tl] + part[0][3][tl]);
+        const double fy = (part[1][0][tl] + part[1][1][tl]) + (part[1][2][tl] + part[1][3][tl]);
+        const double fz = (part[2][0][tl] + part[2][1][tl]) + (part[2][2][tl] + part[2][3][tl]);
+        const double ex = fx - pdx[t], ey = fy - pdy[t], ez = fz - pdz[t];
+        e2 = fma(ez, ez, fma(ey, ey, ex * ex));
+    }
+    Best b{mine ? e2 : -1.0, (int32_t)t, 0};
+    b = block_best(b);
+    const double sum = block_sum<kBlock>(e2);
+    if (threadIdx.x == 0) {
+        red[2 * blockIdx.x] = b.v;
+        red[2 * blockIdx.x + 1] = sum;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_certify(int64_t nb, const double* __restrict__ px,
                                                     const double* __restrict__ py, const double* __restrict__ pz,
                                                     const double* __restrict__ pdx, const double* __restrict__ pdy,
                                                     const double* __restrict__ pdz, SupportView sv, int n,
                                                     double* __restrict__ red) {
-    const int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    const bool live = t < nb;
-    const int64_t tt = live ? t : nb - 1;
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    accumulate64(px[tt], py[tt], pz[tt], 0, n, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
-    double e2 = 0.0;
-    if (live) {
-        const double ex = ax - pdx[t], ey = ay - pdy[t], ez = az - pdz[t];
-        e2 = fma(ez, ez, fma(ey, ey, ex * ex));
-    }
-    Best b{live ? e2 : -1.0, (int32_t)t, 0};
-    b = block_best(b);
-    const double s = block_sum<kBlock>(e2);
-    if (threadIdx.x == 0) {
-        red[2 * blockIdx.x] = b.v;
-        red[2 * blockIdx.x + 1] = s;
-    }
+    all_node_block(nb, px, py, pz, pdx, pdy, pdz, sv, n, red);
 }
 
 __global__ __launch_bounds__(kBlock) void k_certify_final(int nblk, const double* __restrict__ red,
@@ -1038,23 +1065,7 @@ __global__ __launch_bounds__(kBlock) void k_monitor(int64_t nb, const double* __
                                                     double* __restrict__ red) {
     const GState s = *st;
     if (s.log_len < need) return;
-    const int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    const bool live = t < nb;
-    const int64_t tt = live ? t : nb - 1;
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    accumulate64(px[tt], py[tt], pz[tt], 0, s.n, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
-    double e2 = 0.0;
-    if (live) {
-        const double ex = ax - pdx[t], ey = ay - pdy[t], ez = az - pdz[t];
-        e2 = fma(ez, ez, fma(ey, ey, ex * ex));
-    }
-    Best b{live ? e2 : -1.0, (int32_t)t, 0};
-    b = block_best(b);
-    const double sum = block_sum<kBlock>(e2);
-    if (threadIdx.x == 0) {
-        red[2 * blockIdx.x] = b.v;
-        red[2 * blockIdx.x + 1] = sum;
-    }
+    all_node_block(nb, px, py, pz, pdx, pdy, pdz, sv, s.n, red);
 }
 
 __global__ __launch_bounds__(kBlock) void k_monitor_final(int nblk, const double* __restrict__ red,
@@ -1402,14 +1413,14 @@ void launch_transpose_factor(hipStream_t s, const double* Mr, double* Mc, int n,
 
 void launch_monitor(hipStream_t s, const Boundary& bd, const Support& sp, const GState* st, int64_t need,
                     double* red, double* out) {
-    const unsigned g = (unsigned)((bd.nb + kBlock - 1) / kBlock);
+    const unsigned g = (unsigned)certify_blocks(bd.nb);
     GCB_LAUNCH(k_monitor, dim3(g), dim3(kBlock), s, bd.nb, bd.px, bd.py, bd.pz, bd.pdx, bd.pdy, bd.pdz, view(sp), st,
                need, red);
     GCB_LAUNCH(k_monitor_final, dim3(1), dim3(kBlock), s, (int)g, red, st, need, out);
 }
 
 void launch_certify(hipStream_t s, const Boundary& bd, const Support& sp, int n, double* red, double* out) {
-    const unsigned g = (unsigned)((bd.nb + kBlock - 1) / kBlock);
+    const unsigned g = (unsigned)certify_blocks(bd.nb);
     GCB_LAUNCH(k_certify, dim3(g), dim3(kBlock), s, bd.nb, bd.px, bd.py, bd.pz, bd.pdx, bd.pdy, bd.pdz, view(sp), n, red);
     GCB_LAUNCH(k_certify_final, dim3(1), dim3(kBlock), s, (int)g, red, out);
 }

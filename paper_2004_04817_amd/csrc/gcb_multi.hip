@@ -19,38 +19,61 @@ __global__ __launch_bounds__(kBlock) void k_gather_modes(int n, int rc, int R, c
     D[x] = c < rc ? modes[(int64_t)orig[s] * rc + c] : 0.0;
 }
 
-// Y[i][c] = sum_{j <= i} M[i][j] D[j][c]; lanes are columns, the row of M is wave-uniform.
+// One workgroup per row of the result; thread t handles column c = t % R of
+// the R right-hand sides and every J-th term of the row (J = kBlock / R, at
+// least 1), and the J partial sums are added in a fixed order.  With few
+// right-hand sides (the 3 displacement components of the weights) every
+// thread still has work.
+// Y[i][c] = sum_{j <= i} M[i][j] D[j][c], M by packed rows.
 __global__ __launch_bounds__(kBlock) void k_trmm_lower(int n, int R, const double* __restrict__ M,
                                                        const double* __restrict__ D, double* __restrict__ Y) {
-    const int c = blockIdx.x * kBlock + threadIdx.x;
-    const int i = blockIdx.y;
-    if (c >= R) return;
+    __shared__ double part[kBlock];
+    const int i = blockIdx.x;
+    const int J = max(1, kBlock / R);
+    const int t = threadIdx.x, c = t % R, jl = t / R;
     const double* Mi = M + (size_t)i * (i + 1) / 2;
     double a0 = 0.0, a1 = 0.0;
-    int j = 0;
-    for (; j + 1 <= i; j += 2) {
-        a0 = fma(Mi[j], D[(size_t)j * R + c], a0);
-        a1 = fma(Mi[j + 1], D[(size_t)(j + 1) * R + c], a1);
+    if (jl < J) {
+        int j = jl;
+        for (; j + J <= i; j += 2 * J) {
+            a0 = fma(Mi[j], D[(size_t)j * R + c], a0);
+            a1 = fma(Mi[j + J], D[(size_t)(j + J) * R + c], a1);
+        }
+        if (j <= i) a0 = fma(Mi[j], D[(size_t)j * R + c], a0);
     }
-    if (j <= i) a0 = fma(Mi[j], D[(size_t)j * R + c], a0);
-    Y[(size_t)i * R + c] = a0 + a1;
+    part[t] = a0 + a1;
+    __syncthreads();
+    if (t < R) {
+        double sum = 0.0;
+        for (int q = 0; q < J; ++q) sum += part[q * R + t];
+        Y[(size_t)i * R + t] = sum;
+    }
 }
 
 // W[j][c] = sum_{i >= j} M[i][j] Y[i][c], M read by columns from Mc.
 __global__ __launch_bounds__(kBlock) void k_trmm_upper(int n, int R, const double* __restrict__ Mc, int64_t cap,
                                                        const double* __restrict__ Y, double* __restrict__ W) {
-    const int c = blockIdx.x * kBlock + threadIdx.x;
-    const int j = blockIdx.y;
-    if (c >= R) return;
+    __shared__ double part[kBlock];
+    const int j = blockIdx.x;
+    const int J = max(1, kBlock / R);
+    const int t = threadIdx.x, c = t % R, il = t / R;
     const double* col = Mc + (size_t)j * cap - (size_t)j * (j - 1) / 2;
     double a0 = 0.0, a1 = 0.0;
-    int i = j;
-    for (; i + 1 < n; i += 2) {
-        a0 = fma(col[i - j], Y[(size_t)i * R + c], a0);
-        a1 = fma(col[i + 1 - j], Y[(size_t)(i + 1) * R + c], a1);
+    if (il < J) {
+        int i = j + il;
+        for (; i + J < n; i += 2 * J) {
+            a0 = fma(col[i - j], Y[(size_t)i * R + c], a0);
+            a1 = fma(col[i + J - j], Y[(size_t)(i + J) * R + c], a1);
+        }
+        if (i < n) a0 = fma(col[i - j], Y[(size_t)i * R + c], a0);
     }
-    if (i < n) a0 = fma(col[i - j], Y[(size_t)i * R + c], a0);
-    W[(size_t)j * R + c] = a0 + a1;
+    part[t] = a0 + a1;
+    __syncthreads();
+    if (t < R) {
+        double sum = 0.0;
+        for (int q = 0; q < J; ++q) sum += part[q * R + t];
+        W[(size_t)j * R + t] = sum;
+    }
 }
 
 // Volume sweep with R right-hand sides (R a multiple of 16, at most kMaxR).
@@ -142,9 +165,8 @@ bool launch_deform_multi(hipStream_t s, const Support& sp, int n, int rc, const 
     const int64_t cnt = (int64_t)n * R;
     hipLaunchKernelGGL(k_gather_modes, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, rc, R,
                        sp.orig, modes_dev, Dbuf);
-    const dim3 g((unsigned)((R + kBlock - 1) / kBlock), (unsigned)n);
-    hipLaunchKernelGGL(k_trmm_lower, g, dim3(kBlock), 0, s, n, R, sp.M, Dbuf, Ybuf);
-    hipLaunchKernelGGL(k_trmm_upper, g, dim3(kBlock), 0, s, n, R, sp.Mc, sp.cap, Ybuf, Wbuf);
+    hipLaunchKernelGGL(k_trmm_lower, dim3((unsigned)n), dim3(kBlock), 0, s, n, R, sp.M, Dbuf, Ybuf);
+    hipLaunchKernelGGL(k_trmm_upper, dim3((unsigned)n), dim3(kBlock), 0, s, n, R, sp.Mc, sp.cap, Ybuf, Wbuf);
     if (nv <= 0) return true;
     const unsigned gv = (unsigned)((nv + kMWaves * 16 - 1) / (kMWaves * 16));
     if (in_f64 && out_f64)

@@ -282,7 +282,7 @@ IterCtx make_ic(gcb_ctx* ctx) {
 }
 
 void ensure_red(gcb_ctx* ctx) {
-    const int64_t need = 2 * (ctx->bd.nb / kBlock + 2) + 2;
+    const int64_t need = 2 * (certify_blocks(ctx->bd.nb) + 2) + 2;
     dalloc_cap(ctx, ctx->red, ctx->red_cap, (decltype(ctx->red_cap))need);
 }
 
@@ -1393,6 +1393,7 @@ int gcb_certify(gcb_ctx* ctx, double* max_err, double* rms_err) {
     return guard(ctx, [&] {
         if (!ctx->selected) fail(ctx, GCB_E_STATE, "no finished selection");
         HIPCHK(ctx, hipSetDevice(ctx->device));
+        ensure_red(ctx);
         launch_certify(ctx->stream, ctx->bd, ctx->sp, (int)ctx->info.nc, ctx->red, ctx->red + ctx->red_cap - 2);
         HIPCHK(ctx, hipGetLastError());
         double mr[2];
