@@ -104,6 +104,18 @@ def measured_valu(kernel_src: str) -> dict | None:
             "valu_busy_pct": float(vals["valu_busy_pct"]), "greedy_valu_busy_pct": greedy}
 
 
+def kl_divergence(xyz: np.ndarray, s1, s2) -> float:
+    """KL(S1 || S2) between two support sets of the same boundary (Section 4.1, the KL
+    equation): sum over boundary nodes i of d1_i log(d1_i / d2_i), with dk_i the distance
+    from node i to the nearest node of Sk.  A node of either set has a zero distance, which
+    makes its term 0 log 0 or x log(x / 0); such terms are left out of the sum."""
+    from scipy.spatial import cKDTree
+    d1, _ = cKDTree(xyz[np.asarray(s1)]).query(xyz)
+    d2, _ = cKDTree(xyz[np.asarray(s2)]).query(xyz)
+    ok = (d1 > 0.0) & (d2 > 0.0)
+    return float(np.sum(d1[ok] * np.log(d1[ok] / d2[ok])))
+
+
 def problem(name):
     import synth
     if name == "small":
@@ -415,16 +427,25 @@ def main():
             r["speedup_vs_m1"] = base / r["select_ms"] if base else None
         # fixed Nc (Tables 2 and 5 protocol): E* = 0, every m selects exactly Nc^max supports
         nc_fixed = 1100
-        fixed = []
+        fixed, sets = [], {}
         for m in [int(x) for x in a.m_sweep.split(",")]:
             ctx.set_params(p.radius, m, 0.0, nc_max=nc_fixed, seed=p.seed)
             ctx.select()
             inf = ctx.select()
+            sets[m] = ctx.get_support()[0]
             fixed.append({"m": m, "nc": inf["nc"], "iterations": inf["iterations"], "select_ms": inf["ms_select"],
                           "final_max_err_rel": inf["final_max_err"] / p.max_disp})
         fbase = next((r["select_ms"] for r in fixed if r["m"] == 1), None)
         for r in fixed:
             r["speedup_vs_m1"] = fbase / r["select_ms"] if fbase else None
+        # distribution of the support nodes against the traditional greedy's (Table 4 analog): KL(m = 1 || m),
+        # and two seeded random sets of the same size
+        kl = None
+        if 1 in sets:
+            kl = {f"m{m}": kl_divergence(p.xyz, sets[1], S) for m, S in sets.items() if m != 1}
+            for r_id in (1, 2):
+                rnd = np.random.default_rng(1000 + r_id).choice(p.nb, size=nc_fixed, replace=False)
+                kl[f"random{r_id}"] = kl_divergence(p.xyz, sets[1], rnd)
         # error history of the benchmark selection (all-node max and RMS every m iterations; Figs. 4-7 analog)
         ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed, monitor_every=p.m)
         ctx.select()
@@ -434,7 +455,8 @@ def main():
         pick = np.unique(np.linspace(0, len(it_h) - 1, 8).astype(int)) if len(it_h) else []
         history = [{"iteration": int(it_h[i]), "nc": int(nc_at[it_h[i] - 1]), "max_err_rel": float(mx_h[i] / p.max_disp),
                     "rms_err_rel": float(rm_h[i] / p.max_disp)} for i in pick]
-        rec["m_sweep"] = {"free_nc": rows, "fixed_nc": {"nc": nc_fixed, "rows": fixed}, "history_m107": history}
+        rec["m_sweep"] = {"free_nc": rows, "fixed_nc": {"nc": nc_fixed, "rows": fixed, "kl_vs_m1": kl},
+                          "history_m107": history}
         ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
         ctx.select()
     if a.surfaces > 0:
