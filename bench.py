@@ -143,14 +143,16 @@ def cpu_baseline(p, nv_sample):
             "seconds": t2 - t0}, r, ref
 
 
-def multi_surface(count, dev):
+def multi_surface(count, dev, vs_oracle=False):
     """Uneven independent surfaces (Nb log-uniform in [1e3, 5e4], Nv = 25 Nb), each selected and
-    deformed: one context at a time vs one batch (shared launches)."""
+    deformed: one context at a time vs one batch (shared launches); with vs_oracle, the batch's
+    support sets, certificates and sampled displacements against the FP64 oracle."""
     import torch
     import synth
     import paper_2004_04817_amd as gcb
     probs = synth.config_multi_surface(count, with_volume=True)
     vols = [torch.from_numpy(q.volume).to(dev) for q in probs]
+    samples = [q.volume[:: max(1, q.volume.shape[0] // 2000)] for q in probs] if vs_oracle else None
     for q in probs:
         q.volume = None
     ctxs = []
@@ -193,6 +195,20 @@ def multi_surface(count, dev):
                      "iterations_sum": sum(i["iterations"] for i in infos),
                      "all_converged": all(bool(i["converged"]) for i in infos)}
     res["speedup"] = res["one_at_a_time"]["ms"] / res["batched"]["ms"]
+    if vs_oracle:
+        import oracle
+        same, cert, verr = 0, 0.0, 0.0
+        for q, c, o, smp in zip(probs, ctxs, outs, samples):
+            r = oracle.select(q.xyz, q.disp, q.radius, q.m, q.tol_abs, seed=q.seed, nthreads=16)
+            S, _ = c.get_support()
+            same += int(list(S) == list(r.S))
+            cert = max(cert, abs(c.certify()[0] - r.final_max_err) / max(r.final_max_err, 1e-300))
+            step = max(1, o.shape[0] // 2000)
+            ref = oracle.interpolate(q.xyz[r.S], r.W, q.radius, smp, nthreads=16)
+            verr = max(verr, float(np.abs(o[::step].cpu().numpy() - ref).max()) / q.max_disp)
+        res["vs_oracle"] = {"same_support_sets": same, "surfaces": count,
+                            "certificate_rel_diff_max": cert, "volume_max_err_rel_max_d": verr,
+                            "volume_points_compared_per_surface": "about 2,000 (every k-th point)"}
     res["autotune"] = {"chosen": {"sweep_targets_per_lane": best[0], "factor_chunks_per_wave": best[1]},
                        "select_ms": {f"tpl{c[0]}_rpw{c[1]}": 1e3 * t for c, t in times.items()},
                        "note": "0 = automatic (narrow layouts below 4 running surfaces, wide above)"}
@@ -406,7 +422,20 @@ def main():
         ms = float(np.mean(ts))
         rhs = 3 * a.modes
         flops = (2.0 * rhs + 15.0) * nv * nc   # matrix-core FMAs + the phi evaluation per pair
-        rec["modes"] = {"k_modes": a.modes, "rhs": rhs, "nv": nv, "nc": nc, "ms": ms,
+        mvs = None
+        if not a.no_cpu_baseline:
+            # sampled points of the 192-column output against the oracle's solve on the same support set
+            import oracle
+            S_m, _ = ctx.get_support()
+            mh = modes.cpu().numpy()
+            Wo = oracle.solve_on_support(p.xyz, S_m, p.radius, mh)
+            step = max(1, nv // 20000)
+            ref = oracle.interpolate(p.xyz[S_m], Wo, p.radius, p.volume[::step], nthreads=16)
+            got = mout[::step].cpu().numpy()
+            scale = float(np.abs(mh).max())
+            mvs = {"points_compared": int(ref.shape[0]), "max_err_rel_max_mode": float(np.abs(got - ref).max()) / scale,
+                   "rms_err_rel_max_mode": float(np.sqrt(np.mean((got - ref) ** 2))) / scale}
+        rec["modes"] = {"k_modes": a.modes, "rhs": rhs, "nv": nv, "nc": nc, "ms": ms, "vs_oracle": mvs,
                         "pair_evals_per_s": nv * nc / (ms * 1e-3),
                         "roofline": {"kernel": "k_volume_multi<double,double> (+ weight TRMMs)", "bound": "mfma",
                                      "achieved": flops / (ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
@@ -460,7 +489,7 @@ def main():
         ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
         ctx.select()
     if a.surfaces > 0:
-        rec["multi_surface"] = multi_surface(a.surfaces, dev)
+        rec["multi_surface"] = multi_surface(a.surfaces, dev, vs_oracle=not a.no_cpu_baseline)
     if a.requests > 0:
         rec["serving"] = serving_section(a.requests, dev, sat_rate=a.saturation_rate)
         rec["latency_ms"] = {"p50": rec["serving"]["served"]["p50_ms"], "p99": rec["serving"]["served"]["p99_ms"],
