@@ -556,7 +556,7 @@ size_t ctx_device_bytes(const gcb_ctx* ctx) {
     if (sp.fsx) b += 6 * sizeof(float) * (size_t)sp.cap;   // FP32 evaluation copies
     if (sp.qx) b += 4 * sizeof(double) * (size_t)sp.cap;   // volume table
     b += sizeof(double) * (size_t)ctx->Pb_cap + sizeof(ArgRec) * (size_t)ctx->argrec_cap;
-    b += (size_t)ctx->log_cap * (2 * sizeof(int32_t) + sizeof(double) + 1);
+    b += (size_t)ctx->log_cap * (2 * sizeof(int32_t) + 3 * sizeof(double) + 1);   // log and monitor samples
     b += sizeof(double) * (size_t)ctx->red_cap + ctx->tmp_cap + sizeof(GState) + sizeof(IterRec);
     return b;
 }
@@ -924,7 +924,7 @@ void gcb_destroy(gcb_ctx* ctx) {
     free_boundary(ctx->bd);
     free_support(ctx->sp);
     dfree(ctx->state); dfree(ctx->argrec); dfree(ctx->red); dfree(ctx->irec); dfree(ctx->Pb);
-    dfree(ctx->log_group); dfree(ctx->log_node); dfree(ctx->log_err); dfree(ctx->log_app);
+    dfree(ctx->log_group); dfree(ctx->log_node); dfree(ctx->log_err); dfree(ctx->log_app); dfree(ctx->mon);
     if (ctx->tmp) (void)hipFree(ctx->tmp);
     if (ctx->chunk_exec) (void)hipGraphExecDestroy(ctx->chunk_exec);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);

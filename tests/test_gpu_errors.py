@@ -87,3 +87,33 @@ def test_run_to_run_bitwise_determinism():
     assert np.array_equal(a[4].err, b[4].err)
     a[0].close()
     b[0].close()
+
+
+def test_contexts_return_their_device_memory():
+    """Creating, using (selection, FP64 and FP32 deformation, refactorisation) and destroying
+    contexts leaves the device's free memory where it was: nothing a context allocates outlives it."""
+    import torch
+    p = synth.config_small_ellipsoid(nv=20000)
+    vol = torch.from_numpy(p.volume).cuda()
+    torch.cuda.synchronize()
+
+    def cycle():
+        c = gcb.Context(0)
+        c.set_boundary(p.xyz, p.disp)
+        c.set_params(p.radius, p.m, p.tol_abs, seed=p.seed, monitor_every=p.m)
+        c.select()
+        c.deform(vol)
+        c.set_params(p.radius, p.m, p.tol_abs, seed=p.seed, precision=gcb.GCB_PREC_FP32_EVAL)
+        c.select()
+        c.deform(vol)
+        c.refactor()
+        torch.cuda.synchronize()
+        c.close()
+
+    cycle()   # first use: runtime and module set-up
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(12):
+        cycle()
+    free1 = torch.cuda.mem_get_info()[0]
+    print("free device bytes before / after 12 context cycles:", free0, free1)
+    assert free0 - free1 < (4 << 20)
