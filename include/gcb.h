@@ -334,6 +334,12 @@ int gcb_server_progress(gcb_server *s, int32_t iterations, int32_t *in_flight);
 /* The state and timings of a ticket. */
 int gcb_server_result(const gcb_server *s, int64_t ticket, gcb_result *res);
 
+/* Drop the record of a finished (state 3) or failed ticket, so that a server
+ * that runs for long keeps a bounded amount of host memory; the ticket is
+ * unknown afterwards (GCB_E_INVALID).  GCB_E_STATE while it is still queued
+ * or running. */
+int gcb_server_forget(gcb_server *s, int64_t ticket);
+
 /* Device bytes held by resident and running meshes, and the resident count. */
 int gcb_server_memory(const gcb_server *s, uint64_t *bytes, int32_t *resident);
 

@@ -34,7 +34,8 @@ EXPORTS = ["gcb_version", "gcb_partition", "gcb_create", "gcb_destroy", "gcb_las
            "gcb_batch_create", "gcb_batch_destroy", "gcb_batch_last_error", "gcb_batch_begin", "gcb_batch_step",
            "gcb_batch_end", "gcb_select_batch", "gcb_deform_batch", "gcb_batch_set_layout",
            "gcb_server_clock", "gcb_server_create", "gcb_server_destroy", "gcb_server_last_error",
-           "gcb_server_submit", "gcb_server_progress", "gcb_server_result", "gcb_server_memory"]
+           "gcb_server_submit", "gcb_server_progress", "gcb_server_result", "gcb_server_forget",
+           "gcb_server_memory"]
 
 
 class GcbError(RuntimeError):
@@ -134,6 +135,7 @@ def lib():
         L.gcb_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(i64)]
         L.gcb_server_progress.argtypes = [vp, i32, C.POINTER(i32)]
         L.gcb_server_result.argtypes = [vp, i64, C.POINTER(Result)]
+        L.gcb_server_forget.argtypes = [vp, i64]
         L.gcb_server_memory.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(i32)]
         for name in EXPORTS:
             getattr(L, name)
@@ -615,6 +617,10 @@ class Server:
         if r.state == 3 or r.state < 0:
             self._keep.pop(int(ticket), None)
         return d
+
+    def forget(self, ticket: int):
+        """Drop the server's record of a finished or failed ticket."""
+        self._check(lib().gcb_server_forget(self._h, int(ticket)))
 
     def memory(self):
         b, n = C.c_uint64(), C.c_int32()

@@ -441,6 +441,16 @@ int gcb_server_result(const gcb_server* s, int64_t ticket, gcb_result* res) {
     return GCB_OK;
 }
 
+int gcb_server_forget(gcb_server* s, int64_t ticket) {
+    if (!s) return GCB_E_INVALID;
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return GCB_E_INVALID;
+    const int32_t st = it->second.res.state;
+    if (st != kDone && st >= 0) return GCB_E_STATE;
+    s->reqs.erase(it);   // a finished or failed request holds no context and no event any more
+    return GCB_OK;
+}
+
 int gcb_server_memory(const gcb_server* s, uint64_t* bytes, int32_t* resident) {
     if (!s) return GCB_E_INVALID;
     if (bytes) *bytes = used_bytes(s);

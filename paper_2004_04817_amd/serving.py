@@ -104,6 +104,7 @@ def replay(server: Server, items, pool, nv_per_nb: int = 25, iterations: int = 1
     torch.cuda.synchronize()
     for s in served:
         s.result = server.result(s.ticket)
+        server.forget(s.ticket)   # the server keeps no record of finished requests
     return served
 
 

@@ -130,3 +130,28 @@ def test_mixed_dtypes_in_one_round():
             md = float(np.sqrt((disp ** 2).sum(axis=1)).max())
             assert (out.double() - ref.double()).abs().max().item() <= TOL_SAME * md
             c.close()
+
+
+def test_forget_finished_tickets_only():
+    """A queued ticket cannot be forgotten; a finished one can, and is unknown afterwards."""
+    items = small_stream(3, 0.0)
+    pool64 = serving.volume_pool(20_000, "cuda")
+    with gcb.Server(0, hbm_budget=4 << 30, max_active=1) as srv:
+        tickets = []
+        for req, base, disp, tol in items:
+            vol = pool64[req.key % 2][: 4 * base.nb].contiguous()
+            out = torch.empty_like(vol)
+            tickets.append((srv.submit(base.xyz, disp, base.radius, base.m, tol, seed=base.seed, vol=vol, out=out),
+                            vol, out))
+        with pytest.raises(gcb.GcbError) as e:
+            srv.forget(tickets[-1][0])            # still queued
+        assert e.value.code == gcb.GCB_E_STATE
+        while srv.progress(16):
+            pass
+        torch.cuda.synchronize()
+        for tk, _, _ in tickets:
+            assert srv.result(tk)["state"] == 3
+            srv.forget(tk)
+            with pytest.raises(gcb.GcbError) as e:
+                srv.result(tk)
+            assert e.value.code == gcb.GCB_E_INVALID
