@@ -46,7 +46,7 @@ struct Resident {
 uint64_t estimate_bytes(const gcb_request& r) {
     const uint64_t nb = (uint64_t)r.nb;
     const uint64_t c = (uint64_t)std::min<int64_t>(r.params.nc_max, 1024);
-    return nb * 105 + c * (c + 1) * 8 + c * 96 + 65536ull * 17 + (1u << 20);
+    return nb * 105 + c * (c + 1) * 8 + c * 96 + 65536ull * 33 + (1u << 20);   // log: 65,536 entries
 }
 
 }  // namespace
