@@ -339,19 +339,41 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
         __syncthreads();
     }
     double ax[4] = {0, 0, 0, 0}, ay[4] = {0, 0, 0, 0}, az[4] = {0, 0, 0, 0};
+    // windows after the first: each thread's share of window w + 1 is loaded into registers
+    // while window w is evaluated, and stored to LDS between the two barriers
+    constexpr int kPer = (STAGE + kBlock - 1) / kBlock;
+    double nx[kPer], ny[kPer], nz[kPer], nwx[kPer], nwy[kPer], nwz[kPer];
     for (int w0 = 0; w0 < n; w0 += STAGE) {
         const int w1 = min(n, w0 + STAGE);
         if (w0 > 0) {
             __syncthreads();
-            for (int j = w0 + threadIdx.x; j < w1; j += kBlock) {
-                ls[0][j - w0] = sv.sx[j];
-                ls[1][j - w0] = sv.sy[j];
-                ls[2][j - w0] = sv.sz[j];
-                ls[3][j - w0] = sv.wx[j];
-                ls[4][j - w0] = sv.wy[j];
-                ls[5][j - w0] = sv.wz[j];
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int jj = threadIdx.x + kBlock * u;
+                if (jj < STAGE && w0 + jj < w1) {
+                    ls[0][jj] = nx[u];
+                    ls[1][jj] = ny[u];
+                    ls[2][jj] = nz[u];
+                    ls[3][jj] = nwx[u];
+                    ls[4][jj] = nwy[u];
+                    ls[5][jj] = nwz[u];
+                }
             }
             __syncthreads();
+        }
+        if (w1 < n) {
+            const int w2 = min(n, w1 + STAGE);
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int jj = threadIdx.x + kBlock * u;
+                const int j = min(w1 + jj, w2 - 1);
+                nx[u] = sv.sx[j];
+                ny[u] = sv.sy[j];
+                nz[u] = sv.sz[j];
+                nwx[u] = sv.wx[j];
+                nwy[u] = sv.wy[j];
+                nwz[u] = sv.wz[j];
+            }
         }
         // four supports per step: independent dependency chains keep a lone wave busy
         int j = w0 + gl;
