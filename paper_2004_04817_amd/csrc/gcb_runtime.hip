@@ -1141,19 +1141,14 @@ int gcb_deform(gcb_ctx* ctx, int64_t nv, const void* xyz, int in_dtype, void* ou
         HIPCHK(ctx, hipSetDevice(ctx->device));
         const size_t in_b = (size_t)nv * 3 * (in_dtype == GCB_F64 ? 8 : 4);
         const size_t out_b = (size_t)nv * 3 * (out_dtype == GCB_F64 ? 8 : 4);
+        const size_t in_pad = align_up(in_b);   // the output starts aligned whatever nv and the input type
         const void* din = xyz;
         void* dout = out;
         if (mem == GCB_MEM_HOST) {
-            if (ctx->tmp_cap < in_b + out_b) {
-                if (ctx->tmp) (void)hipFree(ctx->tmp);
-                ctx->tmp = nullptr;
-                ctx->tmp_cap = 0;
-                HIPCHK(ctx, hipMalloc(&ctx->tmp, in_b + out_b));
-                ctx->tmp_cap = in_b + out_b;
-            }
+            ensure_tmp(ctx, in_pad + out_b);
             HIPCHK(ctx, hipMemcpyAsync(ctx->tmp, xyz, in_b, hipMemcpyHostToDevice, ctx->stream));
             din = ctx->tmp;
-            dout = static_cast<char*>(ctx->tmp) + in_b;
+            dout = static_cast<char*>(ctx->tmp) + in_pad;
         }
         if (ctx->params.precision == GCB_PREC_FP32_EVAL) {
             Support& sp = ctx->sp;
@@ -1193,14 +1188,9 @@ int gcb_deform_multi(gcb_ctx* ctx, int32_t k_modes, const double* disp_modes, in
         const size_t in_b = (size_t)nv * 3 * (in_dtype == GCB_F64 ? 8 : 4);
         const size_t out_b = (size_t)nv * rc * (out_dtype == GCB_F64 ? 8 : 4);
         const size_t work_b = sizeof(double) * 3 * (size_t)n * R;
-        const size_t need = work_b + modes_b + (mem == GCB_MEM_HOST ? in_b + out_b : 0) + 1024;
-        if (ctx->tmp_cap < need) {
-            if (ctx->tmp) (void)hipFree(ctx->tmp);
-            ctx->tmp = nullptr;
-            ctx->tmp_cap = 0;
-            HIPCHK(ctx, hipMalloc(&ctx->tmp, need));
-            ctx->tmp_cap = need;
-        }
+        const size_t in_pad = align_up(in_b);   // the output starts aligned whatever nv and the input type
+        const size_t need = work_b + modes_b + (mem == GCB_MEM_HOST ? in_pad + out_b : 0) + 1024;
+        ensure_tmp(ctx, need);
         char* base = static_cast<char*>(ctx->tmp);
         double* D = reinterpret_cast<double*>(base);
         double* Y = D + (size_t)n * R;
@@ -1217,7 +1207,7 @@ int gcb_deform_multi(gcb_ctx* ctx, int32_t k_modes, const double* disp_modes, in
         if (mem == GCB_MEM_HOST && nv > 0) {
             HIPCHK(ctx, hipMemcpyAsync(p, xyz, in_b, hipMemcpyHostToDevice, ctx->stream));
             din = p;
-            dout = p + in_b;
+            dout = p + in_pad;
         }
         if (!launch_deform_multi(ctx->stream, ctx->sp, n, rc, modes_d, D, Y, Wm, nv, din, in_dtype == GCB_F64,
                                  ctx->bd.inv_r, dout, out_dtype == GCB_F64))

@@ -57,6 +57,9 @@ def test_device_tensors_and_dtypes():
     # host numpy path equals the device path bit for bit
     oh = ctx.deform(p.volume)
     assert np.array_equal(oh, o64.cpu().numpy())
+    # host path with FP32 input and FP64 output at an odd point count (output buffer after the input)
+    oh32 = ctx.deform(x32.cpu().numpy())
+    assert oh32.dtype == np.float64 and np.array_equal(oh32, o.cpu().numpy())
     ctx.close()
 
 
