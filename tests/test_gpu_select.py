@@ -170,3 +170,24 @@ def test_empty_and_uneven_groups_single_and_batched():
     assert np.abs(W2 - W).max() <= 1e-12 * max(1.0, np.abs(W).max())
     for c in [ctx, c2] + other:
         c.close()
+
+
+def test_randomised_small_problems_against_the_oracle():
+    """40 seeded random problems: Nb from 5 to 600, any m in [1, Nb], radius from 0.3 to 3 (sparse
+    to dense Phi), tolerance from 0 to 10 % of max|d|, sometimes a cap on Nc: the same run as the
+    oracle (or a run the oracle's replay certifies after a near-tie)."""
+    g = np.random.default_rng(2004)
+    for case in range(40):
+        nb = int(g.integers(5, 601))
+        m = int(g.integers(1, nb + 1))
+        radius = float(g.uniform(0.3, 3.0))
+        p = synth.tiny_problem(nb=nb, seed=1000 + case, m=m, radius=radius)
+        tol = float(g.choice([0.0, 1e-4, 1e-3, 1e-2, 0.1])) * p.max_disp
+        nc_max = int(g.integers(3, nb + 1)) if g.random() < 0.3 else None
+        print(f"case {case}: nb={nb} m={m} R={radius:.3f} tol={tol:.3e} nc_max={nc_max}", flush=True)
+        r = oracle_select(p, tol_abs=tol, m=m, nc_max=nc_max)
+        if r.status < 0:
+            continue   # the oracle found the support matrix singular (close nodes at a large radius)
+        ctx, info, S, W, log = gpu_select(p, tol_abs=tol, m=m, nc_max=nc_max)
+        assert_same_run(p, info, S, W, log, r, tol, m, nc_max=nc_max)
+        ctx.close()
