@@ -164,6 +164,12 @@ int64_t gcb_get_log(gcb_ctx *ctx, int32_t *group, int64_t *node, double *err, in
  * context.  nv = 0 is a no-op.  Requires a finished gcb_select. */
 int gcb_deform(gcb_ctx *ctx, int64_t nv, const void *xyz, int in_dtype, void *out, int out_dtype, int mem);
 
+/* Device time (*ms, milliseconds) of the kernels of the last gcb_deform,
+ * between two events on the context's stream (host copies excluded; not
+ * recorded while the stream is being captured).  Waits for the second event.
+ * GCB_E_STATE if no timed deformation has run. */
+int gcb_deform_time(gcb_ctx *ctx, double *ms);
+
 /* Multiple right-hand sides on one support set: k_modes displacement fields
  * of the same boundary nodes, disp_modes (nb, 3*k_modes) float64 (columns
  * x, y, z of mode 0, then mode 1, ...), are solved on the selected S (Eqs.

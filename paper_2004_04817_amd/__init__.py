@@ -35,7 +35,7 @@ EXPORTS = ["gcb_version", "gcb_partition", "gcb_create", "gcb_destroy", "gcb_las
            "gcb_batch_end", "gcb_select_batch", "gcb_deform_batch", "gcb_batch_set_layout",
            "gcb_server_clock", "gcb_server_create", "gcb_server_destroy", "gcb_server_last_error",
            "gcb_server_submit", "gcb_server_progress", "gcb_server_result", "gcb_server_forget",
-           "gcb_server_memory"]
+           "gcb_server_memory", "gcb_deform_time"]
 
 
 class GcbError(RuntimeError):
@@ -136,6 +136,7 @@ def lib():
         L.gcb_server_progress.argtypes = [vp, i32, C.POINTER(i32)]
         L.gcb_server_result.argtypes = [vp, i64, C.POINTER(Result)]
         L.gcb_server_forget.argtypes = [vp, i64]
+        L.gcb_deform_time.argtypes = [vp, C.POINTER(C.c_double)]
         L.gcb_server_memory.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(i32)]
         for name in EXPORTS:
             getattr(L, name)
@@ -338,6 +339,12 @@ class Context:
         self.use_current_stream(kx)
         self._check(lib().gcb_deform(self._h, nv, px, in_dt, po, out_dt, mx))
         return out
+
+    def deform_time(self) -> float:
+        """Device milliseconds of the last deform's kernels (waits for them)."""
+        ms = C.c_double()
+        self._check(lib().gcb_deform_time(self._h, C.byref(ms)))
+        return ms.value
 
     def deform_multi(self, modes, xyz, out=None, out_dtype=None):
         """K displacement fields of the boundary (nb, 3K) solved on the selected

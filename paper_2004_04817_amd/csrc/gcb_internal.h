@@ -141,6 +141,8 @@ struct gcb_ctx {
     uint64_t alloc_gen = 0;            // bumped by every device allocation
     gcb::GState *state_pin = nullptr;   // pinned host copy of the state
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // selection start / end
+    hipEvent_t ev2 = nullptr, ev3 = nullptr;   // kernels of the last deformation: start / end
+    bool deform_timed = false;
     int64_t k_host = 3;                // the next iteration's k
     bool in_progress = false;          // a selection started by a batch and not yet finished
     // kept support set for a warm start (valid after a finished selection on this boundary)

@@ -728,6 +728,28 @@ int32_t batch_step(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, int32_t it
 
 }  // namespace
 
+namespace {
+
+// Events around the kernels of a deformation (not recorded while the stream is being captured).
+bool deform_timing_begin(gcb_ctx* ctx) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK(ctx, hipStreamIsCapturing(ctx->stream, &cs));
+    ctx->deform_timed = false;
+    if (cs != hipStreamCaptureStatusNone) return false;
+    if (!ctx->ev2) HIPCHK(ctx, hipEventCreate(&ctx->ev2));
+    if (!ctx->ev3) HIPCHK(ctx, hipEventCreate(&ctx->ev3));
+    HIPCHK(ctx, hipEventRecord(ctx->ev2, ctx->stream));
+    return true;
+}
+
+void deform_timing_end(gcb_ctx* ctx, bool on) {
+    if (!on) return;
+    HIPCHK(ctx, hipEventRecord(ctx->ev3, ctx->stream));
+    ctx->deform_timed = true;
+}
+
+}  // namespace
+
 extern "C" {
 
 int gcb_batch_create(gcb_batch** out, int device, void* hip_stream) {
@@ -930,6 +952,8 @@ void gcb_destroy(gcb_ctx* ctx) {
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->ev2) (void)hipEventDestroy(ctx->ev2);
+    if (ctx->ev3) (void)hipEventDestroy(ctx->ev3);
     if (ctx->state_pin) (void)hipHostFree(ctx->state_pin);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
     delete ctx;
@@ -1150,6 +1174,7 @@ int gcb_deform(gcb_ctx* ctx, int64_t nv, const void* xyz, int in_dtype, void* ou
             din = ctx->tmp;
             dout = static_cast<char*>(ctx->tmp) + in_pad;
         }
+        const bool timed = deform_timing_begin(ctx);
         if (ctx->params.precision == GCB_PREC_FP32_EVAL) {
             Support& sp = ctx->sp;
             ensure_fp32_copies(ctx);
@@ -1160,11 +1185,25 @@ int gcb_deform(gcb_ctx* ctx, int64_t nv, const void* xyz, int in_dtype, void* ou
             launch_volume(ctx->stream, nv, din, in_dtype == GCB_F64, ctx->bd.inv_r, ctx->sp, (int)ctx->info.nc, dout,
                           out_dtype == GCB_F64);
         }
+        deform_timing_end(ctx, timed);
         HIPCHK(ctx, hipGetLastError());
         if (mem == GCB_MEM_HOST) {
             HIPCHK(ctx, hipMemcpyAsync(out, dout, out_b, hipMemcpyDeviceToHost, ctx->stream));
             sync(ctx);
         }
+        return GCB_OK;
+    });
+}
+
+int gcb_deform_time(gcb_ctx* ctx, double* ms) {
+    return guard(ctx, [&] {
+        if (!ms) fail(ctx, GCB_E_INVALID, "ms is NULL");
+        if (!ctx->deform_timed) fail(ctx, GCB_E_STATE, "no timed deformation");
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        HIPCHK(ctx, hipEventSynchronize(ctx->ev3));
+        float t = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&t, ctx->ev2, ctx->ev3));
+        *ms = t;
         return GCB_OK;
     });
 }

@@ -181,3 +181,15 @@ def test_volume_far_points_and_translation():
     osup = ctx.deform(q.xyz[S])
     assert np.abs(osup - q.disp[S]).max() <= 1e-9 * md
     ctx.close()
+
+
+def test_deform_time_reports_the_kernels():
+    p = synth.config_small_ellipsoid(nv=20000)
+    ctx, info, S, W, log = gpu_select(p)
+    with pytest.raises(gcb.GcbError) as e:
+        ctx.deform_time()              # nothing timed yet
+    assert e.value.code == gcb.GCB_E_STATE
+    ctx.deform(p.volume)
+    ms = ctx.deform_time()
+    assert 0.0 < ms < 1000.0
+    ctx.close()
