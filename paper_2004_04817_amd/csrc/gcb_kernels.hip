@@ -54,9 +54,9 @@ __device__ __forceinline__ void accumulate_vol(double mx, double my, double mz, 
     const double* __restrict__ qq = vt.qq;
     int j = 0;
 #pragma unroll 1
-    for (; j + 4 <= n; j += 4) {
+    for (; j + 8 <= n; j += 8) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             const double d = fma(mx, qx[j + u], fma(my, qy[j + u], fma(mz, qz[j + u], uu + qq[j + u])));
             const double phi = wendland_quarter(d);
             ax = fma(wx[j + u], phi, ax);
