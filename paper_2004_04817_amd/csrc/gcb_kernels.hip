@@ -472,6 +472,10 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) { sweep_body<kStage>(A, blockIdx.x); }
+// Large groups (several targets per lane): many more blocks, so the small window keeps several blocks resident
+// per CU.  With more than one target per lane every lane sums its supports in one sequence across windows, so
+// the window size does not change any result.
+__global__ __launch_bounds__(kBlock) void k_sweep_wide(SweepArgs A) { sweep_body<kStageBatch>(A, blockIdx.x); }
 
 // l = M b, one wave per row of M (kRowsL rows per block); b_j = phi(|r_new -
 // s_j| / R) staged in LDS windows.  Block partials Pb[blk] = (b.W over
@@ -1409,7 +1413,10 @@ int sweep_blocks(int gmax) {
 void launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub) {
     const SweepArgs A = make_sweep_args(ic, g);
     const int nrec = A.T > 0 ? sweep_nblocks(A.T) : 0;
-    if (A.T > 0) GCB_LAUNCH(k_sweep, dim3(nrec), dim3(kBlock), s, A);
+    if (A.T > 0) {
+        if (A.tpl > 1) GCB_LAUNCH(k_sweep_wide, dim3(nrec), dim3(kBlock), s, A);
+        else GCB_LAUNCH(k_sweep, dim3(nrec), dim3(kBlock), s, A);
+    }
     launch_factor(s, ic, factor_blocks(n_ub), -1, g, nrec);
 }
 

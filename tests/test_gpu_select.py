@@ -191,3 +191,13 @@ def test_randomised_small_problems_against_the_oracle():
         ctx, info, S, W, log = gpu_select(p, tol_abs=tol, m=m, nc_max=nc_max)
         assert_same_run(p, info, S, W, log, r, tol, m, nc_max=nc_max)
         ctx.close()
+
+
+@pytest.mark.parametrize("m", [1, 2])
+def test_large_groups_against_the_oracle(m):
+    """Groups of 10,000 and 5,000 nodes (several targets per lane in the sweep, small staging windows)."""
+    p = synth.config_small_ellipsoid(nb=10_000, with_volume=False)
+    ctx, info, S, W, log = gpu_select(p, m=m)
+    r = oracle_select(p, m=m)
+    assert_same_run(p, info, S, W, log, r, p.tol_abs, m)
+    ctx.close()
