@@ -472,10 +472,61 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) { sweep_body<kStage>(A, blockIdx.x); }
-// Large groups (several targets per lane): many more blocks, so the small window keeps several blocks resident
-// per CU.  With more than one target per lane every lane sums its supports in one sequence across windows, so
-// the window size does not change any result.
+// Groups of 4,097 to 8,192 targets (two targets per lane): many more blocks, so the small window keeps several
+// blocks resident per CU.  With more than one target per lane every lane sums its supports in one sequence
+// across windows, so the window size does not change any result.
 __global__ __launch_bounds__(kBlock) void k_sweep_wide(SweepArgs A) { sweep_body<kStageBatch>(A, blockIdx.x); }
+// Groups above 8,192 targets: one target per lane and 64 targets per block; the block's four waves take contiguous quarters
+// of the supports, read through the scalar cache (no staging, no barrier until the end), and the quarter sums
+// are added in a fixed order.  One best record per block, as in k_sweep.
+constexpr int kLaneTargets = 64;
+
+int sweep_lanes_blocks(int T) { return T > 0 ? (T + kLaneTargets - 1) / kLaneTargets : 1; }
+
+__global__ __launch_bounds__(kBlock) void k_sweep_lanes(SweepArgs A) {
+    __shared__ double part[3][4][kLaneTargets];
+    const GState st = *A.st;
+    if (st.done) return;
+    const int n = st.n;
+    const int q = threadIdx.x >> 6, tl = threadIdx.x & 63;
+    const int t = blockIdx.x * kLaneTargets + tl;   // target within the group
+    const int p = A.t0 + min(t, A.T - 1);
+    const int s0 = (int)((int64_t)n * q / 4), s1 = (int)((int64_t)n * (q + 1) / 4);
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    accumulate64(A.px[p], A.py[p], A.pz[p], s0, s1, A.sv.sx, A.sv.sy, A.sv.sz, A.sv.wx, A.sv.wy, A.sv.wz, ax, ay,
+                 az);
+    part[0][q][tl] = ax;
+    part[1][q][tl] = ay;
+    part[2][q][tl] = az;
+    __syncthreads();
+    if (q != 0) return;
+    const bool live = t < A.T && !A.inS[p];
+    double e2 = -1.0;
+    if (live) {
+        const double fx = (part[0][0][tl] + part[0][1][tl]) + (part[0][2][tl] + part[0][3][tl]);
+        const double fy = (part[1][0][tl] + part[1][1][tl]) + (part[1][2][tl] + part[1][3][tl]);
+        const double fz = (part[2][0][tl] + part[2][1][tl]) + (part[2][2][tl] + part[2][3][tl]);
+        const double ex = fx - A.pdx[p], ey = fy - A.pdy[p], ez = fz - A.pdz[p];
+        e2 = fma(ez, ez, fma(ey, ey, ex * ex));
+    }
+    const int32_t orig = live ? A.perm[p] : 0x7fffffff;
+    const Best b = wave_best(Best{e2, orig, tl});
+    const int32_t count = wave_isum(live ? 1 : 0);
+    // live targets have distinct original indices, so the best lane is unique; with none, lane 0 writes
+    if (count > 0 ? tl == b.aux : tl == 0) {
+        ArgRec& o = A.rec[blockIdx.x];
+        o.e2 = e2;
+        o.orig = orig;
+        o.pos = p;
+        o.count = count;
+        o.x = A.px[p];
+        o.y = A.py[p];
+        o.z = A.pz[p];
+        o.dx = A.pdx[p];
+        o.dy = A.pdy[p];
+        o.dz = A.pdz[p];
+    }
+}
 
 // l = M b, one wave per row of M (kRowsL rows per block); b_j = phi(|r_new -
 // s_j| / R) staged in LDS windows.  Block partials Pb[blk] = (b.W over
@@ -1412,9 +1463,12 @@ int sweep_blocks(int gmax) {
 
 void launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub) {
     const SweepArgs A = make_sweep_args(ic, g);
-    const int nrec = A.T > 0 ? sweep_nblocks(A.T) : 0;
+    // above 8,192 targets the lanes form has at least 129 blocks of 64 targets; below, too few to fill the chip
+    const bool lanes = A.T > 8192;
+    const int nrec = A.T > 0 ? (lanes ? sweep_lanes_blocks(A.T) : sweep_nblocks(A.T)) : 0;
     if (A.T > 0) {
-        if (A.tpl > 1) GCB_LAUNCH(k_sweep_wide, dim3(nrec), dim3(kBlock), s, A);
+        if (lanes) GCB_LAUNCH(k_sweep_lanes, dim3(nrec), dim3(kBlock), s, A);
+        else if (A.tpl > 1) GCB_LAUNCH(k_sweep_wide, dim3(nrec), dim3(kBlock), s, A);
         else GCB_LAUNCH(k_sweep, dim3(nrec), dim3(kBlock), s, A);
     }
     launch_factor(s, ic, factor_blocks(n_ub), -1, g, nrec);

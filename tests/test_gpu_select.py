@@ -195,7 +195,8 @@ def test_randomised_small_problems_against_the_oracle():
 
 @pytest.mark.parametrize("m", [1, 2])
 def test_large_groups_against_the_oracle(m):
-    """Groups of 10,000 and 5,000 nodes (several targets per lane in the sweep, small staging windows)."""
+    """Groups of 10,000 nodes (one target per lane, supports split over the block's waves) and 5,000 nodes (two
+    targets per lane, small staging windows)."""
     p = synth.config_small_ellipsoid(nb=10_000, with_volume=False)
     ctx, info, S, W, log = gpu_select(p, m=m)
     r = oracle_select(p, m=m)
