@@ -198,7 +198,8 @@ Tuning g_tuning;
 // lanes per target (lpt <= the tuning cap) and targets per lane for a group of T targets
 inline void sweep_layout(int T, int& lpt, int& tpl) {
     // one wave per target measured fastest for groups of ~10^3 (each target reads every support
-    // once, so wider layouts only add reduction work); bigger groups hold 2-4 targets per lane
+    // once, so wider layouts only add reduction work); groups of 4,097 to 8,192 hold 2 targets per
+    // lane; above that k_sweep_lanes runs instead, and the 4-per-lane layout only bounds its record count
     if (T <= 512) { lpt = 128; tpl = 1; }
     else if (T <= 4096) { lpt = 64; tpl = 1; }
     else if (T <= 8192) { lpt = 64; tpl = 2; }
