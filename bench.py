@@ -125,9 +125,25 @@ def problem(name):
     return synth.config_wing()
 
 
-def cpu_baseline(p, nv_sample):
-    """The FP64 oracle as it stands, on all host cores: full greedy + a volume sample.
-    Returns the baseline record and the oracle's results (support set, sampled displacements)."""
+def host_cpu() -> dict:
+    """Model name and usable core count of the host the oracle runs on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "cpu_count": os.cpu_count(), "usable_cores": usable}
+
+
+def cpu_baseline(p, nv_sample, nv_single=300_000):
+    """The FP64 oracle as it stands, on all host cores: full greedy + a volume sample, with the
+    greedy (t1 + t2) and volume (t3) phases timed apart; then one thread on the same greedy and a
+    smaller volume sample.  Returns the baseline record and the oracle's all-core results
+    (support set, sampled displacements)."""
     import oracle
     threads = os.cpu_count() or 1
     t0 = time.perf_counter()
@@ -136,11 +152,29 @@ def cpu_baseline(p, nv_sample):
     vol = p.volume[:nv_sample]
     ref = oracle.interpolate(p.xyz[r.S], r.W, p.radius, vol, nthreads=threads)
     t2 = time.perf_counter()
-    pairs = r.pairs_group + r.pairs_append + vol.shape[0] * r.nc
-    return {"value": pairs / (t2 - t0), "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"full greedy (Nb={p.nb}, m={p.m}, Nc={r.nc}, {r.iterations} iterations, {t1 - t0:.2f} s) "
-                      f"+ Eq. 6 at {vol.shape[0]} volume points ({t2 - t1:.2f} s)",
-            "seconds": t2 - t0}, r, ref
+    pg = r.pairs_group + r.pairs_append
+    pv = vol.shape[0] * r.nc
+    rec = {"value": (pg + pv) / (t2 - t0), "unit": "pair-evals/s", "cores": threads, "kind": "oracle",
+           "sample": f"full greedy (Nb={p.nb}, m={p.m}, Nc={r.nc}, {r.iterations} iterations, {t1 - t0:.2f} s) "
+                     f"+ Eq. 6 at {vol.shape[0]} volume points ({t2 - t1:.2f} s)",
+           "seconds": t2 - t0,
+           "phases": {"greedy": {"seconds": t1 - t0, "pair_evals_per_s": pg / (t1 - t0)},
+                      "volume": {"seconds": t2 - t1, "pair_evals_per_s": pv / (t2 - t1)}},
+           "host": host_cpu()}
+    if nv_single > 0:
+        s0 = time.perf_counter()
+        r1 = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed, nthreads=1)
+        s1 = time.perf_counter()
+        vol1 = p.volume[:min(nv_single, p.volume.shape[0])]
+        oracle.interpolate(p.xyz[r1.S], r1.W, p.radius, vol1, nthreads=1)
+        s2 = time.perf_counter()
+        pg1 = r1.pairs_group + r1.pairs_append
+        pv1 = vol1.shape[0] * r1.nc
+        rec["single_thread"] = {"value": (pg1 + pv1) / (s2 - s0), "cores": 1,
+                                "sample": f"full greedy + Eq. 6 at {vol1.shape[0]} volume points",
+                                "phases": {"greedy": {"seconds": s1 - s0, "pair_evals_per_s": pg1 / (s1 - s0)},
+                                           "volume": {"seconds": s2 - s1, "pair_evals_per_s": pv1 / (s2 - s1)}}}
+    return rec, r, ref
 
 
 def multi_surface(count, dev, vs_oracle=False):
