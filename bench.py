@@ -177,6 +177,19 @@ def cpu_baseline(p, nv_sample, nv_single=300_000):
     return rec, r, ref
 
 
+def certify_sequence(ctx, p, S_gpu) -> dict:
+    """Follow-mode replay of the context's last selection by the oracle: every iteration's group, its
+    argmax within tau = 1e-9 max|d| of the oracle's own maximum, and every append decision; continuing from
+    the GPU's choices, so a legitimate near-tie divergence is certified rather than counted as an error."""
+    import oracle
+    log = ctx.get_log()
+    tau = 1e-9 * p.max_disp
+    bad, reason, gap = oracle.validate(p.xyz, p.disp, p.radius, p.m, p.tol_abs, S_gpu[:3], log.group, log.node,
+                                       log.appended, tau, seed=p.seed, nthreads=os.cpu_count() or 1)
+    return {"certified": bad < 0, "first_bad_iteration": bad, "reason": reason, "max_gap_rel_max_d": gap / p.max_disp,
+            "tau_rel_max_d": 1e-9, "iterations": int(len(log.group))}
+
+
 def multi_surface(count, dev, vs_oracle=False):
     """Uneven independent surfaces (Nb log-uniform in [1e3, 5e4], Nv = 25 Nb), each selected and
     deformed: one context at a time vs one batch (shared launches); with vs_oracle, the batch's
@@ -530,8 +543,14 @@ def main():
         S_gpu, _ = ctx.get_support()
         o = out[: ref.shape[0]].cpu().numpy()
         err = np.sqrt(((o - ref) ** 2).sum(axis=1))
+        S_orc = np.asarray(r_orc.S)
+        k = min(len(S_gpu), len(S_orc))
+        diff = np.nonzero(np.asarray(S_gpu[:k]) != S_orc[:k])[0]
         rec["accuracy"]["vs_oracle"] = {
-            "same_support_sequence": bool(np.array_equal(S_gpu, r_orc.S)),
+            "same_support_sequence": bool(np.array_equal(S_gpu, S_orc)),
+            "identical_prefix": int(diff[0]) if diff.size else k,
+            "nc_gpu": int(len(S_gpu)), "nc_oracle": int(len(S_orc)),
+            "gpu_sequence_certified": certify_sequence(ctx, p, S_gpu),
             "volume_points_compared": int(ref.shape[0]),
             "volume_max_err_rel_max_d": float(err.max() / p.max_disp),
             "volume_rms_err_rel_max_d": float(np.sqrt((err ** 2).mean()) / p.max_disp),
