@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--requests", type=int, default=250,
                     help="also replay a Poisson stream of this many deformation requests (20 req/s), served "
                          "with continuous batching and resident meshes vs one at a time (0: skip)")
+    ap.add_argument("--warmup-requests", type=int, default=25,
+                    help="requests at the start of the stream left out of the latency percentiles")
     ap.add_argument("--saturation-rate", type=float, default=80.0,
                     help="also replay the stream at this arrival rate (req/s), above one-at-a-time capacity (0: skip)")
     ap.add_argument("--m-sweep", default="1,5,10,20,40,80,107,160",
@@ -542,7 +544,8 @@ def main():
     if a.surfaces > 0:
         rec["multi_surface"] = multi_surface(a.surfaces, dev, vs_oracle=not a.no_cpu_baseline)
     if a.requests > 0:
-        rec["serving"] = serving_section(a.requests, dev, sat_rate=a.saturation_rate)
+        rec["serving"] = serving_section(a.requests, dev, warmup_requests=a.warmup_requests,
+                                         sat_rate=a.saturation_rate)
         rec["latency_ms"] = {"p50": rec["serving"]["served"]["p50_ms"], "p99": rec["serving"]["served"]["p99_ms"],
                              "p50_one_at_a_time_fp64": rec["serving"]["one_at_a_time"]["p50_ms"],
                              "p99_one_at_a_time_fp64": rec["serving"]["one_at_a_time"]["p99_ms"],
