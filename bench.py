@@ -374,6 +374,9 @@ def main():
                    "tol_abs": p.tol_abs, "tol_rel": p.tol_rel, "nc": nc, "iterations": info["iterations"],
                    "precision": "fp64", "parallelism": "single-gpu"},
         "phases_ms": {"select": float(np.mean([i["ms_select"] for i in infos])), "volume": vol_avg_ms},
+        "phase_pair_evals_per_s": {
+            "greedy": pairs_greedy / (1e-3 * float(np.mean([i["ms_select"] for i in infos]))),
+            "volume": pairs_volume / (1e-3 * vol_avg_ms)},
         "pairs": {"group": info["pairs_group"], "append": info["pairs_append"], "volume": pairs_volume,
                   "certificate": info["pairs_cert"]},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
