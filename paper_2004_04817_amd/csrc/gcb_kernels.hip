@@ -225,14 +225,14 @@ struct Decision {
     double E;
 };
 
-__device__ __forceinline__ Decision decide_local(const GState& st, int n, int32_t m, double e2, double tol_abs,
-                                                 int64_t nc_max, int64_t cap) {
+__device__ __forceinline__ Decision decide_local(int32_t done, int32_t quiet, int n, int32_t m, double e2,
+                                                 double tol_abs, int64_t nc_max, int64_t cap) {
     Decision d;
     const bool have = e2 >= 0.0;
     d.E = have ? sqrt(e2) : 0.0;
     d.app = 0;
-    d.done = st.done;
-    d.quiet = st.quiet;
+    d.done = done;
+    d.quiet = quiet;
     if (have && d.E > tol_abs) {
         if (n < nc_max && n < cap) {
             d.app = 1;
@@ -281,10 +281,12 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
     const int grp = threadIdx.x / lpt;
     const int gl = threadIdx.x % lpt;               // lane within the group
     const int tbase = (bid * groups + grp) * tpl;
-    if (threadIdx.x == 0) {
-        s_n = st->n;
-        s_done = st->done;
-    }
+    // |S| and the status, loaded by every lane with a zero offset held in a vector register (so they
+    // issue as vector loads and nothing waits for them here); thread 0 publishes its values after the
+    // other loads are issued
+    int zero = 0;
+    asm volatile("" : "+v"(zero));
+    const int32_t st_n = st[zero].n, st_done = st[zero].done;
     // everything below is independent of |S| and is loaded in one round with the state:
     // the group's targets, what the candidate threads need, and the first window of supports
     double tx[4], ty[4], tz[4];
@@ -295,24 +297,17 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
         ty[q] = py[t0 + t];
         tz[q] = pz[t0 + t];
     }
+    // candidate threads (one per target of the block) load what the record needs; the others repeat
+    // thread 0's loads (same addresses, no traffic), so the loads carry no branch, and the membership byte
+    // is tested only after the barrier (nothing waits for it here)
     const int ncand = groups * 4;
-    double cdx = 0.0, cdy = 0.0, cdz = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
-    int32_t corig = 0x7fffffff;
-    bool clive = false;
-    int ct = 0;
-    if ((int)threadIdx.x < ncand) {
-        const int gq = threadIdx.x / 4, q = threadIdx.x % 4;
-        ct = (bid * groups + gq) * tpl + q;
-        const int tc = min(ct, T - 1);
-        clive = q < tpl && ct < T && !inS[t0 + tc];
-        cdx = pdx[t0 + tc];
-        cdy = pdy[t0 + tc];
-        cdz = pdz[t0 + tc];
-        cx = px[t0 + tc];
-        cy = py[t0 + tc];
-        cz = pz[t0 + tc];
-        corig = perm[t0 + tc];
-    }
+    const int tcand = (int)threadIdx.x < ncand ? (int)threadIdx.x : 0;
+    const int ct = (bid * groups + tcand / 4) * tpl + tcand % 4;
+    const int tc = min(ct, T - 1);
+    const uint8_t cins = inS[t0 + tc];
+    const double cdx = pdx[t0 + tc], cdy = pdy[t0 + tc], cdz = pdz[t0 + tc];
+    const double cx = px[t0 + tc], cy = py[t0 + tc], cz = pz[t0 + tc];
+    const int32_t corig = perm[t0 + tc];
     // the first 256 supports are staged with the state load; the rest of the first window once |S| is
     // known (a window of up to STAGE supports staged before |S| is known wastes bandwidth while |S| is small)
     const int w0eager = (int)min((int64_t)min(STAGE, 256), nub);
@@ -324,9 +319,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
         ls[4][j] = sv.wy[j];
         ls[5][j] = sv.wz[j];
     }
+    if (threadIdx.x == 0) {
+        s_n = st_n;
+        s_done = st_done;
+    }
     __syncthreads();
     if (s_done) return;
     const int n = s_n;
+    const bool clive = (int)threadIdx.x < ncand && tcand % 4 < tpl && ct < T && !cins;
     const int w0end = min(STAGE, n);
     if (w0end > w0eager) {
         for (int j = w0eager + threadIdx.x; j < w0end; j += kBlock) {
@@ -565,7 +565,7 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
     const int64_t log_cap = A.log_cap;
     __shared__ double bw[kBWindow];
     __shared__ double sl[kRowsL * RPW];
-    __shared__ GState s_st;
+    __shared__ int32_t s_n, s_done;
     __shared__ double s_we2[kBigBlock / 64];
     __shared__ int32_t s_wor[kBigBlock / 64], s_wri[kBigBlock / 64], s_cnt[kBigBlock / 64];
     __shared__ double s_win[6];
@@ -576,21 +576,18 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
     const int lane = threadIdx.x & 63;
     constexpr int rpw = RPW;             // rows of M per wave
     constexpr int rpb = kRowsL * rpw;    // rows of M per block
-    if (threadIdx.x == 0) s_st = *st;
-    // each thread keeps the best of its records on (e^2, original index), with its fields
-    double be2 = -1.0, bx = 0.0, by = 0.0, bz = 0.0, bdx = 0.0, bdy = 0.0, bdz = 0.0;
-    int32_t bor = 0x7fffffff, bpos = -1, c = 0;
-    if (init_t < 0) {
-        for (int i = threadIdx.x; i < nrec; i += kBigBlock) {
-            const ArgRec x = srec[i];
-            if (better(x.e2, x.orig, be2, bor)) {
-                be2 = x.e2; bor = x.orig; bpos = x.pos;
-                bx = x.x; by = x.y; bz = x.z; bdx = x.dx; bdy = x.dy; bdz = x.dz;
-            }
-            c += x.count;
-        }
-    }
-    // support coordinates of the first b window and of this block's b.W slice, loaded early
+    // Thread 0 reads the fields of the state it needs into registers and publishes |S| and the status to
+    // the block only after the other loads are issued: loads that depend neither on |S| nor on the
+    // decision (support coordinates of the first b window and of this block's b.W slice) then arrive in
+    // the round trip of the state and the records.
+    // (Every lane loads them with a zero offset held in a vector register, so they issue as vector loads
+    // and no wait is placed before the other loads; only thread 0's values are used.)
+    int zero = 0;
+    asm volatile("" : "+v"(zero));
+    const GState& stv = st[zero];
+    const int32_t st_n = stv.n, st_done = stv.done, st_quiet = stv.quiet;
+    const int64_t st_log = stv.log_len;
+    const uint64_t st_pairs = stv.pairs_group;
     constexpr int kBPre = 1;
     double pbx[kBPre], pby[kBPre], pbz[kBPre];
 #pragma unroll
@@ -606,16 +603,36 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
         wsx = sv.sx[j]; wsy = sv.sy[j]; wsz = sv.sz[j];
         wwx = sv.wx[j]; wwy = sv.wy[j]; wwz = sv.wz[j];
     }
+    // each thread keeps the best of its records on (e^2, original index), with its fields
+    double be2 = -1.0, bx = 0.0, by = 0.0, bz = 0.0, bdx = 0.0, bdy = 0.0, bdz = 0.0;
+    int32_t bor = 0x7fffffff, bpos = -1, c = 0;
+    if (init_t < 0) {
+        for (int i = threadIdx.x; i < nrec; i += kBigBlock) {
+            // whole records with selects: every field is loaded at once, nothing stays in flight
+            const ArgRec x = srec[i];
+            const bool bt = better(x.e2, x.orig, be2, bor);
+            be2 = bt ? x.e2 : be2; bor = bt ? x.orig : bor; bpos = bt ? x.pos : bpos;
+            bx = bt ? x.x : bx; by = bt ? x.y : by; bz = bt ? x.z : bz;
+            bdx = bt ? x.dx : bdx; bdy = bt ? x.dy : bdy; bdz = bt ? x.dz : bdz;
+            c += x.count;
+        }
+    }
+    if (threadIdx.x == 0) {
+        s_n = st_n;
+        s_done = st_done;
+    }
+    // Everything loaded so far has arrived (the records came last); waiting for it here, where it costs
+    // nothing, keeps the loads of M below free to stay in flight through the decision.
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    const GState sg = s_st;
-    if (init_t < 0 && sg.done) {
+    if (init_t < 0 && s_done) {
         if (bid == 0 && threadIdx.x == 0) {
             irec->app = 0;
             irec->ran = 0;
         }
         return;
     }
-    const int n = init_t >= 0 ? init_t : sg.n;
+    const int n = init_t >= 0 ? init_t : s_n;
     const int i0 = bid * rpb;
     const int i = i0 + wave;   // first of this wave's rows i, i + kRowsL, ...
     // this wave's row of M, loaded while the decision is taken
@@ -699,14 +716,14 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
                 b.pos = -1;
                 b.x = b.y = b.z = b.dx = b.dy = b.dz = 0.0;
             }
-            const Decision d = decide_local(sg, n, m, b.e2, tol_abs, nc_max, cap);
+            const Decision d = decide_local(st_done, st_quiet, n, m, b.e2, tol_abs, nc_max, cap);   // thread 0
             s_app = d.app;
             s_q[0] = b.x;
             s_q[1] = b.y;
             s_q[2] = b.z;
             if (bid == 0) {
                 if (d.done != 4) {
-                    const int64_t it = sg.log_len;
+                    const int64_t it = st_log;
                     if (it < log_cap) {
                         log_group[it] = g;
                         log_node[it] = b.e2 >= 0.0 ? b.orig : -1;
@@ -714,7 +731,7 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
                         log_app[it] = (int8_t)d.app;
                     }
                     st->log_len = it + 1;
-                    st->pairs_group = sg.pairs_group + (uint64_t)total * (uint64_t)n;
+                    st->pairs_group = st_pairs + (uint64_t)total * (uint64_t)n;
                 }
                 st->quiet = d.quiet;
                 st->done = d.done;
@@ -838,7 +855,7 @@ __global__ __launch_bounds__(kBigBlock) void k_factor_l(FactorLArgs A) { factor_
 // sums the k_factor_l partials in block order to s = 1 - l.l and
 // e = d_new - b.W.  Writes the new row [-u^T/sqrt(s), 1/sqrt(s)] into both
 // copies of M and W <- [W - u e/s; e/s]; block 0 commits the iteration.
-template <int RPW>
+template <int RPW, bool PREW = false>
 __device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bid) {
     GState* __restrict__ st = A.st;
     const IterRec* __restrict__ irec = A.irec;
@@ -851,12 +868,27 @@ __device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bi
     __shared__ double part[4][kBigBlock / 64];
     __shared__ double sh[4];
     __shared__ int32_t s_bad;
-    // the iteration record is only read here (k_factor_l wrote it), so every block sees the same values
-    const IterRec r = *irec;
-    // this thread's share of the k_factor_l partials, loaded with the record (masked once n is known)
-    double pv[4] = {0.0, 0.0, 0.0, 0.0};
     constexpr int rpw = RPW;             // columns of M per wave
     constexpr int rpb = kRowsL * rpw;    // columns of M per block (as in k_factor_l)
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int j = bid * rpb + wave;   // first of this wave's columns j, j + kRowsL, ...
+    // With PREW, the W entries of this wave's columns are loaded with the iteration record (bounded by the
+    // capacity; used only for columns below n), so that the update at the end needs no further round
+    // trip; the batched kernels, short of registers, read them at the end.
+    double wox[RPW], woy[RPW], woz[RPW];
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) {
+        const int jq = j + kRowsL * q;
+        const bool ok = PREW && lane == 0 && jq < cap;
+        wox[q] = ok ? sm.wx[jq] : 0.0;
+        woy[q] = ok ? sm.wy[jq] : 0.0;
+        woz[q] = ok ? sm.wz[jq] : 0.0;
+    }
+    // the iteration record is only read here (k_factor_l wrote it), so every block sees the same values
+    const IterRec r = *irec;
+    // this thread's share of the k_factor_l partials (masked once n is known)
+    double pv[4] = {0.0, 0.0, 0.0, 0.0};
     const int nbl_cap = (int)((cap + kRowsL - 1) / kRowsL);   // partials come per chunk of kRowsL rows
     if ((int)threadIdx.x < nbl_cap) {
 #pragma unroll
@@ -866,9 +898,6 @@ __device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bi
     const int n = r.n;
     const int ncb = max(1, (n + kRowsL - 1) / kRowsL);
     if ((int)bid >= max(1, (n + rpb - 1) / rpb)) return;
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const int j = bid * rpb + wave;   // first of this wave's columns j, j + kRowsL, ...
     // column j of M and the matching entries of l, loaded before s is known
     constexpr int kColPre = 16;
     double mc[kColPre], lv[kColPre];
@@ -924,6 +953,9 @@ __device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bi
         if (jq < n) {
             double* cq = Mc + (size_t)jq * cap - (size_t)jq * (jq - 1) / 2;
             double a0 = 0.0, a1 = 0.0;
+            // an accumulator defined here keeps the first products from being folded into the prefetch
+            // above, where they would wait for its first loads before the others are issued
+            asm volatile("" : "+v"(a0));
             // the same summation order for every column, whichever wave and round holds it
 #pragma unroll
             for (int u = 0; u < kColPre; ++u) {
@@ -945,9 +977,9 @@ __device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bi
                 const double v = -u * rs;
                 sm.M[(size_t)n * (n + 1) / 2 + jq] = v;
                 cq[n - jq] = v;
-                sm.wx[jq] = fma(-u, cx, sm.wx[jq]);
-                sm.wy[jq] = fma(-u, cy, sm.wy[jq]);
-                sm.wz[jq] = fma(-u, cz, sm.wz[jq]);
+                sm.wx[jq] = fma(-u, cx, PREW ? wox[q] : sm.wx[jq]);
+                sm.wy[jq] = fma(-u, cy, PREW ? woy[q] : sm.wy[jq]);
+                sm.wz[jq] = fma(-u, cz, PREW ? woz[q] : sm.wz[jq]);
             }
         }
     }
@@ -969,7 +1001,7 @@ __device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bi
     }
 }
 
-__global__ __launch_bounds__(kBigBlock) void k_factor_u(FactorUArgs A) { factor_u_body<1>(A, blockIdx.x); }
+__global__ __launch_bounds__(kBigBlock) void k_factor_u(FactorUArgs A) { factor_u_body<1, true>(A, blockIdx.x); }
 
 // ---------------------------------------------------------------- batched iteration kernels (a10)
 // One launch advances every surface of a batch: block b belongs to surface s
