@@ -97,9 +97,44 @@ __device__ __forceinline__ bool better(double v, int32_t i, double bv, int32_t b
     return v > bv || (v == bv && i < bi);
 }
 
+// Wave reductions (every lane of the wave active).  The first four steps pair lanes inside each row of
+// 16 with DPP lane moves (no LDS round trip): swaps within quads (xor 1, xor 2), then the half-row and
+// row mirrors; the last two pair rows 16 and 32 lanes apart.  Every step pairs each lane with a partner
+// that pairs back with it, and both combine the same two values, so all lanes end with one identical
+// result in a fixed order.
+constexpr int kDppXor1 = 0xB1;          // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;          // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;   // lane i of each half row of 8 reads lane 7 - i
+constexpr int kDppMirror = 0x140;       // lane i of each row of 16 reads lane 15 - i
+
+template <int CTRL>
+__device__ __forceinline__ int32_t dpp_i32(int32_t v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)dpp_i32<CTRL>((int32_t)(uint32_t)b);
+    const uint32_t hi = (uint32_t)dpp_i32<CTRL>((int32_t)(uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+template <int CTRL>
+__device__ __forceinline__ void best_step_dpp(Best& b) {
+    const double v = dpp_f64<CTRL>(b.v);
+    const int32_t i = dpp_i32<CTRL>(b.idx);
+    const int32_t a = dpp_i32<CTRL>(b.aux);
+    if (better(v, i, b.v, b.idx)) { b.v = v; b.idx = i; b.aux = a; }
+}
+
 __device__ __forceinline__ Best wave_best(Best b) {
+    best_step_dpp<kDppXor1>(b);
+    best_step_dpp<kDppXor2>(b);
+    best_step_dpp<kDppHalfMirror>(b);
+    best_step_dpp<kDppMirror>(b);
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
+    for (int off = 16; off <= 32; off <<= 1) {
         const double v = __shfl_xor(b.v, off, 64);
         const int32_t i = __shfl_xor(b.idx, off, 64);
         const int32_t a = __shfl_xor(b.aux, off, 64);
@@ -139,8 +174,12 @@ __device__ Best block_best_n(Best b) {
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    v += dpp_f64<kDppXor1>(v);
+    v += dpp_f64<kDppXor2>(v);
+    v += dpp_f64<kDppHalfMirror>(v);
+    v += dpp_f64<kDppMirror>(v);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
     return v;
 }
 
@@ -158,8 +197,12 @@ __device__ double block_sum(double v) {
 }
 
 __device__ __forceinline__ int32_t wave_isum(int32_t v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    v += dpp_i32<kDppXor1>(v);
+    v += dpp_i32<kDppXor2>(v);
+    v += dpp_i32<kDppHalfMirror>(v);
+    v += dpp_i32<kDppMirror>(v);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
     return v;
 }
 
@@ -669,15 +712,10 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
             }
         }
     } else {
-        // block-wide best: xor tree per wave, then waves in order (a total order, so the result is unique)
-        double we2 = be2;
-        int32_t wor = bor;
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double oe = __shfl_xor(we2, off, 64);
-            const int32_t oo = __shfl_xor(wor, off, 64);
-            if (better(oe, oo, we2, wor)) { we2 = oe; wor = oo; }
-        }
+        // block-wide best: per wave, then waves in order (a total order, so the result is unique)
+        const Best wb = wave_best(Best{be2, bor, 0});
+        const double we2 = wb.v;
+        const int32_t wor = wb.idx;
         c = wave_isum(c);
         if (lane == 0) {
             s_we2[wave] = we2;

@@ -67,14 +67,18 @@ def test_refactor_wing_drift_and_same_result():
     M0 = c.get_factor()
     drift, info2 = c.refactor()
     M1 = c.get_factor()
-    assert drift <= 1e-9, drift
-    assert np.abs(M1 - M0).max() <= 1e-9 * np.abs(M0).max()
+    # Two FP64 computations of L^-1 for Phi_S (kappa 1.6e9 here, so kappa(L) ~ 4e4) may differ by about
+    # n kappa(L) u ~ 5e-9 relative at n = 1,135: the grown factor, the dense one and the oracle's all
+    # within 1e-8 of each other
+    assert drift <= 1e-8, drift
+    assert np.abs(M1 - M0).max() <= 1e-8 * np.abs(M0).max()
     _, W1 = c.get_support()
     assert np.abs(W1 - W).max() <= 1e-7 * np.abs(W).max()
     assert info2["converged"] and info2["final_max_err"] == pytest.approx(info["final_max_err"], rel=1e-4)
     # against the oracle's factor of the same set (sampled rows: the full dense inverse is 1e6 entries)
     Mo = oracle.inverse_factor(p.xyz, S, p.radius)
     assert np.abs(M1 - Mo).max() <= 1e-8 * np.abs(Mo).max()
+    assert np.abs(M0 - Mo).max() <= 1e-8 * np.abs(Mo).max()
     c.close()
 
 
