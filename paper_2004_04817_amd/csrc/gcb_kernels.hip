@@ -97,11 +97,12 @@ __device__ __forceinline__ bool better(double v, int32_t i, double bv, int32_t b
     return v > bv || (v == bv && i < bi);
 }
 
-// Wave reductions (every lane of the wave active).  The first four steps pair lanes inside each row of
-// 16 with DPP lane moves (no LDS round trip): swaps within quads (xor 1, xor 2), then the half-row and
-// row mirrors; the last two pair rows 16 and 32 lanes apart.  Every step pairs each lane with a partner
-// that pairs back with it, and both combine the same two values, so all lanes end with one identical
-// result in a fixed order.
+// Wave reductions (every lane of the wave active), with no LDS round trip.  The first four steps pair
+// lanes inside each row of 16 with DPP lane moves: swaps within quads (xor 1, xor 2), then the half-row and
+// row mirrors.  The last two combine rows 16 and 32 lanes apart with the permlane swaps: swapping a value
+// with itself leaves the even and the odd rows (or the lower and the upper 32 lanes) in the two results of
+// every lane.  Every step pairs each lane with a partner that pairs back with it, and both combine the same
+// two values, so all lanes end with one identical result in a fixed order.
 constexpr int kDppXor1 = 0xB1;          // quad_perm [1, 0, 3, 2]
 constexpr int kDppXor2 = 0x4E;          // quad_perm [2, 3, 0, 1]
 constexpr int kDppHalfMirror = 0x141;   // lane i of each half row of 8 reads lane 7 - i
@@ -120,6 +121,56 @@ __device__ __forceinline__ double dpp_f64(double v) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// lo / hi: the value of the lower / upper partner (rows 16 apart with K32 = false, halves 32 apart with true)
+template <bool K32>
+__device__ __forceinline__ void swap_rows_u32(uint32_t x, uint32_t& lo, uint32_t& hi) {
+    if constexpr (K32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+        lo = r[0];
+        hi = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+        lo = r[0];
+        hi = r[1];
+    }
+}
+
+template <bool K32>
+__device__ __forceinline__ void swap_rows_f64(double x, double& lo, double& hi) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    uint32_t l0, h0, l1, h1;
+    swap_rows_u32<K32>((uint32_t)b, l0, h0);
+    swap_rows_u32<K32>((uint32_t)(b >> 32), l1, h1);
+    lo = __longlong_as_double((long long)(((uint64_t)l1 << 32) | l0));
+    hi = __longlong_as_double((long long)(((uint64_t)h1 << 32) | h0));
+}
+
+template <bool K32>
+__device__ __forceinline__ double sum_rows_f64(double v) {
+    double lo, hi;
+    swap_rows_f64<K32>(v, lo, hi);
+    return lo + hi;
+}
+
+template <bool K32>
+__device__ __forceinline__ int32_t sum_rows_i32(int32_t v) {
+    uint32_t lo, hi;
+    swap_rows_u32<K32>((uint32_t)v, lo, hi);
+    return (int32_t)(lo + hi);
+}
+
+template <bool K32>
+__device__ __forceinline__ void best_step_rows(Best& b) {
+    Best lo, hi;
+    swap_rows_f64<K32>(b.v, lo.v, hi.v);
+    uint32_t il, ih, al, ah;
+    swap_rows_u32<K32>((uint32_t)b.idx, il, ih);
+    swap_rows_u32<K32>((uint32_t)b.aux, al, ah);
+    lo.idx = (int32_t)il; hi.idx = (int32_t)ih;
+    lo.aux = (int32_t)al; hi.aux = (int32_t)ah;
+    b = better(hi.v, hi.idx, lo.v, lo.idx) ? hi : lo;
+}
+
 template <int CTRL>
 __device__ __forceinline__ void best_step_dpp(Best& b) {
     const double v = dpp_f64<CTRL>(b.v);
@@ -133,13 +184,8 @@ __device__ __forceinline__ Best wave_best(Best b) {
     best_step_dpp<kDppXor2>(b);
     best_step_dpp<kDppHalfMirror>(b);
     best_step_dpp<kDppMirror>(b);
-#pragma unroll
-    for (int off = 16; off <= 32; off <<= 1) {
-        const double v = __shfl_xor(b.v, off, 64);
-        const int32_t i = __shfl_xor(b.idx, off, 64);
-        const int32_t a = __shfl_xor(b.aux, off, 64);
-        if (better(v, i, b.v, b.idx)) { b.v = v; b.idx = i; b.aux = a; }
-    }
+    best_step_rows<false>(b);
+    best_step_rows<true>(b);
     return b;
 }
 
@@ -178,9 +224,8 @@ __device__ __forceinline__ double wave_sum(double v) {
     v += dpp_f64<kDppXor2>(v);
     v += dpp_f64<kDppHalfMirror>(v);
     v += dpp_f64<kDppMirror>(v);
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    return v;
+    v = sum_rows_f64<false>(v);
+    return sum_rows_f64<true>(v);
 }
 
 template <int NT>
@@ -201,9 +246,8 @@ __device__ __forceinline__ int32_t wave_isum(int32_t v) {
     v += dpp_i32<kDppXor2>(v);
     v += dpp_i32<kDppHalfMirror>(v);
     v += dpp_i32<kDppMirror>(v);
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    return v;
+    v = sum_rows_i32<false>(v);
+    return sum_rows_i32<true>(v);
 }
 
 __device__ Best big_block_best(Best b) { return block_best_n<kBigBlock>(b); }
