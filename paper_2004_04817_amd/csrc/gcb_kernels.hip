@@ -361,9 +361,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
     ArgRec* __restrict__ rec = A.rec;
     __shared__ double ls[6][STAGE];
     __shared__ double red[3][4][kBlock / 64];
-    __shared__ double s_e2[kBlock / 64 * 4];
-    __shared__ int32_t s_or[kBlock / 64 * 4], s_cnt[kBlock / 64 * 4];
-    __shared__ int32_t s_win, s_tot, s_n, s_done;
+    __shared__ int32_t s_n, s_done;
     const int groups = kBlock / lpt;                // target groups per block
     const int grp = threadIdx.x / lpt;
     const int gl = threadIdx.x % lpt;               // lane within the group
@@ -513,43 +511,32 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
         }
     }
     __syncthreads();
-    // one thread per (group, q): error of target tbase + q; the best is chosen on
-    // (e^2, original index) only, then its owner writes the full record
+    // Every candidate is a lane of wave 0 (at most 16 per block): one lane per (group, q) forms the error of
+    // target tbase + q, the wave takes the best on (e^2, original index) only (a total order over live
+    // candidates), and its lane writes the full record (lane 0 when the block has no live candidate).
+    if (wave != 0) return;
     double e2 = -1.0;
-    if ((int)threadIdx.x < ncand) {
+    if ((int)threadIdx.x < ncand && clive) {
         const int gq = threadIdx.x / 4, q = threadIdx.x % 4;
-        if (clive) {
-            const int wpg = lpt / 64;   // waves per group
-            double fx = 0.0, fy = 0.0, fz = 0.0;
-            for (int w = 0; w < wpg; ++w) {
-                fx += red[0][q][gq * wpg + w];
-                fy += red[1][q][gq * wpg + w];
-                fz += red[2][q][gq * wpg + w];
-            }
-            const double ex = fx - cdx, ey = fy - cdy, ez = fz - cdz;
-            e2 = fma(ez, ez, fma(ey, ey, ex * ex));
+        const int wpg = lpt / 64;   // waves per group
+        double fx = 0.0, fy = 0.0, fz = 0.0;
+        for (int w = 0; w < wpg; ++w) {
+            fx += red[0][q][gq * wpg + w];
+            fy += red[1][q][gq * wpg + w];
+            fz += red[2][q][gq * wpg + w];
         }
-        s_e2[threadIdx.x] = e2;
-        s_or[threadIdx.x] = clive ? corig : 0x7fffffff;
-        s_cnt[threadIdx.x] = clive ? 1 : 0;
+        const double ex = fx - cdx, ey = fy - cdy, ez = fz - cdz;
+        e2 = fma(ez, ez, fma(ey, ey, ex * ex));
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int bi = 0, c = s_cnt[0];
-        for (int i = 1; i < ncand; ++i) {
-            if (better(s_e2[i], s_or[i], s_e2[bi], s_or[bi])) bi = i;
-            c += s_cnt[i];
-        }
-        s_win = bi;
-        s_tot = c;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x == s_win) {
+    const int32_t orig = clive ? corig : 0x7fffffff;
+    const Best b = wave_best(Best{e2, orig, lane});
+    const int32_t tot = wave_isum(clive ? 1 : 0);
+    if (lane == (tot > 0 ? b.aux : 0)) {
         ArgRec& o = rec[bid];
         o.e2 = e2;
-        o.orig = clive ? corig : 0x7fffffff;
+        o.orig = orig;
         o.pos = t0 + ct;
-        o.count = s_tot;
+        o.count = tot;
         o.x = cx;
         o.y = cy;
         o.z = cz;
@@ -654,7 +641,7 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
     __shared__ double sl[kRowsL * RPW];
     __shared__ int32_t s_n, s_done;
     __shared__ double s_we2[kBigBlock / 64];
-    __shared__ int32_t s_wor[kBigBlock / 64], s_wri[kBigBlock / 64], s_cnt[kBigBlock / 64];
+    __shared__ int32_t s_wor[kBigBlock / 64], s_cnt[kBigBlock / 64];
     __shared__ double s_win[6];
     __shared__ int32_t s_winpos;
     __shared__ int32_t s_app;
@@ -767,29 +754,21 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
             s_cnt[wave] = c;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            int bw_ = 0;
-            int32_t total = s_cnt[0];
-            for (int w = 1; w < kBigBlock / 64; ++w) {
-                if (better(s_we2[w], s_wor[w], s_we2[bw_], s_wor[bw_])) bw_ = w;
-                total += s_cnt[w];
-            }
-            s_wri[0] = s_wor[bw_];
-            s_wri[1] = total;
-            s_we2[0] = s_we2[bw_];
-        }
-        __syncthreads();
+        // every wave reduces the per-wave bests itself (its first lanes read them), so all threads know the
+        // block's best and count with no serial pass and no further barrier
+        const bool has = lane < kBigBlock / 64;
+        const Best bb = wave_best(Best{has ? s_we2[lane] : -1.0, has ? s_wor[lane] : 0x7fffffff, 0});
+        const int32_t total = wave_isum(has ? s_cnt[lane] : 0);
         // the thread holding the winning record publishes its fields (original indices are unique)
-        if (be2 >= 0.0 && bor == s_wri[0]) {
+        if (be2 >= 0.0 && bor == bb.idx) {
             s_win[0] = bx; s_win[1] = by; s_win[2] = bz; s_win[3] = bdx; s_win[4] = bdy; s_win[5] = bdz;
             s_winpos = bpos;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            const int32_t total = s_wri[1];
             ArgRec b;
-            b.e2 = s_we2[0];
-            b.orig = s_wri[0];
+            b.e2 = bb.v;
+            b.orig = bb.idx;
             if (b.e2 >= 0.0) {
                 b.pos = s_winpos;
                 b.x = s_win[0]; b.y = s_win[1]; b.z = s_win[2];
@@ -992,7 +971,8 @@ __device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bi
         lv[u] = ok ? l[ii] : 0.0;
     }
     {
-        // fixed-order reduction: per thread in block order, xor tree per wave, waves in order
+        // fixed-order reduction: per thread in block order, a tree per wave, waves in order (thread 0 reads
+        // the 16 wave sums with independent loads)
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         if ((int)threadIdx.x < ncb) {
 #pragma unroll
