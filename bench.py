@@ -305,7 +305,7 @@ def serving_section(n_requests, dev, warmup_requests=25, rate=20.0, sat_rate=0.0
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
     import torch
     import paper_2004_04817_amd as gcb
