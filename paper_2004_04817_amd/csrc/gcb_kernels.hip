@@ -179,6 +179,8 @@ __device__ __forceinline__ void best_step_dpp(Best& b) {
     if (better(v, i, b.v, b.idx)) { b.v = v; b.idx = i; b.aux = a; }
 }
 
+// Every lane ends with the same (v, idx); aux comes with it when that pair is held by a single lane (equal
+// pairs keep the aux of whichever lane the pairing order reaches first).
 __device__ __forceinline__ Best wave_best(Best b) {
     best_step_dpp<kDppXor1>(b);
     best_step_dpp<kDppXor2>(b);
@@ -494,7 +496,7 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
             }
         }
     }
-    // sum over the lpt lanes of each target: xor tree per wave, then the waves of a group in order
+    // sum over the lpt lanes of each target: a tree per wave, then the waves of a group in order
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -876,7 +878,7 @@ __device__ __forceinline__ void factor_l_body(const FactorLArgs& A, const int bi
     __syncthreads();
     if (wave == 0) {
         // shares of b.W and l.l per chunk of kRowsL rows (chunk index i / kRowsL, whatever
-        // the rows per block), each in xor-tree order, so the sums do not depend on rpw
+        // the rows per block), each in the wave-tree order, so the sums do not depend on rpw
         for (int r = 0; r < rpw; ++r) {
             const int c0 = i0 + kRowsL * r;
             if (r > 0 && c0 >= i1) break;   // chunk 0 is always written (zeros while |S| = 0)
