@@ -989,17 +989,20 @@ __device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bi
             if (lane == 0) part[c][wave] = v[c];
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double f[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int t = 0; t < kBigBlock / 64; ++t)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) f[c] += part[c][t];
-            const double s = 1.0 - f[3];
-            s_bad = !(s > kSingularTol);
-            sh[0] = 1.0 / sqrt(s);
-            sh[1] = (r.dx - f[0]) / s;
-            sh[2] = (r.dy - f[1]) / s;
-            sh[3] = (r.dz - f[2]) / s;
+        // lanes 0..3 form 1 / sqrt(s) and the three e / s side by side (each sums the wave totals in block
+        // order, as one thread would): one sum chain, one square root and one division deep
+        if (threadIdx.x < 4) {
+            const int k = threadIdx.x;
+            const int c = k > 0 ? k - 1 : 0;
+            double fc = 0.0, f3 = 0.0;
+            for (int t = 0; t < kBigBlock / 64; ++t) {
+                fc += part[c][t];
+                f3 += part[3][t];
+            }
+            const double s = 1.0 - f3;
+            const double dk = k == 1 ? r.dx : (k == 2 ? r.dy : r.dz);
+            sh[k] = k == 0 ? 1.0 / sqrt(s) : (dk - fc) / s;
+            if (k == 0) s_bad = !(s > kSingularTol);
         }
         __syncthreads();
     }
