@@ -46,6 +46,12 @@ MUTANTS = [
      "if (v < best || (v == best && j < arg)) { best = v; arg = j; }",
      [lambda: pins.test_select_matches_brute_force_tiny(12, "2")]),
     ("start-rule-min", "double v = a < b ? a : b;", "double v = a < b ? b : a;", [pins.test_initial_nodes_rule_brute_force]),
+    ("validate-skip-check-dropped",
+     "if (n >= 0 && E > p->tol_abs + tau && st.nS < p->nc_max) { bad = it; r = 4; break; }", "(void)0;",
+     [pins.test_validate_rejects_false_skip]),
+    ("validate-termination-check-dropped",
+     "if (!(quiet == p->m || st.nS == p->nc_max)) { bad = n_iter; r = 6; }", "(void)0;",
+     [pins.test_validate_rejects_truncated_fresh_run]),
 ]
 
 

@@ -312,6 +312,59 @@ def test_validate_accepts_own_run_and_flags_planted_deviation():
     assert bad == 5 and reason == 1
 
 
+def test_validate_rejects_false_skip():
+    """Algorithm 1 appends whenever the group maximum exceeds E* and |S| <
+    Nc^max: a replayed sequence that marks such an iteration as skipped is
+    rejected there (reason 4), even with a generous tau below the margin."""
+    p = synth.config_small_ellipsoid(with_volume=False)
+    r = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed)
+    app = r.log_appended.copy()
+    # an append whose error clears E* by a wide margin (the starting iterations have E >> E*)
+    it = next(i for i in range(len(app)) if app[i] and r.log_err[i] > 10.0 * p.tol_abs)
+    app[it] = 0
+    tau = 1e-3 * p.tol_abs
+    bad, reason, _ = oracle.validate(p.xyz, p.disp, p.radius, p.m, p.tol_abs, r.S, r.log_group, r.log_node,
+                                     app, tau, seed=p.seed)
+    assert bad == it and reason == 4
+    # the same skip late in the run, where the error is only a few E*
+    late = [i for i in range(len(app)) if r.log_appended[i] and r.log_err[i] > p.tol_abs + 10 * tau]
+    it2 = late[-1]
+    app = r.log_appended.copy()
+    app[it2] = 0
+    bad, reason, _ = oracle.validate(p.xyz, p.disp, p.radius, p.m, p.tol_abs, r.S, r.log_group, r.log_node,
+                                     app, tau, seed=p.seed)
+    assert bad == it2 and reason == 4
+
+
+def test_validate_rejects_truncated_fresh_run():
+    """A fresh run ends only after m consecutive iterations without an append
+    (every group checked with one W) or at the cap: the oracle's own sequence
+    cut before its last quiet iteration is rejected at its end (reason 6),
+    and so is one cut right after an append; the whole sequence passes."""
+    p = synth.config_small_ellipsoid(with_volume=False)
+    r = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed)
+    n = len(r.log_group)
+    assert not r.log_appended[n - p.m:].any() and r.log_appended[n - p.m - 1]
+    for cut in (n - 1, n - p.m):
+        bad, reason, _ = oracle.validate(p.xyz, p.disp, p.radius, p.m, p.tol_abs, r.S, r.log_group[:cut],
+                                         r.log_node[:cut], r.log_appended[:cut], 0.0, seed=p.seed)
+        assert bad == cut and reason == 6, (cut, bad, reason)
+    bad, reason, _ = oracle.validate(p.xyz, p.disp, p.radius, p.m, p.tol_abs, r.S, r.log_group, r.log_node,
+                                     r.log_appended, 0.0, seed=p.seed)
+    assert bad == -1 and reason == 0
+    # at the cap the run may end right after an append
+    rc = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, nc_max=50, seed=p.seed)
+    nz = len(rc.log_group)
+    bad, reason, _ = oracle.validate(p.xyz, p.disp, p.radius, p.m, p.tol_abs, rc.S, rc.log_group, rc.log_node,
+                                     rc.log_appended, 0.0, nc_max=50, seed=p.seed)
+    assert bad == -1, (bad, reason)
+    last_app = int(np.flatnonzero(rc.log_appended)[-1])
+    cut = last_app   # one append short of the cap
+    bad, reason, _ = oracle.validate(p.xyz, p.disp, p.radius, p.m, p.tol_abs, rc.S, rc.log_group[:cut],
+                                     rc.log_node[:cut], rc.log_appended[:cut], 0.0, nc_max=50, seed=p.seed)
+    assert bad == cut and reason == 6 and nz > cut
+
+
 # ------------------------------------------------------------------ Table 1
 def test_table1_cost_model():
     """Table 1 (Nv = 4e6, Nb = 8e4, Nc = 2000): 5.3e9, 4.8e11, 8.0e10 and the
