@@ -111,7 +111,10 @@ int gcb_set_stream(gcb_ctx *ctx, void *hip_stream);
 int gcb_set_boundary(gcb_ctx *ctx, int64_t nb, const double *xyz, const double *disp, int mem);
 
 /* Replace the displacements of the same nodes, (nb, 3) float64.  The
- * previous selection is dropped; the next gcb_select starts afresh. */
+ * previous selection's results (its weights, gcb_deform, gcb_get_support)
+ * are unavailable until the next gcb_select.  Its support set S0 and the
+ * factor of S0 stay in the context: a gcb_select with params.warm_start = 1
+ * starts from them, one with warm_start = 0 starts afresh. */
 int gcb_set_displacement(gcb_ctx *ctx, const double *disp, int mem);
 
 /* Algorithm 1 parameters plus R (Eq. 2).  Checked against the boundary when
@@ -289,6 +292,26 @@ typedef struct gcb_server gcb_server;
 
 enum gcb_serve_flags { GCB_SERVE_BATCH = 1, GCB_SERVE_CACHE = 2 };
 
+/* What a request's selection produced, copied into caller-owned host
+ * arrays when the selection finishes (Algorithm 1's outputs S and W plus its
+ * per-iteration record, as gcb_get_support and gcb_get_log give them for a
+ * context of its own).  The copies synchronise the server's stream, so a
+ * recorded request delays the rounds that finish it: meant for verification,
+ * not for timed streams.  Arrays may be NULL; at most cap_support supports
+ * and cap_log iterations are written; nc and iterations are filled in. */
+typedef struct {
+    int64_t cap_support;     /* entries support[] (and rows of weights[]) can hold */
+    int64_t *support;        /* selected nodes, original boundary indices, selection order */
+    double *weights;         /* (cap_support, 3): W^x, W^y, W^z */
+    int64_t cap_log;         /* entries each log array can hold */
+    int32_t *log_group;      /* group k mod m of each iteration of this request's loop */
+    int64_t *log_node;       /* its argmax node (original index, -1: no candidate) */
+    double *log_err;         /* the group maximum error E */
+    int8_t *log_appended;    /* 1: the node was appended */
+    int64_t nc;              /* out: |S| */
+    int64_t iterations;      /* out: loop iterations of this request (0 for a warm start that met E*) */
+} gcb_record;
+
 typedef struct {
     int64_t mesh_key;        /* >= 0: identity of the boundary for the resident cache; -1: never kept */
     int64_t nb;              /* boundary nodes */
@@ -301,6 +324,7 @@ typedef struct {
     int32_t out_dtype;       /* GCB_F32 or GCB_F64 */
     void *out;               /* (nv, 3) of out_dtype, device memory: the displacements of Eq. (6) */
     double t_arrival;        /* arrival time on gcb_server_clock(); < 0: the time of submission */
+    gcb_record *record;      /* NULL, or host memory filled when the selection finishes (valid until done) */
 } gcb_request;
 
 typedef struct {

@@ -59,10 +59,18 @@ class SelectInfo(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Record(C.Structure):
+    _fields_ = [("cap_support", C.c_int64), ("support", C.c_void_p), ("weights", C.c_void_p),
+                ("cap_log", C.c_int64), ("log_group", C.c_void_p), ("log_node", C.c_void_p),
+                ("log_err", C.c_void_p), ("log_appended", C.c_void_p), ("nc", C.c_int64),
+                ("iterations", C.c_int64)]
+
+
 class Request(C.Structure):
     _fields_ = [("mesh_key", C.c_int64), ("nb", C.c_int64), ("xyz", C.c_void_p), ("disp", C.c_void_p),
                 ("params", Params), ("nv", C.c_int64), ("vol_xyz", C.c_void_p), ("in_dtype", C.c_int32),
-                ("out_dtype", C.c_int32), ("out", C.c_void_p), ("t_arrival", C.c_double)]
+                ("out_dtype", C.c_int32), ("out", C.c_void_p), ("t_arrival", C.c_double),
+                ("record", C.c_void_p)]
 
 
 class Result(C.Structure):
@@ -548,12 +556,14 @@ class Server:
             raise GcbError(rc, "gcb_server_create failed")
         self._h = h
         self._keep = {}
+        self._records = {}
 
     def close(self):
         if getattr(self, "_h", None):
             lib().gcb_server_destroy(self._h)
             self._h = None
             self._keep = {}
+            self._records = {}
 
     def __del__(self):
         try:
@@ -573,8 +583,10 @@ class Server:
             raise GcbError(rc, lib().gcb_server_last_error(self._h).decode())
 
     def submit(self, xyz, disp, radius, m, tol_abs, seed=0, nc_max=None, mesh_key=-1, vol=None, out=None,
-               t_arrival=-1.0) -> int:
-        """Queue a request: boundary (nb, 3) host arrays, volume and output device tensors."""
+               t_arrival=-1.0, record=False, log_cap=1 << 18) -> int:
+        """Queue a request: boundary (nb, 3) host arrays, volume and output device tensors.
+        record=True: the selection's support set, weights and per-iteration log are copied
+        out when it finishes (``result`` then holds them; the copies synchronise the stream)."""
         import torch
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         disp = np.ascontiguousarray(disp, dtype=np.float64)
@@ -604,9 +616,22 @@ class Server:
         else:
             r.in_dtype = r.out_dtype = GCB_F64
         r.t_arrival = float(t_arrival)
+        rec = None
+        if record:
+            ncap = int(r.params.nc_max)
+            arrs = {"support": np.zeros(ncap, dtype=np.int64), "weights": np.zeros((ncap, 3)),
+                    "log_group": np.zeros(log_cap, dtype=np.int32), "log_node": np.zeros(log_cap, dtype=np.int64),
+                    "log_err": np.zeros(log_cap), "log_appended": np.zeros(log_cap, dtype=np.int8)}
+            rec = Record(ncap, arrs["support"].ctypes.data, arrs["weights"].ctypes.data, int(log_cap),
+                         arrs["log_group"].ctypes.data, arrs["log_node"].ctypes.data, arrs["log_err"].ctypes.data,
+                         arrs["log_appended"].ctypes.data, 0, 0)
+            r.record = C.addressof(rec)
+            keep += [rec, arrs]
         t = C.c_int64()
         self._check(lib().gcb_server_submit(self._h, C.byref(r), C.byref(t)))
         self._keep[t.value] = keep
+        if rec is not None:
+            self._records[t.value] = (rec, arrs)
         return t.value
 
     def progress(self, iterations: int = 16) -> int:
@@ -621,8 +646,17 @@ class Server:
              "t_admit": r.t_admit,
              "t_done": r.t_done}
         d.update(r.info.as_dict())
+        if r.state == 3 and int(ticket) in self._records:
+            rec, arrs = self._records[int(ticket)]
+            nc, it = int(rec.nc), int(rec.iterations)
+            if it > len(arrs["log_group"]):
+                raise GcbError(GCB_E_INVALID, f"record log holds {len(arrs['log_group'])} of {it} iterations")
+            d["support"] = arrs["support"][:nc].copy()
+            d["weights"] = arrs["weights"][:nc].copy()
+            d["log"] = {k: arrs[k][:it].copy() for k in ("log_group", "log_node", "log_err", "log_appended")}
         if r.state == 3 or r.state < 0:
             self._keep.pop(int(ticket), None)
+            self._records.pop(int(ticket), None)
         return d
 
     def forget(self, ticket: int):

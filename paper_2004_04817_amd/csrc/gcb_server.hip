@@ -162,6 +162,24 @@ void release(gcb_server* s, Req& q) {
     q.ctx = nullptr;
 }
 
+// Copy a finished selection into the request's record (host memory; synchronises the stream).
+int fill_record(Req& q) {
+    gcb_record* rec = q.r.record;
+    if (!rec) return GCB_OK;
+    rec->nc = q.res.info.nc;
+    rec->iterations = q.res.info.iterations;
+    if (rec->cap_support >= q.res.info.nc && (rec->support || rec->weights)) {
+        const int rc = gcb_get_support(q.ctx, rec->support, rec->weights, GCB_MEM_HOST);
+        if (rc != GCB_OK) return rc;
+    }
+    if (rec->cap_log > 0 && (rec->log_group || rec->log_node || rec->log_err || rec->log_appended)) {
+        const int64_t n = gcb_get_log(q.ctx, rec->log_group, rec->log_node, rec->log_err, rec->log_appended,
+                                      rec->cap_log);
+        if (n < 0) return (int)n;
+    }
+    return GCB_OK;
+}
+
 int check_request(const gcb_request& r) {
     if (r.nb < 3 || !r.xyz || !r.disp) return GCB_E_INVALID;
     if (r.nv < 0 || (r.nv > 0 && (!r.vol_xyz || !r.out))) return GCB_E_INVALID;
@@ -238,6 +256,10 @@ bool admit_head(gcb_server* s) {
     }
     // one at a time: the plain path
     rc = gcb_select(q.ctx, &q.res.info);
+    if (rc >= 0) {
+        const int rr = fill_record(q);
+        if (rr < 0) rc = rr;
+    }
     if (rc < 0) {
         fail_request(s, q, rc);
         return true;
@@ -299,8 +321,9 @@ void step_batch(gcb_server* s, int32_t iterations) {
             still.push_back(s->selecting[i]);   // still running; the failing context is another one
             continue;
         }
-        if (rc < 0) {
-            fail_request(s, q, rc);
+        const int rr = rc >= 0 ? fill_record(q) : rc;
+        if (rr < 0) {
+            fail_request(s, q, rr);
             continue;
         }
         finished.push_back(s->selecting[i]);

@@ -70,9 +70,11 @@ def volume_pool(max_nv: int, device, dtype=None):
 
 
 def replay(server: Server, items, pool, nv_per_nb: int = 25, iterations: int = 16, time_limit: float = 600.0,
-           out_dtype=None):
+           out_dtype=None, record: bool = False):
     """Submit each request at its arrival time, drive the server until every
-    request is done, and return the Served records (with results)."""
+    request is done, and return the Served records (with results).
+    record=True asks the server for each selection's support set, weights and
+    log (verification: the copies synchronise the stream)."""
     import torch
     served = []
     start = clock() + 0.05
@@ -91,7 +93,7 @@ def replay(server: Server, items, pool, nv_per_nb: int = 25, iterations: int = 1
             vol = cloud[:nv]
             out = torch.empty((nv, 3), dtype=out_dtype or cloud.dtype, device=cloud.device)
             tk = server.submit(base.xyz, disp, base.radius, base.m, tol, seed=base.seed, mesh_key=req.key,
-                               vol=vol, out=out, t_arrival=start + req.t)
+                               vol=vol, out=out, t_arrival=start + req.t, record=record)
             served.append(Served(tk, req, base.xyz, disp, base.radius, base.m, tol, base.seed, vol, out))
             nxt += 1
             in_flight += 1

@@ -104,7 +104,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         pytest.skip("gcc not available")
     src = tmp_path / "sizes.c"
     fields = {"gcb_params": gcb.Params, "gcb_select_info": gcb.SelectInfo, "gcb_request": gcb.Request,
-              "gcb_result": gcb.Result}
+              "gcb_result": gcb.Result, "gcb_record": gcb.Record}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "gcb.h"', "int main(void) {"]
     for cname, cls in fields.items():
         lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')

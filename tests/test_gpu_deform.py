@@ -130,8 +130,10 @@ def test_wing_large_full_size():
 def test_fp32_evaluation_accuracy_and_dtypes():
     """GCB_PREC_FP32_EVAL: Eq. (6) in FP32 with FP64 chunk sums.  Its error is that
     of phi and the coordinates in FP32, amplified by the weights of the
-    ill-conditioned support system: bounded here by 1e-3 max|d| (the FP64 path
-    meets 1e-11), and FP32 in / FP64 out does not change it."""
+    ill-conditioned support system (sum condition about 195 here): measured at
+    1.2e-5 max|d| against the oracle's own selection and weights, bounded here
+    by 5e-5 max|d| (max) and 1e-5 max|d| (RMS), so that a regression shows; the
+    FP64 path meets 1e-11.  FP32 in / FP64 out does not change it."""
     torch = _torch()
     p = synth.config_small_ellipsoid(nv=20000)
     c = gcb.Context(0)
@@ -139,7 +141,9 @@ def test_fp32_evaluation_accuracy_and_dtypes():
     c.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
     c.select()
     S, W = c.get_support()
-    ref = oracle.interpolate(p.xyz[S], W, p.radius, p.volume)
+    r = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed)
+    assert np.array_equal(S, r.S)
+    ref = oracle.interpolate(p.xyz[r.S], r.W, p.radius, p.volume)
     x = torch.from_numpy(p.volume).cuda()
     o64 = c.deform(x).cpu().numpy()
     c.set_params(p.radius, p.m, p.tol_abs, seed=p.seed, precision=gcb.GCB_PREC_FP32_EVAL)
@@ -149,13 +153,14 @@ def test_fp32_evaluation_accuracy_and_dtypes():
     md = p.max_disp
     e64 = np.abs(o64 - ref).max() / md
     e32 = np.abs(o32 - ref).max() / md
-    print("FP64 eval err / max|d|:", e64, " FP32 eval err / max|d|:", e32, flush=True)
+    r32 = float(np.sqrt(((o32 - ref) ** 2).sum(axis=1).mean())) / md
+    print("FP64 eval err / max|d|:", e64, " FP32 eval err / max|d|: max", e32, "RMS", r32, flush=True)
     assert e64 <= 1e-11
-    assert e32 <= 1e-3
-    assert np.abs(o32f - ref).max() / md <= 1e-3
+    assert e32 <= 5e-5 and r32 <= 1e-5
+    assert np.abs(o32f - ref).max() / md <= 5e-5
     # support nodes: the FP32 interpolant still reproduces the field to FP32 accuracy
     o_s = c.deform(np.ascontiguousarray(p.xyz[S]))
-    assert np.abs(o_s - p.disp[S]).max() / md <= 1e-3
+    assert np.abs(o_s - p.disp[S]).max() / md <= 5e-5
     c.close()
 
 

@@ -187,7 +187,13 @@ def test_randomised_small_problems_against_the_oracle():
         print(f"case {case}: nb={nb} m={m} R={radius:.3f} tol={tol:.3e} nc_max={nc_max}", flush=True)
         r = oracle_select(p, tol_abs=tol, m=m, nc_max=nc_max)
         if r.status < 0:
-            continue   # the oracle found the support matrix singular (close nodes at a large radius)
+            # the oracle found the support matrix singular (close nodes at a large radius): the library
+            # must report the same condition, not a result
+            assert r.status == oracle.ORC_E_SINGULAR
+            with pytest.raises(gcb.GcbError) as e:
+                gpu_select(p, tol_abs=tol, m=m, nc_max=nc_max)
+            assert e.value.code == gcb.GCB_E_SINGULAR
+            continue
         ctx, info, S, W, log = gpu_select(p, tol_abs=tol, m=m, nc_max=nc_max)
         assert_same_run(p, info, S, W, log, r, tol, m, nc_max=nc_max)
         ctx.close()

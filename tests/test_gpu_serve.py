@@ -69,6 +69,77 @@ def test_served_mix_equals_alone():
         check_same(served)
 
 
+TAU_REL = 1e-9      # near-tie tolerance of the follow-mode replay, relative to max|d|
+TOL_ORACLE = 1e-9   # Eq. 6 outputs against the oracle's, relative to max|d|
+
+
+def check_against_oracle(served, n_points=2000):
+    """Every served request against the FP64 oracle (Algorithm 1 + Eq. 6 per request).
+
+    Fresh requests: the recorded support sequence equals oracle.select's, or the
+    oracle's follow-mode replay certifies every iteration of the served run.
+    Warm starts: the same against the oracle's warm start from the support set
+    the mesh kept (the served sequence of the previous request of that key).
+    Outputs: sampled Eq. 6 displacements against oracle.interpolate with the
+    oracle's weights for the served support set."""
+    import oracle
+    kept = {}
+    rng = np.random.default_rng(7)
+    stats = {"same": 0, "certified": 0, "warm": 0}
+    for s in sorted(served, key=lambda s: s.result["t_admit"]):
+        r = s.result
+        assert r["state"] == 3 and "support" in r, (s.req, r["state"])
+        S = r["support"]
+        lg = r["log"]
+        md = float(np.sqrt((s.disp ** 2).sum(axis=1)).max())
+        warm_S = kept[s.req.key] if r["warm"] else None
+        o = oracle.select(s.xyz, s.disp, s.radius, s.m, s.tol_abs, seed=s.seed, warm_S=warm_S)
+        assert r["iterations"] == len(lg["log_group"])
+        if len(o.S) == len(S) and np.array_equal(o.S, S):
+            stats["same"] += 1
+            assert o.iterations == r["iterations"], s.req
+            W = o.W
+        else:
+            bad, reason, _ = oracle.validate(s.xyz, s.disp, s.radius, s.m, s.tol_abs, S, lg["log_group"],
+                                             lg["log_node"], lg["log_appended"], TAU_REL * md, seed=s.seed,
+                                             warm_S=warm_S)
+            assert bad == -1, (s.req, bad, reason)
+            stats["certified"] += 1
+            W = oracle.solve_on_support(s.xyz, S, s.radius, s.disp)
+        stats["warm"] += int(bool(r["warm"]))
+        # the served weights are the oracle's solve on the same support set
+        assert np.abs(r["weights"] - W).max() <= 1e-7 * max(1.0, np.abs(W).max()), s.req
+        if r["kept"]:
+            kept[s.req.key] = S
+        nv = s.vol.shape[0]
+        if nv:
+            idx = np.sort(rng.choice(nv, size=min(n_points, nv), replace=False))
+            pts = s.vol[torch.from_numpy(idx).to(s.vol.device)].double().cpu().numpy()
+            ref = oracle.interpolate(s.xyz[S], W, s.radius, pts)
+            got = s.out[torch.from_numpy(idx).to(s.out.device)].double().cpu().numpy()
+            assert np.abs(got - ref).max() <= TOL_ORACLE * md, (s.req, np.abs(got - ref).max() / md)
+    return stats
+
+
+def test_served_requests_match_the_oracle():
+    """Continuous batching with resident meshes: each served selection and its Eq. 6 output
+    agree with the oracle run on that request alone (warm starts included)."""
+    items = small_stream(14, 0.4)
+    pool = serving.volume_pool(40_000, "cuda")
+    with gcb.Server(0, hbm_budget=4 << 30, max_active=8) as srv:
+        served = serving.replay(srv, items, pool, nv_per_nb=6, iterations=8, record=True)
+    stats = check_against_oracle(served)
+    assert stats["warm"] > 0 and stats["same"] + stats["certified"] == len(served), stats
+
+
+def test_one_at_a_time_matches_the_oracle():
+    items = small_stream(5, 0.0)
+    pool = serving.volume_pool(40_000, "cuda")
+    with gcb.Server(0, hbm_budget=4 << 30, max_active=1, flags=0) as srv:
+        served = serving.replay(srv, items, pool, nv_per_nb=6, record=True)
+    check_against_oracle(served)
+
+
 def test_one_at_a_time_equals_alone():
     items = small_stream(6, 0.0)
     pool = serving.volume_pool(40_000, "cuda")
