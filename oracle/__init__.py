@@ -23,7 +23,7 @@ class _Problem(C.Structure):
     _fields_ = [("nb", C.c_int64), ("xyz", C.c_void_p), ("disp", C.c_void_p), ("radius", C.c_double),
                 ("m", C.c_int32), ("seed", C.c_uint64), ("tol_abs", C.c_double), ("nc_max", C.c_int64),
                 ("group_of", C.c_void_p), ("init_idx", C.c_void_p), ("nthreads", C.c_int32),
-                ("warm_S", C.c_void_p), ("warm_n", C.c_int64)]
+                ("warm_S", C.c_void_p), ("warm_n", C.c_int64), ("per_iter", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -69,6 +69,9 @@ def load(path: str):
     L.orc_validate.restype = C.c_int64
     L.orc_validate.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                C.c_void_p, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    L.orc_validate_block.restype = C.c_int64
+    L.orc_validate_block.argtypes = [C.POINTER(_Problem), C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
+                                     C.c_void_p, C.c_double, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
     return L
 
 
@@ -201,24 +204,28 @@ class SelectResult:
     mon_rms: np.ndarray = None
 
 
-def _problem(xyz, disp, radius, m, seed, tol_abs, nc_max, group_of=None, init_idx=None, nthreads=0, warm_S=None):
+def _problem(xyz, disp, radius, m, seed, tol_abs, nc_max, group_of=None, init_idx=None, nthreads=0, warm_S=None,
+             per_iter=1):
     if warm_S is not None:
         warm_S = np.ascontiguousarray(warm_S, dtype=np.int64)
     keep = [xyz, disp, group_of, init_idx, warm_S]
     p = _Problem(xyz.shape[0], _ptr(xyz), _ptr(disp), float(radius), int(m), int(seed) & 0xFFFFFFFFFFFFFFFF,
                  float(tol_abs), int(nc_max), _ptr(group_of), _ptr(init_idx), int(nthreads),
-                 _ptr(warm_S), 0 if warm_S is None else len(warm_S))
+                 _ptr(warm_S), 0 if warm_S is None else len(warm_S), int(per_iter))
     return p, keep
 
 
 def select(xyz, disp, radius, m, tol_abs, nc_max=None, seed=0, group_of=None, init_idx=None,
-           nthreads: int = 0, log_cap: int | None = None, warm_S=None, monitor_every: int = 0) -> SelectResult:
+           nthreads: int = 0, log_cap: int | None = None, warm_S=None, monitor_every: int = 0,
+           per_iter: int = 1) -> SelectResult:
     """Algorithm 1 (GCB greedy) in FP64 with the RC solve.
 
     warm_S: a kept support set (>= 3 distinct nodes, in order) to start from
     instead of the three starting nodes; the selection ends at once when it
     already meets E* for these displacements, else the loop runs from k = len(warm_S).
-    monitor_every: record the all-node max / RMS error after every that many iterations."""
+    monitor_every: record the all-node max / RMS error after every that many iterations.
+    per_iter: nodes appended per iteration (1: Algorithm 1; p > 1: the top p of the
+    group over E*, ranked by error descending then index; log_appended holds counts)."""
     xyz, disp = _f64(xyz), _f64(disp)
     nb = xyz.shape[0]
     nc_max = nb if nc_max is None else int(nc_max)
@@ -226,7 +233,7 @@ def select(xyz, disp, radius, m, tol_abs, nc_max=None, seed=0, group_of=None, in
         group_of = np.ascontiguousarray(group_of, dtype=np.int32)
     if init_idx is not None:
         init_idx = np.ascontiguousarray(init_idx, dtype=np.int64)
-    p, keep = _problem(xyz, disp, radius, m, seed, tol_abs, nc_max, group_of, init_idx, nthreads, warm_S)
+    p, keep = _problem(xyz, disp, radius, m, seed, tol_abs, nc_max, group_of, init_idx, nthreads, warm_S, per_iter)
     if log_cap is None:
         log_cap = (nc_max + 1) * int(m) + 8
     lg = np.empty(log_cap, dtype=np.int32)
@@ -268,6 +275,30 @@ def validate(xyz, disp, radius, m, tol_abs, S_init, group, node, appended, tau, 
     gap = C.c_double(0.0)
     bad = lib().orc_validate(C.byref(p), _ptr(S_init), len(group), _ptr(group), _ptr(node), _ptr(appended),
                              float(tau), C.byref(reason), C.byref(gap))
+    del keep
+    return int(bad), int(reason.value), float(gap.value)
+
+
+def validate_block(xyz, disp, radius, m, tol_abs, S_seq, group, appended, tau, per_iter, nc_max=None, seed=0,
+                   group_of=None, init_idx=None, nthreads: int = 0):
+    """Follow-mode replay of a foreign run of the several-nodes-per-iteration variant
+    (S_seq: the whole support sequence; appended: per-iteration counts); returns
+    (first_bad or -1, reason, max_gap)."""
+    xyz, disp = _f64(xyz), _f64(disp)
+    nb = xyz.shape[0]
+    nc_max = nb if nc_max is None else int(nc_max)
+    if group_of is not None:
+        group_of = np.ascontiguousarray(group_of, dtype=np.int32)
+    if init_idx is not None:
+        init_idx = np.ascontiguousarray(init_idx, dtype=np.int64)
+    p, keep = _problem(xyz, disp, radius, m, seed, tol_abs, nc_max, group_of, init_idx, nthreads, None, per_iter)
+    S_seq = np.ascontiguousarray(S_seq, dtype=np.int64)
+    group = np.ascontiguousarray(group, dtype=np.int32)
+    appended = np.ascontiguousarray(appended, dtype=np.int8)
+    reason = C.c_int32(0)
+    gap = C.c_double(0.0)
+    bad = lib().orc_validate_block(C.byref(p), _ptr(S_seq), len(S_seq), len(group), _ptr(group), _ptr(appended),
+                                   float(tau), C.byref(reason), C.byref(gap))
     del keep
     return int(bad), int(reason.value), float(gap.value)
 

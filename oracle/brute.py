@@ -44,11 +44,17 @@ def start_nodes(xyz: np.ndarray, disp: np.ndarray) -> list[int]:
     return [n0, n1, n2]
 
 
-def gcb_brute(xyz, disp, radius, group_of, m, tol_abs, nc_max=None, init=None, warm=None):
+def gcb_brute(xyz, disp, radius, group_of, m, tol_abs, nc_max=None, init=None, warm=None, per_iter=1):
     """Algorithm 1 by brute force.  Returns (S, log) with log entries
     (k, group, node, E, appended).  warm: a kept support set to start from
     (no iteration if it already meets tol_abs at every node, else k starts
-    at len(warm))."""
+    at len(warm)).  per_iter > 1: the several-nodes-per-iteration variant
+    (block form of the peak-selection idea cited in Section 1): every node of
+    the group whose error exceeds tol_abs is ranked by (error descending, index
+    ascending) and the first per_iter of them (fewer if |S| would pass nc_max)
+    are appended; `appended` in the log is then their count."""
+    if per_iter > 1:
+        return _block_brute(xyz, disp, radius, group_of, m, tol_abs, nc_max, init, per_iter)
     xyz = np.asarray(xyz, np.float64)
     disp = np.asarray(disp, np.float64)
     nb = xyz.shape[0]
@@ -87,6 +93,41 @@ def gcb_brute(xyz, disp, radius, group_of, m, tol_abs, nc_max=None, init=None, w
         else:
             quiet += 1
         log.append((k, g, n, E, app))
+        k += 1
+        if stop or quiet >= m:
+            break
+    return S, log
+
+
+def _block_brute(xyz, disp, radius, group_of, m, tol_abs, nc_max, init, per_iter):
+    xyz = np.asarray(xyz, np.float64)
+    disp = np.asarray(disp, np.float64)
+    nb = xyz.shape[0]
+    nc_max = nb if nc_max is None else nc_max
+    S = list(start_nodes(xyz, disp) if init is None else init)
+    k, quiet, log = 3, 0, []
+    while True:
+        g = k % m
+        W = solve_weights(xyz[S], disp[S], radius)
+        cand = np.array([j for j in range(nb) if group_of[j] == g and j not in S], dtype=np.int64)
+        E, n, take, stop = 0.0, -1, [], False
+        if cand.size:
+            F = rbf_matrix(xyz[cand], xyz[S], radius) @ W
+            e = np.sqrt(((F - disp[cand]) ** 2).sum(axis=1))
+            order = np.lexsort((cand, -e))          # error descending, then index ascending
+            E, n = float(e[order[0]]), int(cand[order[0]])
+            over = [int(cand[t]) for t in order if e[t] > tol_abs]
+            if over:
+                room = nc_max - len(S)
+                if room <= 0:
+                    stop = True
+                take = over[: min(per_iter, max(room, 0))]
+        S.extend(take)
+        if take:
+            quiet = 0
+        elif not stop:
+            quiet += 1
+        log.append((k, g, n, E, len(take)))
         k += 1
         if stop or quiet >= m:
             break

@@ -241,6 +241,7 @@ static int validate_problem(const orc_problem *p) {
         free(seen);
         if (!ok) return 0;
     }
+    if (p->per_iter < 0 || p->per_iter > 64) return 0;
     if (p->init_idx) {
         for (int t = 0; t < 3; ++t)
             if (p->init_idx[t] < 0 || p->init_idx[t] >= p->nb) return 0;
@@ -350,6 +351,37 @@ static void group_argmax(const orc_state *st, int32_t g, double *E, int64_t *n) 
     *n = arg;
 }
 
+/* The several-nodes-per-iteration rule: the nodes of G_g \ S whose error
+ * exceeds tol, ranked by (error descending, node index ascending).  Returns
+ * a malloc'd array of *count node indices. */
+typedef struct {
+    double e;
+    int64_t j;
+} orc_cand;
+
+static int cand_order(const void *a, const void *b) {
+    const orc_cand *x = (const orc_cand *)a, *y = (const orc_cand *)b;
+    if (x->e > y->e) return -1;
+    if (x->e < y->e) return 1;
+    return x->j < y->j ? -1 : (x->j > y->j ? 1 : 0);
+}
+
+static orc_cand *group_ranking(const orc_state *st, int32_t g, double tol, int64_t *count) {
+    int64_t lo = st->goff[g], hi = st->goff[g + 1];
+    orc_cand *c = (orc_cand *)malloc(sizeof(orc_cand) * (size_t)(hi > lo ? hi - lo : 1));
+    int64_t n = 0;
+    for (int64_t t = lo; t < hi; ++t) {
+        double v = st->e[t - lo];
+        if (v < 0.0 || !(v > tol)) continue;
+        c[n].e = v;
+        c[n].j = st->members[t];
+        n++;
+    }
+    qsort(c, (size_t)n, sizeof(orc_cand), cand_order);
+    *count = n;
+    return c;
+}
+
 static int start_support(orc_state *st) {
     const orc_problem *p = st->p;
     int64_t init[3];
@@ -439,20 +471,47 @@ int orc_select(const orc_problem *p, int64_t *S_out, double *W_out, orc_log *log
         (void)gsize;
         int8_t app = 0;
         int stop = 0;
-        if (n >= 0 && E > p->tol_abs) {
-            if (st.nS < p->nc_max) {
-                double tb = now_s();
-                info->pairs_append += (uint64_t)st.nS;
-                rc = state_append(&st, n);
-                info->t_solve += now_s() - tb;
-                if (rc != ORC_OK) { status = rc; info->singular_node = n; stop = 1; }
-                else { app = 1; quiet = 0; }
+        if (p->per_iter <= 1) {
+            if (n >= 0 && E > p->tol_abs) {
+                if (st.nS < p->nc_max) {
+                    double tb = now_s();
+                    info->pairs_append += (uint64_t)st.nS;
+                    rc = state_append(&st, n);
+                    info->t_solve += now_s() - tb;
+                    if (rc != ORC_OK) { status = rc; info->singular_node = n; stop = 1; }
+                    else { app = 1; quiet = 0; }
+                } else {
+                    status = ORC_NOT_CONVERGED;
+                    stop = 1;
+                }
             } else {
-                status = ORC_NOT_CONVERGED;
-                stop = 1;
+                quiet++;
             }
         } else {
-            quiet++;
+            /* several nodes per iteration: the top per_iter nodes over E*, appended in rank order */
+            int64_t over = 0;
+            orc_cand *c = group_ranking(&st, g, p->tol_abs, &over);
+            if (over > 0) {
+                if (st.nS < p->nc_max) {
+                    int64_t q = over < p->per_iter ? over : p->per_iter;
+                    if (q > p->nc_max - st.nS) q = p->nc_max - st.nS;
+                    double tb = now_s();
+                    for (int64_t t = 0; t < q && !stop; ++t) {
+                        info->pairs_append += (uint64_t)st.nS;
+                        rc = state_append(&st, c[t].j);
+                        if (rc != ORC_OK) { status = rc; info->singular_node = c[t].j; stop = 1; }
+                        else app++;
+                    }
+                    info->t_solve += now_s() - tb;
+                    quiet = 0;
+                } else {
+                    status = ORC_NOT_CONVERGED;
+                    stop = 1;
+                }
+            } else {
+                quiet++;
+            }
+            free(c);
         }
         int64_t it = k - k0;
         if (log && it < log->cap) {
@@ -605,6 +664,80 @@ int64_t orc_validate(const orc_problem *p, const int64_t S_init[3], int64_t n_it
     if (bad < 0) {
         /* the run must end after m quiet iterations or at the cap */
         if (!(quiet == p->m || st.nS == p->nc_max)) { bad = n_iter; r = 6; }
+    }
+    if (reason) *reason = r;
+    if (max_gap) *max_gap = gap_max;
+    state_free(&st);
+    return bad;
+}
+
+/* ------------------------------------------------------------------ follow-mode replay, several nodes per iteration */
+int64_t orc_validate_block(const orc_problem *p, const int64_t *S_seq, int64_t n_S, int64_t n_iter,
+                           const int32_t *group, const int8_t *appended, double tau, int32_t *reason,
+                           double *max_gap) {
+    int32_t r = 0;
+    double gap_max = 0.0;
+    int64_t bad = -1;
+    if (!validate_problem(p) || p->warm_n != 0 || n_S < 3) { if (reason) *reason = 1; return 0; }
+    const int64_t pm = p->per_iter > 1 ? p->per_iter : 1;
+    orc_state st;
+    state_init(&st, p);
+    int64_t init[3];
+    orc_initial_nodes(p->nb, p->xyz, p->disp, init);
+    if (p->init_idx) { init[0] = p->init_idx[0]; init[1] = p->init_idx[1]; init[2] = p->init_idx[2]; }
+    if (S_seq[0] != init[0] || S_seq[1] != init[1] || S_seq[2] != init[2]) {
+        if (reason) *reason = 2;
+        state_free(&st);
+        return 0;
+    }
+    if (start_support(&st) != ORC_OK) { if (reason) *reason = 5; state_free(&st); return 0; }
+    int64_t used = 3, quiet = 0;
+    for (int64_t it = 0; it < n_iter && bad < 0; ++it) {
+        int64_t k = it + 3;
+        int32_t g = (int32_t)(k % p->m);
+        if (group[it] != g) { bad = it; r = 1; break; }
+        group_errors(&st, g, p->nthreads);
+        /* every candidate ranked (tol = -1 keeps them all), and the counts the rule gives at E* +- tau */
+        int64_t nall = 0;
+        orc_cand *c = group_ranking(&st, g, -1.0, &nall);
+        int64_t hi = 0, lo = 0;
+        for (int64_t t = 0; t < nall; ++t) {
+            if (c[t].e > p->tol_abs + tau) hi++;
+            if (c[t].e > p->tol_abs - tau) lo++;
+        }
+        const int64_t room = p->nc_max - st.nS;
+        int64_t qmin = hi < pm ? hi : pm, qmax = lo < pm ? lo : pm;
+        if (qmin > room) qmin = room;
+        if (qmax > room) qmax = room;
+        if (qmin < 0) qmin = 0;
+        if (qmax < 0) qmax = 0;
+        int64_t q = appended[it];
+        if (q < qmin || q > qmax) { bad = it; r = 4; free(c); break; }
+        if (used + q > n_S) { bad = it; r = 7; free(c); break; }
+        for (int64_t t = 0; t < q && bad < 0; ++t) {
+            int64_t j = S_seq[used + t];
+            if (j < 0 || j >= p->nb || st.group_of[j] != g || st.in_S[j]) { bad = it; r = 2; break; }
+            double ej = -1.0;
+            for (int64_t u = 0; u < nall; ++u)
+                if (c[u].j == j) ej = c[u].e;
+            /* the t-th appended node against the t-th largest error of the sweep */
+            double gap = c[t].e - ej;
+            if (gap > gap_max) gap_max = gap;
+            if (gap > tau) { bad = it; r = 3; break; }
+            if (!(ej > p->tol_abs - tau)) { bad = it; r = 4; break; }
+        }
+        free(c);
+        if (bad >= 0) break;
+        for (int64_t t = 0; t < q; ++t)
+            if (state_append(&st, S_seq[used + t]) != ORC_OK) { bad = it; r = 5; break; }
+        if (bad >= 0) break;
+        used += q;
+        if (q > 0) quiet = 0;
+        else quiet++;
+    }
+    if (bad < 0) {
+        if (used != n_S) { bad = n_iter; r = 7; }
+        else if (!(st.nS == p->nc_max || quiet == p->m)) { bad = n_iter; r = 6; }
     }
     if (reason) *reason = r;
     if (max_gap) *max_gap = gap_max;

@@ -78,6 +78,15 @@ typedef struct {
      * the loop of Algorithm 1 runs from k = warm_n.  init_idx is ignored. */
     const int64_t *warm_S;
     int64_t warm_n;
+    /* Nodes appended per iteration (0 or 1: Algorithm 1).  per_iter = p > 1 is
+     * the several-nodes-per-iteration variant, a block form of the peak-
+     * selection idea the paper cites in Section 1 (not Algorithm 1): every
+     * node of G_i \ S whose error exceeds E* is ranked by (error descending,
+     * index ascending) and the first p of them are appended in that order
+     * (fewer when |S| reaches nc_max), all ranked on the errors of one sweep.
+     * An iteration with no such node is quiet; the stopping rule is unchanged.
+     * 1 <= p <= 64. */
+    int32_t per_iter;
 } orc_problem;
 
 typedef struct {
@@ -96,7 +105,9 @@ typedef struct {
 } orc_info;
 
 /* Per-iteration record: arrays of length cap; the first min(iterations, cap)
- * entries are written.  Any pointer may be NULL. */
+ * entries are written.  Any pointer may be NULL.  With per_iter = p > 1,
+ * appended[it] is the number of nodes the iteration appended (the nodes are
+ * the next entries of S), node[it] / err[it] still the group maximum. */
 typedef struct {
     int64_t cap;
     int32_t *group;           /* i = k mod m */
@@ -146,6 +157,20 @@ int orc_inverse_factor(int64_t nb, const double *xyz, const int64_t *S, int64_t 
 int64_t orc_validate(const orc_problem *p, const int64_t S_init[3], int64_t n_iter,
                      const int32_t *group, const int64_t *node, const int8_t *appended,
                      double tau, int32_t *reason, double *max_gap);
+
+/* Follow-mode replay of a foreign run of the several-nodes-per-iteration
+ * variant (per_iter = p; p = 1 is Algorithm 1): S_seq[0..n_S) is the foreign
+ * support sequence (the three starting nodes, then every appended node in
+ * order), appended[it] the count appended at iteration it.  At every
+ * iteration: the group is k mod m; the count lies between the counts the
+ * rule gives with E* + tau and with E* - tau; the t-th appended node lies in
+ * G_i \ S and its error is >= (the t-th largest error) - tau and > E* - tau;
+ * then the foreign nodes are appended.  Termination as in orc_validate.
+ * Returns -1 or the first bad iteration; reasons as in orc_validate, plus
+ * 7 (the appended counts do not add up to n_S). */
+int64_t orc_validate_block(const orc_problem *p, const int64_t *S_seq, int64_t n_S, int64_t n_iter,
+                           const int32_t *group, const int8_t *appended, double tau, int32_t *reason,
+                           double *max_gap);
 
 #ifdef __cplusplus
 }

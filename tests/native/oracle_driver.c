@@ -69,6 +69,17 @@ int main(void) {
     for (int64_t t = 0; t < n; ++t)   /* Eq. 3 at the supports */
         for (int c = 0; c < 3; ++c) emax = fmax(emax, fabs(F[3 * S[t] + c] - disp[3 * S[t] + c]));
     if (emax > 1e-10) { fprintf(stderr, "interpolation condition violated: %g\n", emax); return 1; }
+    /* several nodes per iteration, and its block replay */
+    orc_problem b = p;
+    b.per_iter = 4;
+    int64_t *S3 = malloc(sizeof(int64_t) * nb);
+    double *W3 = malloc(sizeof(double) * 3 * nb);
+    orc_info info3;
+    rc = orc_select(&b, S3, W3, &lg, &info3);
+    if (rc < 0) { fprintf(stderr, "block select failed %d\n", rc); return 1; }
+    bad = orc_validate_block(&b, S3, info3.nc, info3.iterations, lg.group, lg.appended, 1e-12, &reason, &gap);
+    if (bad != -1) { fprintf(stderr, "block replay failed at %ld (%d)\n", (long)bad, reason); return 1; }
+    free(S3); free(W3);
     int32_t *g = malloc(sizeof(int32_t) * nb);
     orc_partition(nb, 7, 99, g);
     printf("ok nc=%ld iterations=%ld warm_iterations=%ld\n", (long)info.nc, (long)info.iterations,

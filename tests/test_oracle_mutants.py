@@ -8,6 +8,7 @@ import subprocess
 import pytest
 
 import oracle
+from tests import test_oracle_block as blk
 from tests import test_oracle_pins as pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "gcb_oracle.c")
@@ -46,6 +47,13 @@ MUTANTS = [
      "if (v < best || (v == best && j < arg)) { best = v; arg = j; }",
      [lambda: pins.test_select_matches_brute_force_tiny(12, "2")]),
     ("start-rule-min", "double v = a < b ? a : b;", "double v = a < b ? b : a;", [pins.test_initial_nodes_rule_brute_force]),
+    ("block-rank-ascending", "if (x->e > y->e) return -1;\n    if (x->e < y->e) return 1;",
+     "if (x->e > y->e) return 1;\n    if (x->e < y->e) return -1;",
+     [lambda: blk.test_block_select_matches_brute_force_tiny(12, 2, 3, 0.0)]),
+    ("block-count-uncapped", "int64_t q = over < p->per_iter ? over : p->per_iter;", "int64_t q = over;",
+     [lambda: blk.test_block_select_matches_brute_force_tiny(12, 2, 2, 0.0)]),
+    ("block-candidates-below-tolerance", "if (v < 0.0 || !(v > tol)) continue;", "if (v < 0.0) continue;",
+     [lambda: blk.test_block_select_matches_brute_force_tiny(16, 2, 3, 0.05)]),
     ("validate-skip-check-dropped",
      "if (n >= 0 && E > p->tol_abs + tau && st.nS < p->nc_max) { bad = it; r = 4; break; }", "(void)0;",
      [pins.test_validate_rejects_false_skip]),
