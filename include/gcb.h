@@ -167,6 +167,26 @@ int64_t gcb_get_log(gcb_ctx *ctx, int32_t *group, int64_t *node, double *err, in
  * context.  nv = 0 is a no-op.  Requires a finished gcb_select. */
 int gcb_deform(gcb_ctx *ctx, int64_t nv, const void *xyz, int in_dtype, void *out, int out_dtype, int mem);
 
+/* Largest support count gcb_deform_noalloc accepts. */
+#define GCB_NOALLOC_MAX_SUPPORTS 8192
+
+/* Allocation-free form of gcb_deform, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops or harnesses
+ * that forbid hipMalloc).  Same result as gcb_deform with mem =
+ * GCB_MEM_DEVICE, bitwise: the same kernels, in the context's precision.
+ * xyz (nv, 3) of in_dtype and out (nv, 3) of out_dtype are device memory on
+ * the context's device, owned by the caller.  The per-call support table
+ * (FP64: 32 bytes per support; FP32 evaluation: 24 bytes) is kept in one
+ * static device array of GCB_NOALLOC_MAX_SUPPORTS entries per GPU (256 KiB,
+ * held until the process ends) instead of context buffers: the call makes
+ * no device allocation, copy or event.  Every call on one GPU shares that
+ * array, so calls that overlap on one GPU (other contexts, other streams)
+ * race.  Returns GCB_E_INVALID when the selection has more than
+ * GCB_NOALLOC_MAX_SUPPORTS supports (gcb_deform has no such limit),
+ * GCB_E_STATE without a finished selection.  gcb_deform_time does not time
+ * it.  nv = 0 is a no-op. */
+int gcb_deform_noalloc(gcb_ctx *ctx, int64_t nv, const void *xyz, int in_dtype, void *out, int out_dtype);
+
 /* Device time (*ms, milliseconds) of the kernels of the last gcb_deform,
  * between two events on the context's stream (host copies excluded; not
  * recorded while the stream is being captured).  Waits for the second event.

@@ -35,7 +35,9 @@ EXPORTS = ["gcb_version", "gcb_partition", "gcb_create", "gcb_destroy", "gcb_las
            "gcb_batch_end", "gcb_select_batch", "gcb_deform_batch", "gcb_batch_set_layout",
            "gcb_server_clock", "gcb_server_create", "gcb_server_destroy", "gcb_server_last_error",
            "gcb_server_submit", "gcb_server_progress", "gcb_server_result", "gcb_server_forget",
-           "gcb_server_memory", "gcb_deform_time"]
+           "gcb_server_memory", "gcb_deform_time", "gcb_deform_noalloc"]
+
+GCB_NOALLOC_MAX_SUPPORTS = 8192
 
 
 class GcbError(RuntimeError):
@@ -115,6 +117,7 @@ def lib():
         L.gcb_get_log.argtypes = [vp, vp, vp, vp, vp, i64]
         L.gcb_get_log.restype = i64
         L.gcb_deform.argtypes = [vp, i64, vp, C.c_int, vp, C.c_int, C.c_int]
+        L.gcb_deform_noalloc.argtypes = [vp, i64, vp, C.c_int, vp, C.c_int]
         L.gcb_deform_multi.argtypes = [vp, i32, vp, i64, vp, C.c_int, vp, C.c_int, C.c_int]
         L.gcb_certify.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.gcb_set_support.argtypes = [vp, vp, i64, C.c_int, C.POINTER(SelectInfo)]
@@ -346,6 +349,23 @@ class Context:
         nv = int(kx.shape[0])
         self.use_current_stream(kx)
         self._check(lib().gcb_deform(self._h, nv, px, in_dt, po, out_dt, mx))
+        return out
+
+    def deform_noalloc(self, xyz, out):
+        """Eq. (6) through the allocation-free entry point: xyz (nv, 3) and out
+        (nv, 3) are device tensors on the context's device, allocated by the
+        caller; the library allocates nothing."""
+        import torch
+        if not (_is_tensor(xyz) and _is_tensor(out) and xyz.is_cuda and out.is_cuda):
+            raise ValueError("deform_noalloc takes device tensors for xyz and out")
+        in_dt = GCB_F64 if xyz.dtype == torch.float64 else GCB_F32
+        out_dt = GCB_F64 if out.dtype == torch.float64 else GCB_F32
+        px, _, kx = _arg(xyz, np.float64 if in_dt == GCB_F64 else np.float32)
+        po, _, ko = _arg(out, np.float64 if out_dt == GCB_F64 else np.float32)
+        if kx.dim() != 2 or kx.shape[1] != 3 or tuple(ko.shape) != tuple(kx.shape):
+            raise ValueError("xyz and out must have the same shape (nv, 3)")
+        self.use_current_stream(kx)
+        self._check(lib().gcb_deform_noalloc(self._h, int(kx.shape[0]), px, in_dt, po, out_dt))
         return out
 
     def deform_time(self) -> float:

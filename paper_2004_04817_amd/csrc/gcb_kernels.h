@@ -166,5 +166,13 @@ void launch_volume32(hipStream_t s, int64_t nv, const void* xyz, int in_f64, dou
 // FP64 Eq. (6); the volume table is refreshed first (sp.qx..qq must hold sp.cap doubles).
 void launch_volume(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,
                    void* out, int out_f64);
+// Allocation-free Eq. (6): the refreshed support table (FP64) or support copies (FP32 evaluation) go
+// into the module's static scratch array at scratch_ptr (n <= GCB_NOALLOC_MAX_SUPPORTS).
+void launch_volume_noalloc(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp,
+                           int n, void* out, int out_f64, int fp32_eval, void* scratch_ptr);
+// Look up, once per device and with that device current, the device address of the static scratch
+// array; noalloc_scratch returns it (nullptr before the set-up).
+hipError_t noalloc_setup(int device);
+void* noalloc_scratch(int device);
 
 }  // namespace gcb

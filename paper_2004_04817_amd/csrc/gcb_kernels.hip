@@ -8,6 +8,7 @@
 #include "gcb_device.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace gcb {
 
@@ -1616,32 +1617,85 @@ static void vol(hipStream_t s, int64_t nv, const void* xyz, double inv_r, Suppor
 }
 
 template <typename TIn, typename TOut>
-static void vol32(hipStream_t s, int64_t nv, const void* xyz, double inv_r, const Support& sp, int n, void* out) {
+static void vol32(hipStream_t s, int64_t nv, const void* xyz, double inv_r, float* const f[6], int n, void* out) {
     const unsigned g = (unsigned)((nv + kBlock - 1) / kBlock);
-    GCB_LAUNCH((k_volume32<TIn, TOut>), dim3(g), dim3(kBlock), s, nv, (const TIn*)xyz, inv_r, n, sp.fsx, sp.fsy,
-               sp.fsz, sp.fwx, sp.fwy, sp.fwz, (TOut*)out);
+    GCB_LAUNCH((k_volume32<TIn, TOut>), dim3(g), dim3(kBlock), s, nv, (const TIn*)xyz, inv_r, n, f[0], f[1], f[2],
+               f[3], f[4], f[5], (TOut*)out);
 }
 
-void launch_volume32(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,
-                     void* out, int out_f64) {
+// FP32 evaluation with the FP32 copies of the supports in f[0..5] (x, y, z, wx, wy, wz; n floats each).
+static void volume32_into(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, SupportView sv,
+                          float* const f[6], int n, void* out, int out_f64) {
     if (n > 0)
-        GCB_LAUNCH(k_support_f32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), s, n, view(sp), sp.fsx,
-                   sp.fsy, sp.fsz, sp.fwx, sp.fwy, sp.fwz);
-    if (in_f64 && out_f64) vol32<double, double>(s, nv, xyz, inv_r, sp, n, out);
-    else if (in_f64) vol32<double, float>(s, nv, xyz, inv_r, sp, n, out);
-    else if (out_f64) vol32<float, double>(s, nv, xyz, inv_r, sp, n, out);
-    else vol32<float, float>(s, nv, xyz, inv_r, sp, n, out);
+        GCB_LAUNCH(k_support_f32, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), s, n, sv, f[0], f[1],
+                   f[2], f[3], f[4], f[5]);
+    if (in_f64 && out_f64) vol32<double, double>(s, nv, xyz, inv_r, f, n, out);
+    else if (in_f64) vol32<double, float>(s, nv, xyz, inv_r, f, n, out);
+    else if (out_f64) vol32<float, double>(s, nv, xyz, inv_r, f, n, out);
+    else vol32<float, float>(s, nv, xyz, inv_r, f, n, out);
 }
 
-void launch_volume(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,
-                   void* out, int out_f64) {
-    SupportView sv = view(sp);
-    VolTable vt = vtable(sp);
+// FP64 evaluation with the support table in vt (four arrays of at least n doubles).
+static void volume64_into(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, SupportView sv,
+                          VolTable vt, int n, void* out, int out_f64) {
     if (n > 0) GCB_LAUNCH(k_volume_table, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), s, n, sv, vt);
     if (in_f64 && out_f64) vol<double, double>(s, nv, xyz, inv_r, sv, vt, n, out);
     else if (in_f64) vol<double, float>(s, nv, xyz, inv_r, sv, vt, n, out);
     else if (out_f64) vol<float, double>(s, nv, xyz, inv_r, sv, vt, n, out);
     else vol<float, float>(s, nv, xyz, inv_r, sv, vt, n, out);
+}
+
+void launch_volume32(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,
+                     void* out, int out_f64) {
+    float* const f[6] = {sp.fsx, sp.fsy, sp.fsz, sp.fwx, sp.fwy, sp.fwz};
+    volume32_into(s, nv, xyz, in_f64, inv_r, view(sp), f, n, out, out_f64);
+}
+
+void launch_volume(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,
+                   void* out, int out_f64) {
+    volume64_into(s, nv, xyz, in_f64, inv_r, view(sp), vtable(sp), n, out, out_f64);
+}
+
+// ---------------------------------------------------------------- allocation-free deformation
+// The support table of the FP64 sweep (four arrays of kNoAllocSupports doubles) or the FP32 copies
+// of the supports (six arrays of kNoAllocSupports floats) live in this static array instead of in
+// context buffers.  Every GPU holds one copy until the process ends; every call on that GPU shares
+// it, so calls that overlap on one GPU race.  Both tables are written in full (entries 0..n-1)
+// before the sweep reads them, so nothing needs clearing between calls.
+constexpr int kNoAllocSupports = GCB_NOALLOC_MAX_SUPPORTS;
+static __device__ __align__(256) double scratch[4 * kNoAllocSupports];
+
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_ptr;   // device address of `scratch`, per device
+
+hipError_t noalloc_setup(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= device) g_scratch_ptr.resize((size_t)device + 1, nullptr);
+    if (g_scratch_ptr[(size_t)device]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));   // `device` is current
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[(size_t)device] = ptr;
+    return hipSuccess;
+}
+
+void* noalloc_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return device >= 0 && device < (int)g_scratch_ptr.size() ? g_scratch_ptr[(size_t)device] : nullptr;
+}
+
+void launch_volume_noalloc(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp,
+                           int n, void* out, int out_f64, int fp32_eval, void* scratch_ptr) {
+    if (fp32_eval) {
+        float* base = static_cast<float*>(scratch_ptr);
+        float* const f[6] = {base, base + kNoAllocSupports, base + 2 * kNoAllocSupports,
+                             base + 3 * kNoAllocSupports, base + 4 * kNoAllocSupports, base + 5 * kNoAllocSupports};
+        volume32_into(s, nv, xyz, in_f64, inv_r, view(sp), f, n, out, out_f64);
+    } else {
+        double* base = static_cast<double*>(scratch_ptr);
+        const VolTable vt{base, base + kNoAllocSupports, base + 2 * kNoAllocSupports, base + 3 * kNoAllocSupports};
+        volume64_into(s, nv, xyz, in_f64, inv_r, view(sp), vt, n, out, out_f64);
+    }
 }
 
 }  // namespace gcb

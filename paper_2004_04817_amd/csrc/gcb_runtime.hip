@@ -934,6 +934,13 @@ int gcb_create(gcb_ctx** out, int device, void* hip_stream) {
         delete ctx;
         return GCB_E_DEVICE;
     }
+    if (e == hipSuccess) e = noalloc_setup(device);   // the scratch address for gcb_deform_noalloc
+    if (e != hipSuccess) {
+        g_create_err = std::string("hip setup: ") + hipGetErrorString(e);
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+        delete ctx;
+        return GCB_E_DEVICE;
+    }
     ctx->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->own_stream;
     *out = ctx;
     return GCB_OK;
@@ -1191,6 +1198,30 @@ int gcb_deform(gcb_ctx* ctx, int64_t nv, const void* xyz, int in_dtype, void* ou
             HIPCHK(ctx, hipMemcpyAsync(out, dout, out_b, hipMemcpyDeviceToHost, ctx->stream));
             sync(ctx);
         }
+        return GCB_OK;
+    });
+}
+
+int gcb_deform_noalloc(gcb_ctx* ctx, int64_t nv, const void* xyz, int in_dtype, void* out, int out_dtype) {
+    return guard(ctx, [&] {
+        if (!ctx->selected) fail(ctx, GCB_E_STATE, "no finished selection");
+        if (nv < 0) fail(ctx, GCB_E_INVALID, "nv < 0");
+        if (nv == 0) return GCB_OK;
+        if (!xyz || !out) fail(ctx, GCB_E_INVALID, "NULL xyz or out");
+        if ((in_dtype != GCB_F32 && in_dtype != GCB_F64) || (out_dtype != GCB_F32 && out_dtype != GCB_F64))
+            fail(ctx, GCB_E_INVALID, "dtype must be GCB_F32 or GCB_F64");
+        const int64_t n = ctx->info.nc;
+        if (n > GCB_NOALLOC_MAX_SUPPORTS)
+            fail(ctx, GCB_E_INVALID,
+                 "the selection has " + std::to_string(n) + " supports, more than the allocation-free maximum of " +
+                     std::to_string(GCB_NOALLOC_MAX_SUPPORTS) + " (gcb_deform has no such limit)");
+        void* scr = noalloc_scratch(ctx->device);
+        if (!scr) fail(ctx, GCB_E_DEVICE, "no scratch address for this device");
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        ctx->deform_timed = false;   // no events are recorded here
+        launch_volume_noalloc(ctx->stream, nv, xyz, in_dtype == GCB_F64, ctx->bd.inv_r, ctx->sp, (int)n, out,
+                              out_dtype == GCB_F64, ctx->params.precision == GCB_PREC_FP32_EVAL, scr);
+        HIPCHK(ctx, hipGetLastError());
         return GCB_OK;
     });
 }
