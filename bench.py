@@ -3,13 +3,14 @@
 
 One step = the whole hot path over one synthetic input: the GCB greedy
 selection (partition and staging, group sweeps, argmax, FP64 inverse-factor
-appends, FP64 all-node certificate) on the 80,000-node wing at m = 107, then
-the volume deformation (Eq. 6) of 3,000,000 graded volume points.  Inputs are
-resident in HBM before the timed region.
+appends, FP64 all-node certificate) on the 300,000-node wing at m = 399, then
+the volume deformation (Eq. 6) of 20,000,000 graded volume points.  Inputs are
+resident in HBM before the timed region.  The 80,000-node wing with 3,000,000
+points is measured the same way as a section of the same line.
 
 Prints ONE JSON line: metric, value (pair-evals/s over greedy + volume), the
-roofline of the dominant kernel, and the FP64 CPU oracle timed on the host
-cores as a baseline.
+roofline of the dominant kernel and of every kernel of the step, and the FP64
+CPU oracle timed on the host cores as a baseline.
 """
 from __future__ import annotations
 
@@ -25,7 +26,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector (256 CU x 64 lanes x 2 flop x 2.4 GHz)
+FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (packed FP32 counted)
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FLOPS_PER_PAIR = 21            # canonical: 3 sub, 5 for r^2, 1 sqrt, 1 clamp, 5 for phi, 3 FMA (x2)
+KERNEL_SRC = os.path.join(ROOT, "paper_2004_04817_amd", "csrc", "gcb_kernels.hip")
 
 
 def parse():
@@ -33,7 +37,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="wing", choices=["wing", "small", "wing-large"])
+    ap.add_argument("--config", default="wing-large", choices=["wing", "small", "wing-large"],
+                    help="headline workload (default: the 300,000-node wing with 20,000,000 points)")
+    ap.add_argument("--no-wing80k", dest="wing80k", action="store_false",
+                    help="skip the 80,000-node wing section (its step, modes and m-sweep)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-volume", type=int, default=3_000_000,
                     help="volume points in the oracle's timed sample")
@@ -41,10 +48,10 @@ def parse():
                     help="also time Eq. 6 for this many deformation modes on the wing supports (0: skip)")
     ap.add_argument("--surfaces", type=int, default=32,
                     help="also time this many uneven independent surfaces, batched vs one at a time (0: skip)")
-    ap.add_argument("--requests", type=int, default=250,
+    ap.add_argument("--requests", type=int, default=650,
                     help="also replay a Poisson stream of this many deformation requests (20 req/s), served "
                          "with continuous batching and resident meshes vs one at a time (0: skip)")
-    ap.add_argument("--warmup-requests", type=int, default=25,
+    ap.add_argument("--warmup-requests", type=int, default=50,
                     help="requests at the start of the stream left out of the latency percentiles")
     ap.add_argument("--saturation-rate", type=float, default=80.0,
                     help="also replay the stream at this arrival rate (req/s), above one-at-a-time capacity (0: skip)")
@@ -59,11 +66,17 @@ def parse():
 
 
 def kernel_source_hash(kernel_src: str) -> str:
-    """sha256 prefix of the volume kernel's sources (the kernel file and its device header)."""
+    """sha256 prefix of the kernels' code (the kernel file and its device header) with comments and blank lines
+    left out, so that counters stay attached to the code they were taken on."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in (kernel_src, os.path.join(os.path.dirname(kernel_src), "gcb_device.h")):
-        h.update(open(f, "rb").read())
+        text = open(f).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(l.rstrip() for l in text.splitlines() if l.strip())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 
@@ -80,12 +93,6 @@ def profile_values(name: str, kernel_src: str, keys: tuple) -> dict | None:
     if vals.get("kernel_source_sha256_prefix", "") != kernel_source_hash(kernel_src):
         return None
     return vals
-
-
-def measured_traffic(kernel_src: str) -> float | None:
-    """Per-launch HBM bytes of the volume sweep (FETCH_SIZE + WRITE_SIZE, calibrated)."""
-    vals = profile_values("volume_wing80k_traffic.md", kernel_src, ("traffic_bytes_per_launch:",))
-    return float(vals["traffic_bytes_per_launch"]) if vals else None
 
 
 def measured_valu(kernel_src: str) -> dict | None:
@@ -269,10 +276,60 @@ def multi_surface(count, dev, vs_oracle=False):
     return res
 
 
-def serving_section(n_requests, dev, warmup_requests=25, rate=20.0, sat_rate=0.0):
+def serving_vs_oracle(served, n_points=2000, tau_rel=1e-9):
+    """Served requests against the FP64 oracle run on each request alone (Algorithm 1 + Eq. 6): the recorded
+    support sequence equal to the oracle's (warm starts: the oracle's warm start from the set the mesh kept),
+    else certified by the oracle's follow-mode replay; sampled Eq. 6 outputs against the oracle's weights on the
+    served support set."""
+    import torch
+    import oracle
+    kept = {}
+    rng = np.random.default_rng(7)
+    res = {"requests": 0, "warm": 0, "same_sequence": 0, "certified": 0, "not_certified": 0,
+           "points_per_request": n_points, "max_err_rel_max_d": 0.0, "rms_err_rel_max_d": 0.0}
+    sq, cnt = 0.0, 0
+    for s in sorted(served, key=lambda s: s.result["t_admit"]):
+        r = s.result
+        if r["state"] != 3 or "support" not in r:
+            res["not_certified"] += 1
+            continue
+        S, lg = r["support"], r["log"]
+        md = float(np.sqrt((s.disp ** 2).sum(axis=1)).max())
+        warm_S = kept[s.req.key] if r["warm"] else None
+        o = oracle.select(s.xyz, s.disp, s.radius, s.m, s.tol_abs, seed=s.seed, warm_S=warm_S, nthreads=16)
+        if len(o.S) == len(S) and np.array_equal(o.S, S):
+            res["same_sequence"] += 1
+            W = o.W
+        else:
+            bad, _, _ = oracle.validate(s.xyz, s.disp, s.radius, s.m, s.tol_abs, S, lg["log_group"], lg["log_node"],
+                                        lg["log_appended"], tau_rel * md, seed=s.seed, warm_S=warm_S, nthreads=16)
+            res["certified" if bad == -1 else "not_certified"] += 1
+            W = oracle.solve_on_support(s.xyz, S, s.radius, s.disp)
+        res["requests"] += 1
+        res["warm"] += int(bool(r["warm"]))
+        if r["kept"]:
+            kept[s.req.key] = S
+        nv = s.vol.shape[0]
+        if nv:
+            idx = np.sort(rng.choice(nv, size=min(n_points, nv), replace=False))
+            pts = s.vol[torch.from_numpy(idx).to(s.vol.device)].double().cpu().numpy()
+            ref = oracle.interpolate(s.xyz[S], W, s.radius, pts, nthreads=16)
+            got = s.out[torch.from_numpy(idx).to(s.out.device)].double().cpu().numpy()
+            e = np.sqrt(((got - ref) ** 2).sum(axis=1)) / md
+            res["max_err_rel_max_d"] = max(res["max_err_rel_max_d"], float(e.max()))
+            sq += float((e ** 2).sum())
+            cnt += e.size
+    res["rms_err_rel_max_d"] = float(np.sqrt(sq / max(cnt, 1)))
+    return res
+
+
+def serving_section(n_requests, dev, warmup_requests=25, rate=20.0, sat_rate=0.0, check_oracle=False,
+                    oracle_requests=30):
     """Poisson stream (sizes of the uneven batch, 20 % repeats with new fields),
     latency arrival -> output complete: served (continuous batching, resident
-    meshes, warm starts) vs plain FP64 one at a time (FIFO)."""
+    meshes, warm starts) vs plain FP64 one at a time (FIFO).  With check_oracle,
+    the first requests of the stream are served again with their selections
+    recorded (outside the timed replays) and checked against the oracle."""
     import synth
     import paper_2004_04817_amd as gcb
     from paper_2004_04817_amd import serving
@@ -298,8 +355,380 @@ def serving_section(n_requests, dev, warmup_requests=25, rate=20.0, sat_rate=0.0
                 served = serving.replay(srv, fast, pool, nv_per_nb=25, iterations=48)
                 sat[name] = serving.latency_summary(served, skip=warmup_requests)
         res["saturation"] = sat
+    if check_oracle:
+        with gcb.Server(0, hbm_budget=64 << 30, **modes[0][1]) as srv:
+            served = serving.replay(srv, items[:oracle_requests], pool, nv_per_nb=25, iterations=48, record=True)
+        res["vs_oracle"] = serving_vs_oracle(served)
     del pool
     return res
+
+
+def measured_kernel_traffic(tag: str) -> dict:
+    """Per-launch HBM bytes (FETCH_SIZE + WRITE_SIZE, calibrated) of each kernel of a workload, from the
+    committed counter summary; empty when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{tag}.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return {}
+    vals = {k.strip(): v.strip() for k, v in (l.split(":", 1) for l in text.splitlines() if ":" in l
+                                              and l.startswith(("traffic_bytes_per_launch.",
+                                                                "kernel_source_sha256_prefix")))}
+    if vals.get("kernel_source_sha256_prefix", "") != kernel_source_hash(KERNEL_SRC):
+        return {}
+    return {k.split(".", 1)[1]: float(v) for k, v in vals.items() if k.startswith("traffic_bytes_per_launch.")}
+
+
+def rocprof_avg_ms(tag: str) -> dict:
+    """Average launch durations (ms) from the committed rocprofv3 kernel statistics of a workload; empty when
+    the kernel sources changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", f"kernel_stats_{tag}.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return {}
+    vals = {k.strip(): v.strip() for k, v in (l.split(":", 1) for l in text.splitlines() if ":" in l
+                                              and l.startswith(("rocprof_avg_us.", "kernel_source_sha256_prefix")))}
+    if vals.get("kernel_source_sha256_prefix", "") != kernel_source_hash(KERNEL_SRC):
+        return {}
+    return {k.split(".", 1)[1]: 1e-3 * float(v) for k, v in vals.items() if k.startswith("rocprof_avg_us.")}
+
+
+def run_steps(ctx, vol, out, steps, warmup):
+    """W untimed steps, then K timed steps of selection + Eq. 6, each bracketed by device synchronisation."""
+    import torch
+
+    def step():
+        info = ctx.select()
+        ctx.deform(vol, out=out)
+        return info
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    step_ms, vol_ms, infos = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        info = step()
+        torch.cuda.synchronize()
+        step_ms.append(1e3 * (time.perf_counter() - ts))
+        # HIP events the library records on its stream around the volume kernels (host latency excluded)
+        vol_ms.append(ctx.deform_time())
+        infos.append(info)
+    torch.cuda.synchronize()
+    return {"total": time.perf_counter() - t0, "step_ms": step_ms, "vol_ms": vol_ms, "infos": infos}
+
+
+def step_record(p, nv, run, steps):
+    """The step's throughput, phases, pair counts and accuracy figures."""
+    infos = run["infos"]
+    info = infos[-1]
+    nc = info["nc"]
+    pairs_greedy = info["pairs_group"] + info["pairs_append"]
+    pairs_volume = nv * nc
+    sel_ms = float(np.mean([i["ms_select"] for i in infos]))
+    vol_ms = float(np.mean(run["vol_ms"]))
+    return {
+        "value": steps * (pairs_greedy + pairs_volume) / run["total"],
+        "ms_per_step": 1e3 * run["total"] / steps,
+        "config": {"workload": p.name + f"+volume{nv}", "nb": p.nb, "nv": nv, "m": p.m, "radius": p.radius,
+                   "tol_abs": p.tol_abs, "tol_rel": p.tol_rel, "nc": nc, "iterations": info["iterations"],
+                   "precision": "fp64", "parallelism": "single-gpu"},
+        "phases_ms": {"select": sel_ms, "volume": vol_ms},
+        "phase_pair_evals_per_s": {"greedy": pairs_greedy / (1e-3 * sel_ms), "volume": pairs_volume / (1e-3 * vol_ms)},
+        "pairs": {"group": info["pairs_group"], "append": info["pairs_append"], "volume": pairs_volume,
+                  "certificate": info["pairs_cert"]},
+        "latency_ms": {"p50": float(np.percentile(run["step_ms"], 50)),
+                       "p99": float(np.percentile(run["step_ms"], 99))},
+        "accuracy": {"final_max_err": info["final_max_err"], "final_rms_err": info["final_rms_err"],
+                     "converged": bool(info["converged"])},
+        "greedy_iteration": {"bound": "latency", "kernels_per_iteration": 3,
+                             "us_per_iteration": 1e3 * sel_ms / info["iterations"]},
+    }
+
+
+def factor_bytes(log, nc_start=3):
+    """Algorithmic bytes of the append kernels summed over a selection, from its log: an append at |S| = n
+    reads the packed triangle of M (n(n+1)/2 doubles) in each kernel; k_factor_l also reads the supports'
+    coordinates (for b) and weights (for b.W), k_factor_u reads l and W and writes W and the new row twice."""
+    app = np.asarray(log.appended, dtype=np.int64)
+    n = nc_start + np.concatenate([[0], np.cumsum(app)[:-1]]) if len(app) else np.zeros(0, np.int64)
+    n = n[app > 0].astype(np.float64)
+    tri = 8.0 * n * (n + 1) / 2
+    return {"k_factor_l": float(np.sum(tri + 48.0 * n)), "k_factor_u": float(np.sum(tri + 8.0 * n + 48.0 * n + 16.0 * n))}
+
+
+def kernel_rooflines(ctx, p, nv, vol_ms, tag):
+    """One roofline entry per kernel of the step.  The volume sweep is timed by HIP events around its launch
+    in the timed steps; the greedy kernels, which run inside captured graphs there, by a further selection of
+    the same workload with kernel timing on (HIP events between the launches on the library's stream)."""
+    ctx.set_kernel_timing(True)
+    info = ctx.select()
+    kt = ctx.kernel_times()
+    ctx.set_kernel_timing(False)
+    log = ctx.get_log()
+    nc = info["nc"]
+    fb = factor_bytes(log)
+    traffic = measured_kernel_traffic(tag)
+    rp = rocprof_avg_ms(tag)
+    ents = []
+
+    def entry(kernel, bound, units, launches, total_ms, peak, unit, timing, what):
+        avg_ms = total_ms / max(launches, 1)
+        per_launch = units / max(launches, 1)
+        scale = 1e12 if unit == "TFLOP/s" else 1e9
+        ach = per_launch / (avg_ms * 1e-3) / scale
+        t = traffic.get(kernel)
+        e = {"kernel": kernel, "bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+             "traffic": t, "launches_per_step": launches, "avg_launch_ms": avg_ms, "ms_per_step": total_ms,
+             "per_launch": per_launch, "per_launch_what": what, "timing": timing}
+        if kernel in rp:
+            # the committed rocprofv3 average of the same kernel (execution only, no dispatch)
+            e["rocprof_avg_launch_ms"] = rp[kernel]
+            e["rocprof_ms_per_step"] = rp[kernel] * launches
+            e["rocprof_frac"] = per_launch / (rp[kernel] * 1e-3) / scale / peak
+        return e
+
+    ents.append(entry("k_volume64", "alu", FLOPS_PER_PAIR * nv * nc, 1, vol_ms, FP64_PEAK_TFLOPS, "TFLOP/s",
+                      "HIP events on the library stream around the launch, averaged over the timed steps",
+                      "flops: 21 x Nv x Nc pairs"))
+    ktiming = "HIP events between launches on the library stream, one further selection with kernel timing on"
+    ents.append(entry("k_sweep", "alu", FLOPS_PER_PAIR * info["pairs_group"], kt["sweep"]["launches"],
+                      kt["sweep"]["ms"], FP64_PEAK_TFLOPS, "TFLOP/s", ktiming,
+                      "flops: 21 x |G_i minus S| x |S| pairs of the group sweep"))
+    ents.append(entry("k_factor_l", "hbm", fb["k_factor_l"], kt["k_factor_l"]["launches"], kt["k_factor_l"]["ms"],
+                      HBM_PEAK_GBS, "GB/s", ktiming, "bytes: packed triangle of M (4 n^2) + 48 n per append"))
+    ents.append(entry("k_factor_u", "hbm", fb["k_factor_u"], kt["k_factor_u"]["launches"], kt["k_factor_u"]["ms"],
+                      HBM_PEAK_GBS, "GB/s", ktiming, "bytes: packed triangle of M by columns (4 n^2) + 72 n per append"))
+    ents.append(entry("k_certify", "alu", FLOPS_PER_PAIR * info["pairs_cert"], kt["certificate"]["launches"],
+                      kt["certificate"]["ms"], FP64_PEAK_TFLOPS, "TFLOP/s", ktiming,
+                      "flops: 21 x Nb x Nc pairs (with its final reduction)"))
+    same = info["nc"] == nc and bool(info["converged"])
+    return ents, {"iterations": info["iterations"], "select_ms_with_kernel_timing": info["ms_select"],
+                  "same_result_as_timed_steps": same}
+
+
+def fp32_section(ctx, p, vol, out64, sample_ref=None):
+    """Eq. 6 in FP32 (GCB_PREC_FP32_EVAL) on the same supports: time, and max / RMS error against the
+    FP64 oracle's sample (and against the GPU's FP64 output at every point)."""
+    import torch
+    import paper_2004_04817_amd as gcb
+    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed, precision=gcb.GCB_PREC_FP32_EVAL)
+    ctx.select()
+    out32 = torch.empty_like(vol)
+    ctx.deform(vol, out=out32)
+    ts = []
+    for _ in range(3):
+        ctx.deform(vol, out=out32)
+        torch.cuda.synchronize()
+        ts.append(ctx.deform_time())
+    ms32 = float(np.mean(ts))
+    md = p.max_disp
+    e = torch.linalg.vector_norm(out32 - out64, dim=1)
+    rec = {"ms": ms32, "kernel": "k_volume32", "max_err_vs_gpu_fp64_rel_max_d": float(e.max().item()) / md,
+           "rms_err_vs_gpu_fp64_rel_max_d": float(torch.sqrt((e * e).mean()).item()) / md}
+    if sample_ref is not None:
+        o = out32[: sample_ref.shape[0]].cpu().numpy()
+        eo = np.sqrt(((o - sample_ref) ** 2).sum(axis=1))
+        rec.update({"vs_oracle_points": int(sample_ref.shape[0]),
+                    "max_err_vs_oracle_rel_max_d": float(eo.max()) / md,
+                    "rms_err_vs_oracle_rel_max_d": float(np.sqrt((eo ** 2).mean())) / md})
+        rec["meets_1e-6_max_d"] = rec["max_err_vs_oracle_rel_max_d"] <= 1e-6
+    del out32
+    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
+    ctx.select()
+    return rec
+
+
+def vs_oracle_record(ctx, p, out, r_orc, ref):
+    """The GPU's support sequence and sampled displacements against the FP64 oracle's."""
+    S_gpu, _ = ctx.get_support()
+    o = out[: ref.shape[0]].cpu().numpy()
+    err = np.sqrt(((o - ref) ** 2).sum(axis=1))
+    S_orc = np.asarray(r_orc.S)
+    k = min(len(S_gpu), len(S_orc))
+    diff = np.nonzero(np.asarray(S_gpu[:k]) != S_orc[:k])[0]
+    return {"same_support_sequence": bool(np.array_equal(S_gpu, S_orc)),
+            "identical_prefix": int(diff[0]) if diff.size else k,
+            "nc_gpu": int(len(S_gpu)), "nc_oracle": int(len(S_orc)),
+            "gpu_sequence_certified": certify_sequence(ctx, p, S_gpu),
+            "volume_points_compared": int(ref.shape[0]),
+            "volume_max_err_rel_max_d": float(err.max() / p.max_disp),
+            "volume_rms_err_rel_max_d": float(np.sqrt((err ** 2).mean()) / p.max_disp),
+            "oracle_final_max_err": r_orc.final_max_err}
+
+
+def refactor_section(ctx, p):
+    """Dense FP64 refactorisation of the selected support system (blocked Cholesky + inverse, MFMA)."""
+    drift, rinfo = ctx.refactor()        # against the incrementally grown factor
+    _, rinfo = ctx.refactor()            # timed again with warm caches
+    nc = rinfo["nc"]
+    rflops = 2.0 * nc ** 3 / 3.0
+    rec = {"nc": nc, "ms": rinfo["ms_select"], "drift": drift, "tflops": rflops / (rinfo["ms_select"] * 1e-3) / 1e12,
+           "flops": "Nc^3/3 (Cholesky) + Nc^3/3 (triangular inverse)"}
+    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
+    ctx.select()
+    return rec
+
+
+def host_buffers_section(p, nv, nc):
+    """The same step with the inputs and the output in host memory (pageable numpy arrays): boundary copied in,
+    selection, volume points copied in and displacements copied out; never the headline value."""
+    import torch
+    import paper_2004_04817_amd as gcb
+    hctx = gcb.Context(0)
+    hout = np.empty_like(p.volume)
+    hs = []
+    for r in range(3):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        hctx.set_boundary(p.xyz, p.disp)
+        hctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
+        hinfo = hctx.select()
+        hctx.deform(p.volume, out=hout)
+        torch.cuda.synchronize()
+        if r > 0:
+            hs.append(time.perf_counter() - ts)
+    hsec = float(np.mean(hs))
+    rec = {"ms_per_step": 1e3 * hsec,
+           "pair_evals_per_s": (hinfo["pairs_group"] + hinfo["pairs_append"] + nv * hinfo["nc"]) / hsec,
+           "bytes_in": int(p.xyz.nbytes + p.disp.nbytes + p.volume.nbytes), "bytes_out": int(hout.nbytes),
+           "what": "PCIe-inclusive step: host boundary and volume in, host displacements out"}
+    hctx.close()
+    return rec
+
+
+def modes_section(ctx, p, xyz, vol, k_modes, check_oracle, stream):
+    """Many right-hand sides on one support set (64 modes = 192 columns) over the workload's points."""
+    import torch
+    import synth
+    dev = vol.device
+    nv = vol.shape[0]
+    nc = ctx.nc
+    modes = torch.from_numpy(synth.config_modes(p, k_modes)).to(dev)
+    mout = torch.empty((nv, 3 * k_modes), dtype=torch.float64, device=dev)
+    ctx.deform_multi(modes, vol, out=mout)   # warm-up
+    ts = []
+    for _ in range(2):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ctx.deform_multi(modes, vol, out=mout)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.mean(ts))
+    rhs = 3 * k_modes
+    flops = (2.0 * rhs + 15.0) * nv * nc   # matrix-core FMAs + the phi evaluation per pair
+    mvs = None
+    if check_oracle:
+        # sampled points of the 192-column output against the oracle's solve on the same support set
+        import oracle
+        S_m, _ = ctx.get_support()
+        mh = modes.cpu().numpy()
+        Wo = oracle.solve_on_support(p.xyz, S_m, p.radius, mh)
+        step = max(1, nv // 20000)
+        ref = oracle.interpolate(p.xyz[S_m], Wo, p.radius, p.volume[::step], nthreads=16)
+        got = mout[::step].cpu().numpy()
+        scale = float(np.abs(mh).max())
+        mvs = {"points_compared": int(ref.shape[0]), "max_err_rel_max_mode": float(np.abs(got - ref).max()) / scale,
+               "rms_err_rel_max_mode": float(np.sqrt(np.mean((got - ref) ** 2))) / scale}
+    # each mode's interpolation error at all nb boundary nodes (Eq. 3 holds only on S: the support set was
+    # selected for the benchmark field, so no tolerance is claimed for the modes)
+    bout = torch.empty((p.nb, rhs), dtype=torch.float64, device=dev)
+    ctx.deform_multi(modes, xyz, out=bout)
+    e = torch.linalg.vector_norm((bout - modes).reshape(p.nb, k_modes, 3), dim=2).max(dim=0).values
+    peak = torch.linalg.vector_norm(modes.reshape(p.nb, k_modes, 3), dim=2).max(dim=0).values
+    rel = (e / peak).cpu().numpy()
+    all_node = {"max_err_rel_max_mode": {"min": float(rel.min()), "median": float(np.median(rel)),
+                                         "max": float(rel.max())}, "nodes": p.nb}
+    return {"k_modes": k_modes, "rhs": rhs, "nv": nv, "nc": nc, "ms": ms, "vs_oracle": mvs,
+            "all_node_error": all_node, "pair_evals_per_s": nv * nc / (ms * 1e-3),
+            "roofline": {"kernel": "k_volume_multi<double,double> (+ weight TRMMs)", "bound": "mfma",
+                         "achieved": flops / (ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}}
+
+
+def m_sweep_section(ctx, p, ms_list):
+    """GCB group count m against the traditional greedy (m = 1), free and fixed Nc (Tables 2, 3, 5, 6
+    protocol), KL of the support sets (Table 4 analog) and the error history (Figs. 4-7 analog)."""
+    rows = []
+    for m in ms_list:
+        ctx.set_params(p.radius, m, p.tol_abs, seed=p.seed)
+        ctx.select()
+        inf = ctx.select()
+        rows.append({"m": m, "nc": inf["nc"], "iterations": inf["iterations"], "select_ms": inf["ms_select"],
+                     "pairs_greedy": inf["pairs_group"] + inf["pairs_append"], "converged": bool(inf["converged"])})
+    base = next((r["select_ms"] for r in rows if r["m"] == 1), None)
+    for r in rows:
+        r["speedup_vs_m1"] = base / r["select_ms"] if base else None
+    nc_fixed = 1100
+    fixed, sets = [], {}
+    for m in ms_list:
+        ctx.set_params(p.radius, m, 0.0, nc_max=nc_fixed, seed=p.seed)
+        ctx.select()
+        inf = ctx.select()
+        sets[m] = ctx.get_support()[0]
+        fixed.append({"m": m, "nc": inf["nc"], "iterations": inf["iterations"], "select_ms": inf["ms_select"],
+                      "final_max_err_rel": inf["final_max_err"] / p.max_disp})
+    fbase = next((r["select_ms"] for r in fixed if r["m"] == 1), None)
+    for r in fixed:
+        r["speedup_vs_m1"] = fbase / r["select_ms"] if fbase else None
+    kl = None
+    if 1 in sets:
+        kl = {f"m{m}": kl_divergence(p.xyz, sets[1], S) for m, S in sets.items() if m != 1}
+        for r_id in (1, 2):
+            rnd = np.random.default_rng(1000 + r_id).choice(p.nb, size=nc_fixed, replace=False)
+            kl[f"random{r_id}"] = kl_divergence(p.xyz, sets[1], rnd)
+    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed, monitor_every=p.m)
+    ctx.select()
+    it_h, mx_h, rm_h = ctx.get_monitor()
+    log_h = ctx.get_log()
+    nc_at = np.cumsum(log_h.appended.astype(np.int64)) + 3
+    pick = np.unique(np.linspace(0, len(it_h) - 1, 8).astype(int)) if len(it_h) else []
+    history = [{"iteration": int(it_h[i]), "nc": int(nc_at[it_h[i] - 1]), "max_err_rel": float(mx_h[i] / p.max_disp),
+                "rms_err_rel": float(rm_h[i] / p.max_disp)} for i in pick]
+    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
+    ctx.select()
+    return {"free_nc": rows, "fixed_nc": {"nc": nc_fixed, "rows": fixed, "kl_vs_m1": kl},
+            f"history_m{p.m}": history}
+
+
+def wing80k_section(a, dev, stream):
+    """The 80,000-node wing with 3,000,000 points: its own timed steps, per-kernel rooflines, FP32 evaluation,
+    the 64-mode batch and the m-sweep on its supports, and its outputs against the oracle."""
+    import torch
+    import paper_2004_04817_amd as gcb
+    import synth
+    p = synth.config_wing()
+    xyz = torch.from_numpy(p.xyz).to(dev)
+    vol = torch.from_numpy(p.volume).to(dev)
+    out = torch.empty_like(vol)
+    nv = vol.shape[0]
+    ctx = gcb.Context(0)
+    ctx.set_boundary(xyz, torch.from_numpy(p.disp).to(dev))
+    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
+    steps = max(1, min(a.steps, 10))
+    run = run_steps(ctx, vol, out, steps, max(1, min(a.warmup, 3)))
+    rec = step_record(p, nv, run, steps)
+    rec["steps"] = steps
+    rec["rooflines"], rec["kernel_timing_run"] = kernel_rooflines(ctx, p, nv, rec["phases_ms"]["volume"], "wing80k")
+    ref = r = None
+    if not a.no_cpu_baseline:
+        import oracle
+        r = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed, nthreads=os.cpu_count() or 1)
+        ref = oracle.interpolate(p.xyz[r.S], r.W, p.radius, p.volume, nthreads=os.cpu_count() or 1)
+        rec["accuracy"]["vs_oracle"] = vs_oracle_record(ctx, p, out, r, ref)
+    rec["volume_fp32_eval"] = fp32_section(ctx, p, vol, out, ref)
+    rec["volume_fp32_eval"]["speedup_vs_fp64"] = rec["phases_ms"]["volume"] / rec["volume_fp32_eval"]["ms"]
+    rec["refactor"] = refactor_section(ctx, p)
+    if a.modes > 0:
+        rec["modes"] = modes_section(ctx, p, xyz, vol, a.modes, not a.no_cpu_baseline, stream)
+    if a.m_sweep:
+        rec["m_sweep"] = m_sweep_section(ctx, p, [int(x) for x in a.m_sweep.split(",")])
+    ctx.close()
+    return rec
 
 
 def main():
@@ -329,251 +758,72 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def step():
-        info = ctx.select()
-        ctx.deform(vol, out=out)
-        return info
-
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    step_ms, vol_ms, infos = [], [], []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(a.steps):
-        ts = time.perf_counter()
-        info = step()
-        torch.cuda.synchronize()
-        step_ms.append(1e3 * (time.perf_counter() - ts))
-        # HIP events the library records on its stream around the volume kernels (host latency excluded)
-        vol_ms.append(ctx.deform_time())
-        infos.append(info)
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t0
-    info = infos[-1]
-    nc = info["nc"]
-    pairs_greedy = info["pairs_group"] + info["pairs_append"]
-    pairs_volume = nv * nc
-    value = a.steps * (pairs_greedy + pairs_volume) / total
-    vol_avg_ms = float(np.mean(vol_ms))
-    achieved = FLOPS_PER_PAIR * pairs_volume / (vol_avg_ms * 1e-3) / 1e12
+    run = run_steps(ctx, vol, out, a.steps, a.warmup)
+    srec = step_record(p, nv, run, a.steps)
+    tag = {"wing-large": "wing300k", "wing": "wing80k", "small": "ellipsoid2k"}[a.config]
+    rooflines, ktrun = kernel_rooflines(ctx, p, nv, srec["phases_ms"]["volume"], tag)
+    # the dominant kernel: most device time per step, by the rocprofv3 durations when they are current (the
+    # event intervals of the short greedy kernels include their dispatch), else by the events
+    dominant = max(rooflines, key=lambda e: e.get("rocprof_ms_per_step", e["ms_per_step"]))
     rec = {
         "metric": "RBF pair-evals/s (greedy+volume); deform latency p50/p99 vs plain FP64 GPU",
-        "value": value,
+        "value": srec["value"],
         "unit": "pair-evals/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": 1e3 * total / a.steps,
+        "ms_per_step": srec["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": p.name + f"+volume{nv}", "nb": p.nb, "nv": nv, "m": p.m, "radius": p.radius,
-                   "tol_abs": p.tol_abs, "tol_rel": p.tol_rel, "nc": nc, "iterations": info["iterations"],
-                   "precision": "fp64", "parallelism": "single-gpu"},
-        "phases_ms": {"select": float(np.mean([i["ms_select"] for i in infos])), "volume": vol_avg_ms},
-        "phase_pair_evals_per_s": {
-            "greedy": pairs_greedy / (1e-3 * float(np.mean([i["ms_select"] for i in infos]))),
-            "volume": pairs_volume / (1e-3 * vol_avg_ms)},
-        "pairs": {"group": info["pairs_group"], "append": info["pairs_append"], "volume": pairs_volume,
-                  "certificate": info["pairs_cert"]},
-        "latency_ms": {"p50": float(np.percentile(step_ms, 50)), "p99": float(np.percentile(step_ms, 99))},
-        "accuracy": {"final_max_err": info["final_max_err"], "final_rms_err": info["final_rms_err"],
-                     "converged": bool(info["converged"])},
-        "roofline": {"kernel": "k_volume64<double,double>", "bound": "alu", "achieved": achieved,
-                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": (measured_traffic(os.path.join(ROOT, "paper_2004_04817_amd", "csrc",
-                                                               "gcb_kernels.hip")) if a.config == "wing" else None),
-                     "flops_per_pair": FLOPS_PER_PAIR, "pairs_per_launch": pairs_volume,
-                     "launch_ms": vol_avg_ms},
+        "config": srec["config"],
+        "roofline": dict(dominant),
     }
-    valu = measured_valu(os.path.join(ROOT, "paper_2004_04817_amd", "csrc", "gcb_kernels.hip"))
-    greedy_busy = valu.pop("greedy_valu_busy_pct") if valu else None
-    if valu and a.config == "wing":
-        # the instruction mix caps the fraction of peak: 21 flops per pair over 2 flops per issue slot
-        valu["frac_of_op_mix_ceiling"] = (achieved / FP64_PEAK_TFLOPS) / valu["op_mix_ceiling_frac"]
-        rec["roofline"]["instruction_mix"] = valu
-    # the greedy phase: one iteration is three dependent launches; the VALUs are nearly idle in them
-    rec["greedy_iteration"] = {"bound": "latency", "kernels_per_iteration": 3,
-                               "us_per_iteration": 1e3 * rec["phases_ms"]["select"] / info["iterations"],
-                               "valu_busy_pct": greedy_busy if a.config == "wing" else None}
-    # dense FP64 refactorisation of the selected support system (blocked Cholesky + triangular inverse, MFMA)
-    drift, rinfo = ctx.refactor()        # against the incrementally grown factor
-    _, rinfo = ctx.refactor()            # timed again with warm caches
-    rflops = 2.0 * nc ** 3 / 3.0
-    rec["refactor"] = {"nc": nc, "ms": rinfo["ms_select"], "drift": drift,
-                       "tflops": rflops / (rinfo["ms_select"] * 1e-3) / 1e12,
-                       "flops": "Nc^3/3 (Cholesky) + Nc^3/3 (triangular inverse)"}
-    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
-    ctx.select()
-    # Eq. (6) in FP32 (GCB_PREC_FP32_EVAL) on the same supports: time and error against the FP64 output
-    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed, precision=gcb.GCB_PREC_FP32_EVAL)
-    ctx.select()
-    out32 = torch.empty_like(vol)
-    ctx.deform(vol, out=out32)
-    ts = []
-    for _ in range(3):
-        ctx.deform(vol, out=out32)
-        torch.cuda.synchronize()
-        ts.append(ctx.deform_time())
-    ms32 = float(np.mean(ts))
-    err32 = float((out32 - out).abs().max().item()) / p.max_disp
-    rec["volume_fp32_eval"] = {"ms": ms32, "pair_evals_per_s": pairs_volume / (ms32 * 1e-3),
-                               "speedup_vs_fp64": vol_avg_ms / ms32, "max_err_vs_fp64_rel_max_d": err32,
-                               "meets_1e-6_max_d": err32 <= 1e-6}
-    del out32
-    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
-    ctx.select()
+    for k in ("phases_ms", "phase_pair_evals_per_s", "pairs", "latency_ms", "accuracy", "greedy_iteration"):
+        rec[k] = srec[k]
+    rec["rooflines"] = rooflines
+    rec["kernel_timing_run"] = ktrun
+    # the volume sweep's instruction mix (from the committed VALU counters of the 80,000-node wing)
+    valu = measured_valu(KERNEL_SRC)
+    if valu:
+        greedy_busy = valu.pop("greedy_valu_busy_pct")
+        vfrac = next(e["frac"] for e in rooflines if e["kernel"] == "k_volume64")
+        valu["frac_of_op_mix_ceiling"] = vfrac / valu["op_mix_ceiling_frac"]
+        rec["volume_instruction_mix"] = valu
+        rec["greedy_iteration"]["valu_busy_pct_wing80k"] = greedy_busy
+    rec["refactor"] = refactor_section(ctx, p)
     if a.host_buffers:
-        # the same step with the inputs and the output in host memory (pageable numpy arrays): boundary copied in,
-        # selection, volume points copied in and displacements copied out; never the headline value
-        hctx = gcb.Context(0)
-        hout = np.empty_like(p.volume)
-        hs = []
-        for r in range(3):
-            torch.cuda.synchronize()
-            ts = time.perf_counter()
-            hctx.set_boundary(p.xyz, p.disp)
-            hctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
-            hinfo = hctx.select()
-            hctx.deform(p.volume, out=hout)
-            torch.cuda.synchronize()
-            if r > 0:
-                hs.append(time.perf_counter() - ts)
-        hsec = float(np.mean(hs))
-        rec["host_buffers"] = {"ms_per_step": 1e3 * hsec,
-                               "pair_evals_per_s": (hinfo["pairs_group"] + hinfo["pairs_append"] + nv * nc) / hsec,
-                               "bytes_in": int(p.xyz.nbytes + p.disp.nbytes + p.volume.nbytes),
-                               "bytes_out": int(hout.nbytes),
-                               "what": "PCIe-inclusive step: host boundary and volume in, host displacements out"}
-        hctx.close()
-        del hout
-    if a.modes > 0 and a.config == "wing":
-        import synth
-        modes = torch.from_numpy(synth.config_modes(p, a.modes)).to(dev)
-        mout = torch.empty((nv, 3 * a.modes), dtype=torch.float64, device=dev)
-        ctx.deform_multi(modes, vol, out=mout)   # warm-up
-        ts = []
-        for _ in range(2):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            ctx.deform_multi(modes, vol, out=mout)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        ms = float(np.mean(ts))
-        rhs = 3 * a.modes
-        flops = (2.0 * rhs + 15.0) * nv * nc   # matrix-core FMAs + the phi evaluation per pair
-        mvs = None
-        if not a.no_cpu_baseline:
-            # sampled points of the 192-column output against the oracle's solve on the same support set
-            import oracle
-            S_m, _ = ctx.get_support()
-            mh = modes.cpu().numpy()
-            Wo = oracle.solve_on_support(p.xyz, S_m, p.radius, mh)
-            step = max(1, nv // 20000)
-            ref = oracle.interpolate(p.xyz[S_m], Wo, p.radius, p.volume[::step], nthreads=16)
-            got = mout[::step].cpu().numpy()
-            scale = float(np.abs(mh).max())
-            mvs = {"points_compared": int(ref.shape[0]), "max_err_rel_max_mode": float(np.abs(got - ref).max()) / scale,
-                   "rms_err_rel_max_mode": float(np.sqrt(np.mean((got - ref) ** 2))) / scale}
-        # each mode's interpolation error at all nb boundary nodes (Eq. 3 holds only on S: the support set was
-        # selected for the benchmark field, so no tolerance is claimed for the modes)
-        bout = torch.empty((p.nb, rhs), dtype=torch.float64, device=dev)
-        ctx.deform_multi(modes, xyz, out=bout)
-        e = torch.linalg.vector_norm((bout - modes).reshape(p.nb, a.modes, 3), dim=2).max(dim=0).values
-        peak = torch.linalg.vector_norm(modes.reshape(p.nb, a.modes, 3), dim=2).max(dim=0).values
-        rel = (e / peak).cpu().numpy()
-        all_node = {"max_err_rel_max_mode": {"min": float(rel.min()), "median": float(np.median(rel)),
-                                             "max": float(rel.max())}, "nodes": p.nb}
-        del bout
-        rec["modes"] = {"k_modes": a.modes, "rhs": rhs, "nv": nv, "nc": nc, "ms": ms, "vs_oracle": mvs,
-                        "all_node_error": all_node,
-                        "pair_evals_per_s": nv * nc / (ms * 1e-3),
-                        "roofline": {"kernel": "k_volume_multi<double,double> (+ weight TRMMs)", "bound": "mfma",
-                                     "achieved": flops / (ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
-                                     "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}}
-        del mout, modes
-    if a.m_sweep and a.config == "wing":
-        # GCB group count m against the traditional greedy (m = 1), free Nc, same E* (Tables 3 and 6 protocol)
-        rows = []
-        for m in [int(x) for x in a.m_sweep.split(",")]:
-            ctx.set_params(p.radius, m, p.tol_abs, seed=p.seed)
-            ctx.select()
-            inf = ctx.select()
-            rows.append({"m": m, "nc": inf["nc"], "iterations": inf["iterations"], "select_ms": inf["ms_select"],
-                         "pairs_greedy": inf["pairs_group"] + inf["pairs_append"],
-                         "converged": bool(inf["converged"])})
-        base = next((r["select_ms"] for r in rows if r["m"] == 1), None)
-        for r in rows:
-            r["speedup_vs_m1"] = base / r["select_ms"] if base else None
-        # fixed Nc (Tables 2 and 5 protocol): E* = 0, every m selects exactly Nc^max supports
-        nc_fixed = 1100
-        fixed, sets = [], {}
-        for m in [int(x) for x in a.m_sweep.split(",")]:
-            ctx.set_params(p.radius, m, 0.0, nc_max=nc_fixed, seed=p.seed)
-            ctx.select()
-            inf = ctx.select()
-            sets[m] = ctx.get_support()[0]
-            fixed.append({"m": m, "nc": inf["nc"], "iterations": inf["iterations"], "select_ms": inf["ms_select"],
-                          "final_max_err_rel": inf["final_max_err"] / p.max_disp})
-        fbase = next((r["select_ms"] for r in fixed if r["m"] == 1), None)
-        for r in fixed:
-            r["speedup_vs_m1"] = fbase / r["select_ms"] if fbase else None
-        # distribution of the support nodes against the traditional greedy's (Table 4 analog): KL(m = 1 || m),
-        # and two seeded random sets of the same size
-        kl = None
-        if 1 in sets:
-            kl = {f"m{m}": kl_divergence(p.xyz, sets[1], S) for m, S in sets.items() if m != 1}
-            for r_id in (1, 2):
-                rnd = np.random.default_rng(1000 + r_id).choice(p.nb, size=nc_fixed, replace=False)
-                kl[f"random{r_id}"] = kl_divergence(p.xyz, sets[1], rnd)
-        # error history of the benchmark selection (all-node max and RMS every m iterations; Figs. 4-7 analog)
-        ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed, monitor_every=p.m)
-        ctx.select()
-        it_h, mx_h, rm_h = ctx.get_monitor()
-        log_h = ctx.get_log()
-        nc_at = np.cumsum(log_h.appended.astype(np.int64)) + 3
-        pick = np.unique(np.linspace(0, len(it_h) - 1, 8).astype(int)) if len(it_h) else []
-        history = [{"iteration": int(it_h[i]), "nc": int(nc_at[it_h[i] - 1]), "max_err_rel": float(mx_h[i] / p.max_disp),
-                    "rms_err_rel": float(rm_h[i] / p.max_disp)} for i in pick]
-        rec["m_sweep"] = {"free_nc": rows, "fixed_nc": {"nc": nc_fixed, "rows": fixed, "kl_vs_m1": kl},
-                          "history_m107": history}
-        ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
-        ctx.select()
+        rec["host_buffers"] = host_buffers_section(p, nv, srec["config"]["nc"])
+    base = r_orc = ref = None
+    if not a.no_cpu_baseline:
+        base, r_orc, ref = cpu_baseline(p, min(a.cpu_sample_volume, nv))
+        rec["cpu_baseline"] = base
+        rec["accuracy"]["vs_oracle"] = vs_oracle_record(ctx, p, out, r_orc, ref)
+    rec["volume_fp32_eval"] = fp32_section(ctx, p, vol, out, ref)
+    rec["volume_fp32_eval"]["speedup_vs_fp64"] = srec["phases_ms"]["volume"] / rec["volume_fp32_eval"]["ms"]
+    if a.config == "wing":
+        # the 80,000-node wing is the headline: its mode batch and m-sweep join the top level
+        if a.modes > 0:
+            rec["modes"] = modes_section(ctx, p, xyz, vol, a.modes, not a.no_cpu_baseline, stream)
+        if a.m_sweep:
+            rec["m_sweep"] = m_sweep_section(ctx, p, [int(x) for x in a.m_sweep.split(",")])
+    ctx.close()
+    del vol, out, xyz, disp
+    torch.cuda.empty_cache()
+    if a.wing80k and a.config == "wing-large":
+        rec["wing80k"] = wing80k_section(a, dev, stream)
     if a.surfaces > 0:
         rec["multi_surface"] = multi_surface(a.surfaces, dev, vs_oracle=not a.no_cpu_baseline)
     if a.requests > 0:
         rec["serving"] = serving_section(a.requests, dev, warmup_requests=a.warmup_requests,
-                                         sat_rate=a.saturation_rate)
+                                         sat_rate=a.saturation_rate, check_oracle=not a.no_cpu_baseline)
         rec["latency_ms"] = {"p50": rec["serving"]["served"]["p50_ms"], "p99": rec["serving"]["served"]["p99_ms"],
                              "p50_one_at_a_time_fp64": rec["serving"]["one_at_a_time"]["p50_ms"],
                              "p99_one_at_a_time_fp64": rec["serving"]["one_at_a_time"]["p99_ms"],
                              "what": "deformation request latency, arrival to output complete"}
-    if not a.no_cpu_baseline:
-        base, r_orc, ref = cpu_baseline(p, min(a.cpu_sample_volume, nv))
-        rec["cpu_baseline"] = base
-        # the benchmark's own outputs against the FP64 oracle (same inputs)
-        S_gpu, _ = ctx.get_support()
-        o = out[: ref.shape[0]].cpu().numpy()
-        err = np.sqrt(((o - ref) ** 2).sum(axis=1))
-        S_orc = np.asarray(r_orc.S)
-        k = min(len(S_gpu), len(S_orc))
-        diff = np.nonzero(np.asarray(S_gpu[:k]) != S_orc[:k])[0]
-        rec["accuracy"]["vs_oracle"] = {
-            "same_support_sequence": bool(np.array_equal(S_gpu, S_orc)),
-            "identical_prefix": int(diff[0]) if diff.size else k,
-            "nc_gpu": int(len(S_gpu)), "nc_oracle": int(len(S_orc)),
-            "gpu_sequence_certified": certify_sequence(ctx, p, S_gpu),
-            "volume_points_compared": int(ref.shape[0]),
-            "volume_max_err_rel_max_d": float(err.max() / p.max_disp),
-            "volume_rms_err_rel_max_d": float(np.sqrt((err ** 2).mean()) / p.max_disp),
-            "oracle_final_max_err": r_orc.final_max_err}
     print(json.dumps(rec), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

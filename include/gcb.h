@@ -167,6 +167,24 @@ int64_t gcb_get_log(gcb_ctx *ctx, int32_t *group, int64_t *node, double *err, in
  * context.  nv = 0 is a no-op.  Requires a finished gcb_select. */
 int gcb_deform(gcb_ctx *ctx, int64_t nv, const void *xyz, int in_dtype, void *out, int out_dtype, int mem);
 
+/* Measurement aid for the greedy loop's kernels (Algorithm 1's group sweep,
+ * and the two kernels of the support-system append of Section 1's RC
+ * scheme: the decision with l = M b, and u = M^T l with the new factor row).
+ * With on = 1, later gcb_select calls run their iterations without captured
+ * graphs and record HIP events on the context's stream between the launches
+ * of every iteration's kernels, and around the all-node certificate; the
+ * selection is slower, its results are the same.  on = 0 turns it off. */
+int gcb_set_kernel_timing(gcb_ctx *ctx, int32_t on);
+
+/* Device time of the last selection that ran with kernel timing on:
+ * ms[0..3] summed milliseconds and launches[0..3] launch counts of the group
+ * sweep (k_sweep, k_sweep_wide or k_sweep_lanes), k_factor_l, k_factor_u and
+ * the all-node certificate (k_certify with its final reduction); either
+ * pointer may be NULL.  An interval runs from the event before a launch to
+ * the event after it, so it includes that launch's dispatch on the device.
+ * GCB_E_STATE if no selection ran with kernel timing on. */
+int gcb_get_kernel_times(gcb_ctx *ctx, double *ms, int64_t *launches);
+
 /* Largest support count gcb_deform_noalloc accepts. */
 #define GCB_NOALLOC_MAX_SUPPORTS 8192
 

@@ -35,7 +35,8 @@ EXPORTS = ["gcb_version", "gcb_partition", "gcb_create", "gcb_destroy", "gcb_las
            "gcb_batch_end", "gcb_select_batch", "gcb_deform_batch", "gcb_batch_set_layout",
            "gcb_server_clock", "gcb_server_create", "gcb_server_destroy", "gcb_server_last_error",
            "gcb_server_submit", "gcb_server_progress", "gcb_server_result", "gcb_server_forget",
-           "gcb_server_memory", "gcb_deform_time", "gcb_deform_noalloc"]
+           "gcb_server_memory", "gcb_deform_time", "gcb_deform_noalloc",
+           "gcb_set_kernel_timing", "gcb_get_kernel_times"]
 
 GCB_NOALLOC_MAX_SUPPORTS = 8192
 
@@ -118,6 +119,8 @@ def lib():
         L.gcb_get_log.restype = i64
         L.gcb_deform.argtypes = [vp, i64, vp, C.c_int, vp, C.c_int, C.c_int]
         L.gcb_deform_noalloc.argtypes = [vp, i64, vp, C.c_int, vp, C.c_int]
+        L.gcb_set_kernel_timing.argtypes = [vp, i32]
+        L.gcb_get_kernel_times.argtypes = [vp, vp, vp]
         L.gcb_deform_multi.argtypes = [vp, i32, vp, i64, vp, C.c_int, vp, C.c_int, C.c_int]
         L.gcb_certify.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.gcb_set_support.argtypes = [vp, vp, i64, C.c_int, C.POINTER(SelectInfo)]
@@ -367,6 +370,18 @@ class Context:
         self.use_current_stream(kx)
         self._check(lib().gcb_deform_noalloc(self._h, int(kx.shape[0]), px, in_dt, po, out_dt))
         return out
+
+    def set_kernel_timing(self, on: bool):
+        """Record HIP events between the greedy kernels of later selections (slower, same results)."""
+        self._check(lib().gcb_set_kernel_timing(self._h, 1 if on else 0))
+
+    def kernel_times(self) -> dict:
+        """Summed device ms and launch counts per greedy kernel of the last timed selection."""
+        ms = (C.c_double * 4)()
+        n = (C.c_int64 * 4)()
+        self._check(lib().gcb_get_kernel_times(self._h, ms, n))
+        names = ("sweep", "k_factor_l", "k_factor_u", "certificate")
+        return {k: {"ms": ms[q], "launches": int(n[q])} for q, k in enumerate(names)}
 
     def deform_time(self) -> float:
         """Device milliseconds of the last deform's kernels (waits for them)."""

@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/gcb.h"
@@ -136,8 +137,14 @@ struct gcb_ctx {
     gcb_select_info info{};
     // captured chunk of greedy iterations (replayed while its key is unchanged)
     hipStream_t cap_stream = nullptr;
-    hipGraphExec_t chunk_exec = nullptr;
+    std::vector<std::pair<int64_t, hipGraphExec_t>> chunk_execs;   // one per phase k mod m of a chunk start
     std::vector<int64_t> chunk_key;
+    // kernel timing (measurement aid): events between the launches of every iteration of a chunk
+    bool ktime_on = false;
+    std::vector<hipEvent_t> ktime_ev;
+    double ktime_ms[4] = {0, 0, 0, 0};   // group sweep, k_factor_l, k_factor_u, certificate
+    int64_t ktime_n[4] = {0, 0, 0, 0};
+    bool ktime_valid = false;
     uint64_t alloc_gen = 0;            // bumped by every device allocation
     gcb::GState *state_pin = nullptr;   // pinned host copy of the state
     hipEvent_t ev0 = nullptr, ev1 = nullptr;   // selection start / end

@@ -127,7 +127,9 @@ void launch_volume_batch(hipStream_t s, const VolDesc* tab, const BlockMap& map,
 void launch_iteration_batch(hipStream_t s, const SweepArgs* sweep_tab, const FactorLArgs* fl_tab,
                             const FactorUArgs* fu_tab, const BlockMap& sweep_map, const BlockMap& factor_map, int rpw);
 void launch_init_append(hipStream_t s, const IterCtx& ic, int t);
-void launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub);
+// One greedy iteration (group sweep, k_factor_l, k_factor_u).  With marks (four events), events are recorded
+// before the sweep, before each factor kernel and after the last.  Returns 1 if the sweep was launched.
+int launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub, const hipEvent_t* marks = nullptr);
 int multi_padded_r(int rc);
 // Weights of the kept support set for the displacements disp (nb, 3):
 // W = M^T (M Delta_S) into sp.wx/wy/wz.  Buffers hold n * multi_padded_r(3) doubles each.

@@ -1,8 +1,11 @@
 // HIP kernels for gfx950: RBF interpolant sweeps (Eq. 1 / Eq. 6), group
 // argmax (Algorithm 1), starting-node rule, inverse-factor append and the
-// FP64 certificate.  Every lane owns one target point; support data is
-// wave-uniform, so the pair loops read it through the scalar cache (SGPR
-// operands of the VALU ops) and need neither LDS staging nor barriers.
+// FP64 certificate.  In the volume sweeps, the certificate and the
+// large-group sweep every lane owns one target point and the support data is
+// wave-uniform, read through the scalar cache (SGPR operands of the VALU
+// ops) with no LDS staging; the group sweeps of smaller groups split each
+// target's supports over the lanes of a wave and stage windows of supports
+// in LDS between barriers.
 #include "gcb_internal.h"
 #include "gcb_kernels.h"
 #include "gcb_device.h"
@@ -1562,17 +1565,24 @@ int sweep_blocks(int gmax) {
     return best;
 }
 
-void launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub) {
+int launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub, const hipEvent_t* marks) {
     const SweepArgs A = make_sweep_args(ic, g);
     // above 8,192 targets the lanes form has at least 129 blocks of 64 targets; below, too few to fill the chip
     const bool lanes = A.T > 8192;
     const int nrec = A.T > 0 ? (lanes ? sweep_lanes_blocks(A.T) : sweep_nblocks(A.T)) : 0;
+    if (marks) (void)hipEventRecord(marks[0], s);
     if (A.T > 0) {
         if (lanes) GCB_LAUNCH(k_sweep_lanes, dim3(nrec), dim3(kBlock), s, A);
         else if (A.tpl > 1) GCB_LAUNCH(k_sweep_wide, dim3(nrec), dim3(kBlock), s, A);
         else GCB_LAUNCH(k_sweep, dim3(nrec), dim3(kBlock), s, A);
     }
-    launch_factor(s, ic, factor_blocks(n_ub), -1, g, nrec);
+    const int grid = factor_blocks(n_ub);
+    if (marks) (void)hipEventRecord(marks[1], s);
+    GCB_LAUNCH(k_factor_l, dim3(grid), dim3(kBigBlock), s, make_factor_l_args(ic, g, nrec, -1));
+    if (marks) (void)hipEventRecord(marks[2], s);
+    GCB_LAUNCH(k_factor_u, dim3(grid), dim3(kBigBlock), s, make_factor_u_args(ic));
+    if (marks) (void)hipEventRecord(marks[3], s);
+    return A.T > 0;
 }
 
 void launch_iteration_batch(hipStream_t s, const SweepArgs* sweep_tab, const FactorLArgs* fl_tab,

@@ -340,6 +340,11 @@ void warm_begin(gcb_ctx* ctx) {
 
 // Stage the boundary, allocate, pick and append the three starting nodes.
 void select_begin(gcb_ctx* ctx) {
+    for (int q = 0; q < 4; ++q) {
+        ctx->ktime_ms[q] = 0.0;
+        ctx->ktime_n[q] = 0;
+    }
+    ctx->ktime_valid = false;
     if (ctx->params.warm_start) {
         warm_begin(ctx);
         return;
@@ -425,11 +430,21 @@ void select_end(gcb_ctx* ctx, gcb_select_info* info) {
     inf.pairs_append = h.pairs_append;
     // FP64 certificate over all boundary nodes
     ensure_red(ctx);
+    const bool ktime = ctx->ktime_on && ctx->ktime_ev.size() >= 2;
+    if (ktime) HIPCHK(ctx, hipEventRecord(ctx->ktime_ev[ctx->ktime_ev.size() - 2], ctx->stream));
     launch_certify(ctx->stream, bd, ctx->sp, h.n, ctx->red, ctx->red + ctx->red_cap - 2);
     HIPCHK(ctx, hipGetLastError());
+    if (ktime) HIPCHK(ctx, hipEventRecord(ctx->ktime_ev.back(), ctx->stream));
     double mr[2];
     HIPCHK(ctx, hipMemcpyAsync(mr, ctx->red + ctx->red_cap - 2, sizeof(mr), hipMemcpyDeviceToHost, ctx->stream));
     sync(ctx);
+    if (ktime) {
+        float t = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&t, ctx->ktime_ev[ctx->ktime_ev.size() - 2], ctx->ktime_ev.back()));
+        ctx->ktime_ms[3] += t;
+        ctx->ktime_n[3] += 1;
+        ctx->ktime_valid = true;
+    }
     float ms = 0.f;
     HIPCHK(ctx, hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
     inf.ms_select = ms;
@@ -447,15 +462,29 @@ void select_end(gcb_ctx* ctx, gcb_select_info* info) {
     if (info) *info = inf;
 }
 
-// Iterations per captured chunk: a multiple of m (every chunk starts at the same
-// phase of k mod m), about 64; 0 when chunks are not captured.
+// Iterations per captured chunk, 0 when chunks are not captured.  A chunk
+// bakes in the group of every iteration, so its length c divides into the
+// schedule: for m <= 256 a multiple of m of about 64 (every chunk starts at
+// the same phase of k mod m: one graph); above, a divisor of m in [32, 128]
+// (m / c phases, one graph each); none when m has no such divisor.
 int graph_chunk(const gcb_ctx* ctx) {
     const int m = ctx->params.m;
-    return (g_tuning.use_graph && m <= 256) ? m * ((64 + m - 1) / m) : 0;
+    if (!g_tuning.use_graph) return 0;
+    if (m <= 256) return m * ((64 + m - 1) / m);
+    int best = 0;
+    for (int c = 32; c <= 128; ++c)
+        if (m % c == 0 && (best == 0 || std::abs(c - 64) < std::abs(best - 64))) best = c;
+    return best;
 }
 
-// Enqueue `chunk` iterations from ctx->k_host as one captured graph (captured
-// again when anything it baked in has changed).
+void clear_chunk_graphs(gcb_ctx* ctx) {
+    for (auto& pe : ctx->chunk_execs) (void)hipGraphExecDestroy(pe.second);
+    ctx->chunk_execs.clear();
+}
+
+// Enqueue `chunk` iterations from ctx->k_host as one captured graph, kept per
+// phase k mod m of its first iteration (all are captured again when anything
+// else they baked in has changed).
 void launch_chunk(gcb_ctx* ctx, int chunk) {
     const gcb_params& p = ctx->params;
     const int m = p.m;
@@ -463,26 +492,56 @@ void launch_chunk(gcb_ctx* ctx, int chunk) {
     const IterCtx ic = make_ic(ctx);
     int64_t tol_bits;
     std::memcpy(&tol_bits, &p.tol_abs, sizeof(tol_bits));
-    // everything the captured launches baked in: phase, capacities, buffers, parameters
-    const std::vector<int64_t> full = {k % m, m, chunk, ctx->sp.cap, ctx->log_cap, p.nc_max, tol_bits,
-                                       (int64_t)ctx->alloc_gen, (int64_t)(intptr_t)ctx->stream};
-    if (!ctx->chunk_exec || ctx->chunk_key != full) {
-        if (ctx->chunk_exec) (void)hipGraphExecDestroy(ctx->chunk_exec);
-        ctx->chunk_exec = nullptr;
+    // everything else the captured launches baked in: capacities, buffers, parameters
+    const std::vector<int64_t> key = {m, chunk, ctx->sp.cap, ctx->log_cap, p.nc_max, tol_bits,
+                                      (int64_t)ctx->alloc_gen, (int64_t)(intptr_t)ctx->stream};
+    if (ctx->chunk_key != key) {
+        clear_chunk_graphs(ctx);
+        ctx->chunk_key = key;
+    }
+    const int64_t phase = k % m;
+    hipGraphExec_t exec = nullptr;
+    for (auto& pe : ctx->chunk_execs)
+        if (pe.first == phase) exec = pe.second;
+    if (!exec) {
         if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
         hipGraph_t graph;
         HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
         const int n_ub = (int)std::min<int64_t>(p.nc_max, ctx->sp.cap);
         for (int it = 0; it < chunk; ++it) launch_iteration(ctx->cap_stream, ic, (int)((k + it) % m), n_ub);
         HIPCHK(ctx, hipStreamEndCapture(ctx->cap_stream, &graph));
-        hipError_t e = hipGraphInstantiate(&ctx->chunk_exec, graph, nullptr, nullptr, 0);
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIPCHK(ctx, e);
-        ctx->chunk_key = full;
+        ctx->chunk_execs.emplace_back(phase, exec);
     }
-    HIPCHK(ctx, hipGraphLaunch(ctx->chunk_exec, ctx->stream));
+    HIPCHK(ctx, hipGraphLaunch(exec, ctx->stream));
     HIPCHK(ctx, hipGetLastError());
     ctx->k_host = k + chunk;
+}
+
+// Kernel timing: events between the launches of `chunk` iterations (4 per iteration, reused every chunk).
+void ktime_events(gcb_ctx* ctx, int chunk) {
+    while ((int)ctx->ktime_ev.size() < 4 * chunk + 2) {
+        hipEvent_t e;
+        HIPCHK(ctx, hipEventCreate(&e));
+        ctx->ktime_ev.push_back(e);
+    }
+}
+
+// Adds the device times of the chunk just launched (waits for it).
+void ktime_collect(gcb_ctx* ctx, int chunk, const std::vector<int>& swept) {
+    sync(ctx);
+    for (int it = 0; it < chunk; ++it) {
+        const hipEvent_t* e = &ctx->ktime_ev[4 * it];
+        for (int q = 0; q < 3; ++q) {
+            if (q == 0 && !swept[it]) continue;
+            float t = 0.f;
+            HIPCHK(ctx, hipEventElapsedTime(&t, e[q], e[q + 1]));
+            ctx->ktime_ms[q] += t;
+            ctx->ktime_n[q] += 1;
+        }
+    }
 }
 
 void run_select(gcb_ctx* ctx, gcb_select_info* info) {
@@ -493,10 +552,13 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     // same phase of k mod m every time and is captured once into a graph.
     const int m = p.m;
     const int every = p.monitor_every;
-    const int gchunk = every > 0 ? 0 : graph_chunk(ctx);
+    const bool ktime = ctx->ktime_on;
+    const int gchunk = (every > 0 || ktime) ? 0 : graph_chunk(ctx);
     const int chunk = gchunk > 0 ? gchunk : 64;
     const int64_t k0 = ctx->k_host;   // loop start (3, or |S0| for a warm start)
     if (every > 0) ensure_red(ctx);
+    std::vector<int> swept(ktime ? chunk : 0, 0);
+    if (ktime) ktime_events(ctx, chunk);
     for (;;) {
         HIPCHK(ctx, hipMemcpyAsync(ctx->state_pin, ctx->state, sizeof(GState), hipMemcpyDeviceToHost, ctx->stream));
         sync(ctx);
@@ -508,7 +570,9 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
             const IterCtx ic = make_ic(ctx);
             for (int it = 0; it < chunk; ++it) {
                 const int n_ub = (int)n_upper(ctx, ctx->state_h.n, it + 1);
-                launch_iteration(ctx->stream, ic, (int)((k + it) % m), n_ub);
+                const int sw = launch_iteration(ctx->stream, ic, (int)((k + it) % m), n_ub,
+                                                ktime ? &ctx->ktime_ev[4 * it] : nullptr);
+                if (ktime) swept[it] = sw;
                 const int64_t done_iters = k + it + 1 - k0;   // loop iterations launched so far
                 if (every > 0 && done_iters % every == 0) {
                     const int64_t s = done_iters / every - 1;
@@ -518,6 +582,7 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
             }
             HIPCHK(ctx, hipGetLastError());
             ctx->k_host = k + chunk;
+            if (ktime) ktime_collect(ctx, chunk, swept);
         }
     }
     select_end(ctx, info);
@@ -955,7 +1020,8 @@ void gcb_destroy(gcb_ctx* ctx) {
     dfree(ctx->state); dfree(ctx->argrec); dfree(ctx->red); dfree(ctx->irec); dfree(ctx->Pb);
     dfree(ctx->log_group); dfree(ctx->log_node); dfree(ctx->log_err); dfree(ctx->log_app); dfree(ctx->mon);
     if (ctx->tmp) (void)hipFree(ctx->tmp);
-    if (ctx->chunk_exec) (void)hipGraphExecDestroy(ctx->chunk_exec);
+    clear_chunk_graphs(ctx);
+    for (hipEvent_t e : ctx->ktime_ev) (void)hipEventDestroy(e);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
     if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -1222,6 +1288,25 @@ int gcb_deform_noalloc(gcb_ctx* ctx, int64_t nv, const void* xyz, int in_dtype, 
         launch_volume_noalloc(ctx->stream, nv, xyz, in_dtype == GCB_F64, ctx->bd.inv_r, ctx->sp, (int)n, out,
                               out_dtype == GCB_F64, ctx->params.precision == GCB_PREC_FP32_EVAL, scr);
         HIPCHK(ctx, hipGetLastError());
+        return GCB_OK;
+    });
+}
+
+int gcb_set_kernel_timing(gcb_ctx* ctx, int32_t on) {
+    return guard(ctx, [&] {
+        if (on != 0 && on != 1) fail(ctx, GCB_E_INVALID, "on must be 0 or 1");
+        ctx->ktime_on = on != 0;
+        return GCB_OK;
+    });
+}
+
+int gcb_get_kernel_times(gcb_ctx* ctx, double* ms, int64_t* launches) {
+    return guard(ctx, [&] {
+        if (!ctx->ktime_valid) fail(ctx, GCB_E_STATE, "no selection ran with kernel timing on");
+        for (int q = 0; q < 4; ++q) {
+            if (ms) ms[q] = ctx->ktime_ms[q];
+            if (launches) launches[q] = ctx->ktime_n[q];
+        }
         return GCB_OK;
     });
 }

@@ -78,8 +78,13 @@ def config_wing(nv: int = 3_000_000, with_volume: bool = True, m: int = 107, n_c
                    xyz.shape[0], vol)
 
 
-def config_wing_large(nv: int = 20_000_000, with_volume: bool = True, m: int = 160) -> Problem:
-    """Wing at Nb = (2*301-2)*500 = 300,000, Nv = 20,000,000, R = 1.5 c_r, tol 1e-5."""
+def config_wing_large(nv: int = 20_000_000, with_volume: bool = True, m: int = 399) -> Problem:
+    """Wing at Nb = (2*301-2)*500 = 300,000, Nv = 20,000,000, R = 1.5 c_r, tol 1e-5.
+
+    m comes from the same pilot rule as the 80,000-node wing: a pilot run at
+    m0 = 40 gives Nc0 = 1,129, so m = round(1.5 * 300000 / 1129) = 399; the
+    final Nc = 1,176 keeps m inside [Nb/Nc, 2 Nb/Nc] = [255, 510] (Section 4.1).
+    """
     return config_wing(nv=nv, with_volume=with_volume, m=m, n_chord=301, n_span=500, seed=SEED_WING_LARGE)
 
 

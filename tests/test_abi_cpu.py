@@ -33,7 +33,7 @@ def test_version_string():
     assert "gfx950" in gcb.version()
 
 
-@pytest.mark.parametrize("nb,m,seed", [(2000, 10, 1), (80000, 107, 2), (300000, 160, 3), (3, 1, 0), (17, 17, 9),
+@pytest.mark.parametrize("nb,m,seed", [(2000, 10, 1), (80000, 107, 2), (300000, 399, 3), (3, 1, 0), (17, 17, 9),
                                        (1001, 7, 0xFFFFFFFFFFFFFFFF)])
 def test_partition_bit_exact_with_oracle(nb, m, seed):
     """Section 3 partition: identical group of every node for the same seed."""

@@ -37,7 +37,15 @@ def test_bench_line_has_the_contract_fields():
     rf = d["roofline"]
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in rf, k
-    assert rf["bound"] == "alu" and rf["unit"] == "TFLOP/s" and abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-12
+    assert (rf["bound"], rf["unit"]) in (("alu", "TFLOP/s"), ("hbm", "GB/s"))
+    assert abs(rf["frac"] - rf["achieved"] / rf["peak"]) < 1e-12
+    # one roofline per kernel of the step; the headline one is the kernel with the most device time per step
+    names = [e["kernel"] for e in d["rooflines"]]
+    assert names == ["k_volume64", "k_sweep", "k_factor_l", "k_factor_u", "k_certify"]
+    assert rf["kernel"] == max(d["rooflines"], key=lambda e: e.get("rocprof_ms_per_step", e["ms_per_step"]))["kernel"]
+    for e in d["rooflines"]:
+        assert e["launches_per_step"] >= 1 and e["avg_launch_ms"] > 0 and e["frac"] > 0
+    assert d["kernel_timing_run"]["same_result_as_timed_steps"]
     # pair-evaluations per step times steps per second equals the value
     pairs = d["pairs"]["group"] + d["pairs"]["append"] + d["pairs"]["volume"]
     assert abs(pairs / (d["ms_per_step"] * 1e-3) - d["value"]) <= 1e-6 * d["value"]

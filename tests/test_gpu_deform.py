@@ -99,7 +99,7 @@ def test_wing_volume_sampled_full_size():
 
 
 def test_wing_large_full_size():
-    """Precision-scaling case: 300,000-node wing (m = 160, R = 1.5 root chord, E* = 1e-5 max|d|)
+    """Precision-scaling case: 300,000-node wing (m = 399, R = 1.5 root chord, E* = 1e-5 max|d|)
     and 20,000,000 volume points: selection against the oracle (identical or certified by
     replay), Eq. (6) on 20,000 sampled points against the oracle's FP64 sum."""
     torch = _torch()

@@ -208,3 +208,40 @@ def test_large_groups_against_the_oracle(m):
     r = oracle_select(p, m=m)
     assert_same_run(p, info, S, W, log, r, p.tol_abs, m)
     ctx.close()
+
+
+@pytest.mark.parametrize("m", [300, 263])
+def test_group_counts_above_256(m):
+    """m = 300 replays captured chunks of 60 iterations in five phases of k mod m; m = 263 (prime, no
+    divisor in [32, 128]) launches its iterations uncaptured.  Both against the oracle."""
+    p = synth.config_wing(with_volume=False, m=m)
+    ctx, info, S, W, log = gpu_select(p)
+    r = oracle_select(p)
+    assert_same_run(p, info, S, W, log, r, p.tol_abs, m)
+    ctx.close()
+
+
+def test_kernel_timing_keeps_the_selection():
+    """With kernel timing on, the selection runs uncaptured with events between its launches: the same
+    support sequence and weights, bitwise; one launch of each factor kernel per iteration (iterations past the
+    stop included), one certificate."""
+    p = synth.config_small_ellipsoid(with_volume=False)
+    ctx, info, S, W, log = gpu_select(p)
+    ctx.set_kernel_timing(True)
+    info2 = ctx.select()
+    S2, W2 = ctx.get_support()
+    kt = ctx.kernel_times()
+    ctx.set_kernel_timing(False)
+    assert np.array_equal(S, S2) and np.array_equal(W, W2) and info2["iterations"] == info["iterations"]
+    assert kt["k_factor_l"]["launches"] == kt["k_factor_u"]["launches"] >= info2["iterations"]
+    assert 0 < kt["sweep"]["launches"] <= kt["k_factor_l"]["launches"]
+    assert kt["certificate"]["launches"] == 1
+    assert all(v["ms"] > 0 for v in kt.values())
+    info3 = ctx.select()
+    S3, W3 = ctx.get_support()
+    assert np.array_equal(S, S3) and np.array_equal(W, W3)
+    fresh = gcb.Context(0)
+    with pytest.raises(gcb.GcbError):   # no selection ran with kernel timing on
+        fresh.kernel_times()
+    fresh.close()
+    ctx.close()
