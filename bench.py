@@ -57,6 +57,8 @@ def parse():
                     help="also replay the stream at this arrival rate (req/s), above one-at-a-time capacity (0: skip)")
     ap.add_argument("--m-sweep", default="1,5,10,20,40,80,107,160",
                     help="also select the wing at these group counts m (the paper's m-sweep, free Nc; '' skips)")
+    ap.add_argument("--per-iter", default="1,2,4,8,16",
+                    help="also select with these nodes per iteration (the several-nodes variant; '' skips)")
     ap.add_argument("--no-host-buffers", dest="host_buffers", action="store_false",
                     help="skip the PCIe-inclusive step with host inputs and output")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -695,6 +697,42 @@ def m_sweep_section(ctx, p, ms_list):
             f"history_m{p.m}": history}
 
 
+def per_iter_section(ctx, p, ps, check_oracle):
+    """The several-nodes-per-iteration variant (the block form of the peak-selection idea cited in Section 1):
+    per p, the warm selection time (second of two runs), iterations, Nc and the certificate; with check_oracle
+    the support sequence against oracle.select(per_iter = p), certified by the oracle's block replay where it
+    differs.  p = 1 is Algorithm 1."""
+    rows = []
+    for pp in ps:
+        ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed, per_iter=pp)
+        ctx.select()
+        inf = ctx.select()
+        row = {"p": pp, "nc": inf["nc"], "iterations": inf["iterations"], "select_ms": inf["ms_select"],
+               "us_per_iteration": 1e3 * inf["ms_select"] / max(inf["iterations"], 1),
+               "pairs_greedy": inf["pairs_group"] + inf["pairs_append"], "converged": bool(inf["converged"]),
+               "final_max_err_rel": inf["final_max_err"] / p.max_disp}
+        if check_oracle:
+            import oracle
+            S, _ = ctx.get_support()
+            lg = ctx.get_log()
+            r = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed, per_iter=pp,
+                              nthreads=os.cpu_count() or 1)
+            same = len(r.S) == len(S) and bool(np.array_equal(r.S, S))
+            row["same_support_sequence"] = same
+            if not same:
+                bad, reason, _ = oracle.validate_block(p.xyz, p.disp, p.radius, p.m, p.tol_abs, S, lg.group,
+                                                       lg.appended, 1e-9 * p.max_disp, pp, seed=p.seed,
+                                                       nthreads=os.cpu_count() or 1)
+                row["certified"] = bad == -1
+        rows.append(row)
+    base = next((r["select_ms"] for r in rows if r["p"] == 1), None)
+    for r in rows:
+        r["speedup_vs_p1"] = base / r["select_ms"] if base else None
+    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
+    ctx.select()
+    return rows
+
+
 def wing80k_section(a, dev, stream):
     """The 80,000-node wing with 3,000,000 points: its own timed steps, per-kernel rooflines, FP32 evaluation,
     the 64-mode batch and the m-sweep on its supports, and its outputs against the oracle."""
@@ -727,6 +765,8 @@ def wing80k_section(a, dev, stream):
         rec["modes"] = modes_section(ctx, p, xyz, vol, a.modes, not a.no_cpu_baseline, stream)
     if a.m_sweep:
         rec["m_sweep"] = m_sweep_section(ctx, p, [int(x) for x in a.m_sweep.split(",")])
+    if a.per_iter:
+        rec["per_iter"] = per_iter_section(ctx, p, [int(x) for x in a.per_iter.split(",")], not a.no_cpu_baseline)
     ctx.close()
     return rec
 
@@ -803,6 +843,8 @@ def main():
         rec["accuracy"]["vs_oracle"] = vs_oracle_record(ctx, p, out, r_orc, ref)
     rec["volume_fp32_eval"] = fp32_section(ctx, p, vol, out, ref)
     rec["volume_fp32_eval"]["speedup_vs_fp64"] = srec["phases_ms"]["volume"] / rec["volume_fp32_eval"]["ms"]
+    if a.per_iter:
+        rec["per_iter"] = per_iter_section(ctx, p, [int(x) for x in a.per_iter.split(",")], not a.no_cpu_baseline)
     if a.config == "wing":
         # the 80,000-node wing is the headline: its mode batch and m-sweep join the top level
         if a.modes > 0:

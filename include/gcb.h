@@ -73,7 +73,19 @@ typedef struct {
     int32_t monitor_every; /* > 0: after every that many loop iterations record the all-node max and RMS
                             * error with the current W (gcb_get_monitor); never alters the selection,
                             * and turns off captured chunks; not with batches.  0: off */
+    int32_t per_iter;    /* nodes one iteration may append.  0 or 1: Algorithm 1.  2 ..
+                          * GCB_MAX_PER_ITER: the several-nodes-per-iteration variant, a block form
+                          * of the peak-selection idea cited in Section 1 (not Algorithm 1): the
+                          * nodes of G_i \ S whose error exceeds E* are ranked by (error
+                          * descending, original index ascending) on one sweep, and the first
+                          * per_iter of them (fewer at nc_max) are appended together; an iteration
+                          * with no such node is quiet, and the stopping rule is unchanged.  The
+                          * log's appended[] then holds the count.  Not with warm starts, batches
+                          * or the server (GCB_E_INVALID) */
 } gcb_params;
+
+/* Largest per_iter of the several-nodes-per-iteration variant. */
+#define GCB_MAX_PER_ITER 16
 
 typedef struct {
     int64_t nc;              /* |S| */

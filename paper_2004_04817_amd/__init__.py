@@ -39,6 +39,7 @@ EXPORTS = ["gcb_version", "gcb_partition", "gcb_create", "gcb_destroy", "gcb_las
            "gcb_set_kernel_timing", "gcb_get_kernel_times"]
 
 GCB_NOALLOC_MAX_SUPPORTS = 8192
+GCB_MAX_PER_ITER = 16
 
 
 class GcbError(RuntimeError):
@@ -50,7 +51,8 @@ class GcbError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("radius", C.c_double), ("m", C.c_int32), ("seed", C.c_uint64), ("tol_abs", C.c_double),
                 ("nc_max", C.c_int64), ("precision", C.c_int32), ("use_init", C.c_int32),
-                ("init_idx", C.c_int64 * 3), ("warm_start", C.c_int32), ("monitor_every", C.c_int32)]
+                ("init_idx", C.c_int64 * 3), ("warm_start", C.c_int32), ("monitor_every", C.c_int32),
+                ("per_iter", C.c_int32)]
 
 
 class SelectInfo(C.Structure):
@@ -268,9 +270,12 @@ class Context:
         self._check(lib().gcb_set_displacement(self._h, pd, md))
 
     def set_params(self, radius: float, m: int, tol_abs: float, nc_max: int | None = None, seed: int = 0,
-                   precision: int = GCB_PREC_FP64, init_idx=None, warm_start: bool = False, monitor_every: int = 0):
+                   precision: int = GCB_PREC_FP64, init_idx=None, warm_start: bool = False, monitor_every: int = 0,
+                   per_iter: int = 0):
         """warm_start: start from the support set of the last finished selection (same
-        boundary, radius, m and seed; new displacements via set_displacement)."""
+        boundary, radius, m and seed; new displacements via set_displacement).
+        per_iter > 1: the several-nodes-per-iteration variant (up to per_iter nodes appended
+        per iteration; the log's appended entries are counts)."""
         p = Params()
         p.radius = float(radius)
         p.m = int(m)
@@ -284,6 +289,7 @@ class Context:
                 p.init_idx[t] = int(init_idx[t])
         p.warm_start = 1 if warm_start else 0
         p.monitor_every = int(monitor_every)
+        p.per_iter = int(per_iter)
         self._check(lib().gcb_set_params(self._h, C.byref(p)))
 
     def set_groups(self, group_of):

@@ -19,6 +19,9 @@ constexpr int kRowsL = kBigBlock / 64;   // rows (columns) of M per factor block
 constexpr int kMaxRowsPerWave = 4;       // rounds of kRowsL rows a factor block may hold
 constexpr int kBWindow = 4096;       // phi-vector entries staged in LDS at a time
 constexpr double kSingularTol = 64.0 * 2.220446049250313e-16;  // phi0 - l.l below this: not SPD
+constexpr int kMaxPerIter = GCB_MAX_PER_ITER;   // nodes one iteration of the block variant may append
+// block partials per 16-row chunk of the block append: b_t.W (3 per node) and lambda_t.lambda_u (a full square)
+constexpr int kBlkPart = 3 * kMaxPerIter + kMaxPerIter * kMaxPerIter;
 
 // Greedy state, resident in device memory.  Only the kernel that commits an
 // iteration writes k and n, so every block of the other kernels sees the
@@ -51,6 +54,17 @@ struct IterRec {
     double E;             // group maximum error
     double x, y, z;       // the node's scaled coordinates
     double dx, dy, dz;    // its prescribed displacement
+};
+
+// What one iteration of the several-nodes-per-iteration variant decided: the q nodes to append, in rank
+// order (written by the selection kernel, read by the two append kernels).
+struct BlockRec {
+    int32_t n;            // |S| before the append
+    int32_t q;            // nodes to append (0: none)
+    int32_t pad0, pad1;
+    int32_t pos[kMaxPerIter], orig[kMaxPerIter];
+    double x[kMaxPerIter], y[kMaxPerIter], z[kMaxPerIter];
+    double dx[kMaxPerIter], dy[kMaxPerIter], dz[kMaxPerIter];
 };
 
 // Per-block argmax record.
@@ -124,6 +138,9 @@ struct gcb_ctx {
     gcb::IterRec *irec = nullptr;    // device, the current iteration's record
     double *Pb = nullptr;            // block partials of the factor kernels
     int64_t Pb_cap = 0;
+    double *lam = nullptr;           // block variant: Lambda = M B, (cap, kMaxPerIter) by rows
+    int64_t lam_cap = 0;
+    gcb::BlockRec *brec = nullptr;   // block variant: the iteration's decision
     gcb::ArgRec *argrec = nullptr;   // device, per-block records of the sweeps
     int64_t argrec_cap = 0;
     // per-iteration log (device)

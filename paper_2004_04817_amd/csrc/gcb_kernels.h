@@ -35,6 +35,31 @@ struct SweepArgs {
     SupportView sv;
     int64_t nub;      // upper bound of |S| at this iteration (<= capacity): extent of the first staged window
     ArgRec* rec;
+    int ptop;         // block variant: records per block (its best candidates, in rank order); 0 otherwise
+};
+
+// The block variant's two append kernels (the first also ranks the sweep's records and decides).
+struct FactorBlkArgs {
+    GState* st;
+    BlockRec* brec;
+    SupportMut sm;
+    double* Mc;
+    int64_t cap;
+    double* lam;       // Lambda = M B, column-major: entry (i, t) at t * cap + i
+    double* Pb;
+    uint8_t* inS;
+    const ArgRec* srec;
+    int nrec;
+    int ptop;          // nodes the rule may append (per_iter)
+    int32_t m;
+    int g;
+    double tol_abs;
+    int64_t nc_max;
+    int32_t* log_group;
+    int32_t* log_node;
+    double* log_err;
+    int8_t* log_app;
+    int64_t log_cap;
 };
 
 struct FactorLArgs {
@@ -108,6 +133,8 @@ struct IterCtx {
     int32_t* log_node;
     double* log_err;
     int8_t* log_app;
+    double* lam;           // block variant
+    BlockRec* brec;
 };
 
 int sweep_blocks(int gmax);
@@ -130,6 +157,9 @@ void launch_init_append(hipStream_t s, const IterCtx& ic, int t);
 // One greedy iteration (group sweep, k_factor_l, k_factor_u).  With marks (four events), events are recorded
 // before the sweep, before each factor kernel and after the last.  Returns 1 if the sweep was launched.
 int launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub, const hipEvent_t* marks = nullptr);
+// One iteration of the several-nodes-per-iteration variant (up to p nodes appended): top-p group sweep, then
+// the two block-append kernels (the first also ranks and decides).
+void launch_iteration_block(hipStream_t s, const IterCtx& ic, int g, int n_ub, int p);
 int multi_padded_r(int rc);
 // Weights of the kept support set for the displacements disp (nb, 3):
 // W = M^T (M Delta_S) into sp.wx/wy/wz.  Buffers hold n * multi_padded_r(3) doubles each.

@@ -345,12 +345,40 @@ __device__ __forceinline__ Decision decide_local(int32_t done, int32_t quiet, in
 __device__ __forceinline__ bool better_rec(const ArgRec& a, const ArgRec& b) { return better(a.e2, a.orig, b.e2, b.orig); }
 
 
+// Block variant: the wave's best `np` candidates (one per lane at most), in rank order on (e^2 descending,
+// original index ascending), written as np consecutive records; a record with e2 = -1 marks no further
+// candidate.  The first record carries the count of live candidates.  Every lane of the wave takes part.
+__device__ __forceinline__ void write_top_records(ArgRec* __restrict__ out, int np, double e2, int32_t orig,
+                                                  int32_t count, int32_t pos, double x, double y, double z,
+                                                  double dx, double dy, double dz) {
+    const int lane = threadIdx.x & 63;
+    double v = e2;
+    for (int r = 0; r < np; ++r) {
+        const Best b = wave_best(Best{v, v >= 0.0 ? orig : 0x7fffffff, lane});
+        const bool have = b.v >= 0.0;
+        if (lane == (have ? b.aux : 0)) {
+            ArgRec& o = out[r];
+            o.e2 = have ? v : -1.0;
+            o.orig = have ? orig : 0x7fffffff;
+            o.pos = pos;
+            o.count = r == 0 ? count : 0;
+            o.x = x;
+            o.y = y;
+            o.z = z;
+            o.dx = dx;
+            o.dy = dy;
+            o.dz = dz;
+        }
+        if (have && lane == b.aux) v = -1.0;   // taken
+    }
+}
+
 // Supports staged in LDS per window: all loads of a window are issued at once.
 constexpr int kStage = 1280;
 // batched launches hold many more blocks: a smaller window keeps several blocks per CU
 constexpr int kStageBatch = 256;
 
-template <int STAGE>
+template <int STAGE, bool TOPK = false>
 __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
     const GState* __restrict__ st = A.st;
     const int t0 = A.t0, T = A.T, lpt = A.lpt, tpl = A.tpl;
@@ -535,6 +563,11 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
         e2 = fma(ez, ez, fma(ey, ey, ex * ex));
     }
     const int32_t orig = clive ? corig : 0x7fffffff;
+    if constexpr (TOPK) {
+        write_top_records(rec + (size_t)bid * A.ptop, A.ptop, e2, orig, wave_isum(clive ? 1 : 0), t0 + ct, cx, cy,
+                          cz, cdx, cdy, cdz);
+        return;
+    }
     const Best b = wave_best(Best{e2, orig, lane});
     const int32_t tot = wave_isum(clive ? 1 : 0);
     if (lane == (tot > 0 ? b.aux : 0)) {
@@ -553,10 +586,14 @@ __device__ __forceinline__ void sweep_body(const SweepArgs& A, const int bid) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) { sweep_body<kStage>(A, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_sweep_top(SweepArgs A) { sweep_body<kStage, true>(A, blockIdx.x); }
 // Groups of 4,097 to 8,192 targets (two targets per lane): many more blocks, so the small window keeps several
 // blocks resident per CU.  With more than one target per lane every lane sums its supports in one sequence
 // across windows, so the window size does not change any result.
 __global__ __launch_bounds__(kBlock) void k_sweep_wide(SweepArgs A) { sweep_body<kStageBatch>(A, blockIdx.x); }
+__global__ __launch_bounds__(kBlock) void k_sweep_wide_top(SweepArgs A) {
+    sweep_body<kStageBatch, true>(A, blockIdx.x);
+}
 // Groups above 8,192 targets: one target per lane and 64 targets per block; the block's four waves take contiguous quarters
 // of the supports, read through the scalar cache (no staging, no barrier until the end), and the quarter sums
 // are added in a fixed order.  One best record per block, as in k_sweep.
@@ -564,7 +601,8 @@ constexpr int kLaneTargets = 64;
 
 int sweep_lanes_blocks(int T) { return T > 0 ? (T + kLaneTargets - 1) / kLaneTargets : 1; }
 
-__global__ __launch_bounds__(kBlock) void k_sweep_lanes(SweepArgs A) {
+template <bool TOPK>
+__device__ __forceinline__ void sweep_lanes_body(const SweepArgs& A) {
     __shared__ double part[3][4][kLaneTargets];
     const GState st = *A.st;
     if (st.done) return;
@@ -591,6 +629,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep_lanes(SweepArgs A) {
         e2 = fma(ez, ez, fma(ey, ey, ex * ex));
     }
     const int32_t orig = live ? A.perm[p] : 0x7fffffff;
+    if constexpr (TOPK) {
+        write_top_records(A.rec + (size_t)blockIdx.x * A.ptop, A.ptop, e2, orig, wave_isum(live ? 1 : 0), p, A.px[p],
+                          A.py[p], A.pz[p], A.pdx[p], A.pdy[p], A.pdz[p]);
+        return;
+    }
     const Best b = wave_best(Best{e2, orig, tl});
     const int32_t count = wave_isum(live ? 1 : 0);
     // live targets have distinct original indices, so the best lane is unique; with none, lane 0 writes
@@ -608,6 +651,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep_lanes(SweepArgs A) {
         o.dz = A.pdz[p];
     }
 }
+
+__global__ __launch_bounds__(kBlock) void k_sweep_lanes(SweepArgs A) { sweep_lanes_body<false>(A); }
+__global__ __launch_bounds__(kBlock) void k_sweep_lanes_top(SweepArgs A) { sweep_lanes_body<true>(A); }
 
 // l = M b, one wave per row of M (kRowsL rows per block); b_j = phi(|r_new -
 // s_j| / R) staged in LDS windows.  Block partials Pb[blk] = (b.W over
@@ -1074,6 +1120,467 @@ __device__ __forceinline__ void factor_u_body(const FactorUArgs& A, const int bi
 
 __global__ __launch_bounds__(kBigBlock) void k_factor_u(FactorUArgs A) { factor_u_body<1, true>(A, blockIdx.x); }
 
+// ---------------------------------------------------------------- several nodes per iteration (block variant)
+// The peak-selection idea cited in Section 1 in block form: one sweep ranks the active group's nodes over E*
+// and up to p of them are appended together.  With Phi_S = L L^T, M = L^-1, B = phi(S, new) (n x q) and
+// C = phi(new, new) (q x q), the bordered factor is [[L, 0], [Lambda^T, L22]] with Lambda = M B and
+// L22 L22^T = C - Lambda^T Lambda; the new rows of M are [-L22^-1 U^T, L22^-1] with U = M^T Lambda, and
+// W' = [W - U Z ; Z] with Z = L22^-T L22^-1 (D_new - B^T W).  The pivots of L22 are the values 1 - l.l that
+// q single appends in rank order would meet, checked against the same threshold.
+//   k_sweep_top / _wide_top / _lanes_top  each block's best candidates in rank order (SweepArgs.ptop records)
+//   k_factor_l_blk  every block: the group's best p over all records and the decision (block 0 logs it);
+//                   Lambda = M B by rows (B staged in LDS windows), per-chunk partials of B^T W, Lambda^T Lambda
+//   k_factor_u_blk  partials summed, the q x q Cholesky and inverse, U = M^T Lambda by columns, new rows, W
+
+// Order LDS accesses of one wave (its DS instructions complete in order).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The best `np` of the candidates the wave's lanes hold (KPL each; e2 < 0 marks none), in rank order, written
+// to out_*[0..np) by the winning lanes (e2 = -1, index -1 past the last candidate).  Taken candidates are
+// cleared from the lanes' registers.  Every lane of the wave takes part.
+template <int KPL>
+__device__ __forceinline__ void wave_top(double (&e)[KPL], const int32_t (&o)[KPL], const int32_t (&ix)[KPL], int np,
+                                         double* __restrict__ out_e, int32_t* __restrict__ out_o,
+                                         int32_t* __restrict__ out_ix) {
+    const int lane = threadIdx.x & 63;
+    for (int r = 0; r < np; ++r) {
+        double be = -1.0;
+        int32_t bo = 0x7fffffff, bi = -1;
+#pragma unroll
+        for (int k = 0; k < KPL; ++k)
+            if (e[k] >= 0.0 && better(e[k], o[k], be, bo)) { be = e[k]; bo = o[k]; bi = ix[k]; }
+        const Best b = wave_best(Best{be, bo, lane});
+        const bool have = b.v >= 0.0;
+        if (have && lane == b.aux) {
+            out_e[r] = be;
+            out_o[r] = bo;
+            out_ix[r] = bi;
+#pragma unroll
+            for (int k = 0; k < KPL; ++k)
+                if (e[k] >= 0.0 && o[k] == bo) e[k] = -1.0;
+        }
+        if (!have && lane == 0) {
+            out_e[r] = -1.0;
+            out_o[r] = 0x7fffffff;
+            out_ix[r] = -1;
+        }
+    }
+}
+
+constexpr int kSelRec = 8;                         // records per thread per tile of the selection kernel
+constexpr int kSelLists = kBigBlock / 64 + 1;      // the 16 wave lists and the running list
+
+// Offset in a chunk's kBlkPart partials of needed value v < 3 q + q^2 (b_t.W first, then lambda_t.lambda_u).
+__device__ __forceinline__ int blk_part_offset(int v, int q) {
+    if (v < 3 * q) return v;
+    const int y = v - 3 * q, t = y / q;
+    return 3 * kMaxPerIter + t * kMaxPerIter + (y - t * q);
+}
+
+// Every block of k_factor_l_blk ranks the group's records itself (tiles of kBigBlock * kSelRec records:
+// per wave, then merged by wave 0 into a running list) and takes Algorithm 1's decision in block form, so all
+// blocks agree with no grid-wide step; block 0 logs it and writes the decision record.  Returns q (0: no
+// append), leaves the nodes' coordinates in nd[3][Q] and |S| in *n.
+template <int Q>
+__device__ int block_select(const FactorBlkArgs& A, const GState& st, double (&nd)[3][Q], int* n_out) {
+    constexpr int kSelMerge = (kSelLists * Q + 63) / 64;
+    __shared__ double w_e[kSelLists][Q];
+    __shared__ int32_t w_o[kSelLists][Q], w_i[kSelLists][Q];
+    __shared__ int32_t s_cnt[kBigBlock / 64];
+    __shared__ int32_t s_q;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int np = A.ptop;
+    constexpr int run = kSelLists - 1;   // the running list
+    if (threadIdx.x < Q) {
+        w_e[run][threadIdx.x] = -1.0;
+        w_o[run][threadIdx.x] = 0x7fffffff;
+        w_i[run][threadIdx.x] = -1;
+    }
+    int32_t cnt = 0;
+    for (int base = 0; base < A.nrec; base += kBigBlock * kSelRec) {
+        double e[kSelRec];
+        int32_t o[kSelRec], ix[kSelRec];
+#pragma unroll
+        for (int k = 0; k < kSelRec; ++k) {
+            const int i = base + (int)threadIdx.x + kBigBlock * k;
+            const bool ok = i < A.nrec;
+            const int ii = ok ? i : 0;
+            const double ev = A.srec[ii].e2;
+            const int32_t ov = A.srec[ii].orig, cv = A.srec[ii].count;
+            e[k] = ok ? ev : -1.0;
+            o[k] = ok ? ov : 0x7fffffff;
+            ix[k] = i;
+            cnt += ok ? cv : 0;
+        }
+        wave_top<kSelRec>(e, o, ix, np, w_e[wave], w_o[wave], w_i[wave]);
+        __syncthreads();
+        if (wave == 0) {
+            double me[kSelMerge];
+            int32_t mo[kSelMerge], mi[kSelMerge];
+#pragma unroll
+            for (int k = 0; k < kSelMerge; ++k) {
+                const int x = lane + 64 * k;
+                const int li = x / Q, r = x - li * Q;
+                const bool ok = li < kSelLists && r < np;
+                me[k] = ok ? w_e[ok ? li : 0][r] : -1.0;
+                mo[k] = ok ? w_o[ok ? li : 0][r] : 0x7fffffff;
+                mi[k] = ok ? w_i[ok ? li : 0][r] : -1;
+            }
+            wave_lds_sync();
+            wave_top<kSelMerge>(me, mo, mi, np, w_e[run], w_o[run], w_i[run]);
+        }
+        __syncthreads();
+    }
+    cnt = wave_isum(cnt);
+    if (lane == 0) s_cnt[wave] = cnt;
+    __syncthreads();
+    const int n = st.n;
+    if (threadIdx.x == 0) {
+        int have = 0;
+        while (have < np && w_e[run][have] >= 0.0) ++have;
+        const double E = have > 0 ? sqrt(w_e[run][0]) : 0.0;
+        int over = 0;
+        while (over < have && sqrt(w_e[run][over]) > A.tol_abs) ++over;
+        int q = 0;
+        int32_t done = 0, quiet = st.quiet;
+        if (over > 0) {
+            if (n < A.nc_max) {
+                q = (int)min((int64_t)over, A.nc_max - n);
+                if (n + q > A.cap) {
+                    done = 4;   // factor capacity exhausted: the host reports an internal error
+                    q = 0;
+                } else {
+                    quiet = 0;
+                }
+            } else {
+                done = 2;
+            }
+        } else {
+            quiet += 1;
+        }
+        if (done == 0 && q == 0 && quiet >= A.m) done = 1;
+        if (blockIdx.x == 0) {
+            if (done != 4) {
+                uint64_t total = 0;
+                for (int w = 0; w < kBigBlock / 64; ++w) total += (uint64_t)s_cnt[w];
+                const int64_t it = st.log_len;
+                if (it < A.log_cap) {
+                    A.log_group[it] = A.g;
+                    A.log_node[it] = have > 0 ? w_o[run][0] : -1;
+                    A.log_err[it] = E;
+                    A.log_app[it] = (int8_t)q;
+                }
+                A.st->log_len = it + 1;
+                A.st->pairs_group = st.pairs_group + total * (uint64_t)n;
+            }
+            A.st->quiet = quiet;
+            A.st->done = done;
+            A.brec->n = n;
+            A.brec->q = q;
+        }
+        s_q = q;
+    }
+    __syncthreads();
+    const int q = s_q;
+    if ((int)threadIdx.x < q) {
+        const int t = threadIdx.x;
+        const ArgRec r = A.srec[w_i[run][t]];
+        nd[0][t] = r.x;
+        nd[1][t] = r.y;
+        nd[2][t] = r.z;
+        if (blockIdx.x == 0) {
+            A.brec->pos[t] = r.pos;
+            A.brec->orig[t] = r.orig;
+            A.brec->x[t] = r.x;
+            A.brec->y[t] = r.y;
+            A.brec->z[t] = r.z;
+            A.brec->dx[t] = r.dx;
+            A.brec->dy[t] = r.dy;
+            A.brec->dz[t] = r.dz;
+        }
+    }
+    __syncthreads();
+    *n_out = n;
+    return q;
+}
+
+// The selection (block_select), then Lambda = M B: one wave per row of M (kRowsL rows per block, one chunk),
+// B staged in LDS windows of kBWindow / Q supports x q nodes; then this chunk's partials of B^T W (rows of B in
+// the chunk) and Lambda^T Lambda, each summed over the chunk's rows in order.
+template <int Q>
+__global__ __launch_bounds__(kBigBlock) void k_factor_l_blk(FactorBlkArgs A) {
+    __shared__ double bw[kBWindow];
+    __shared__ double s_nd[3][Q];
+    __shared__ double s_lam[kRowsL][Q];
+    __shared__ double s_bw[kRowsL][Q][3];
+    const GState st = *A.st;
+    if (st.done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) A.brec->q = 0;
+        return;
+    }
+    if (blockIdx.x > 0 && (int)blockIdx.x * kRowsL >= st.n) return;   // no rows of M here (block 0 decides)
+    int n = 0;
+    const int q = block_select<Q>(A, st, s_nd, &n);
+    if (q <= 0) return;
+    const int i0 = blockIdx.x * kRowsL;
+    if (i0 >= n) return;
+    const int i1 = min(n, i0 + kRowsL);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const SupportMut sm = A.sm;
+    const int i = i0 + wave;
+    constexpr int wj = kBWindow / Q;   // B window stored node-major: bw[t * wj + (j - w0)]
+    const double* Mi = sm.M + (size_t)i * (i + 1) / 2;
+    double acc[Q];
+#pragma unroll
+    for (int t = 0; t < Q; ++t) acc[t] = 0.0;
+    for (int w0 = 0; w0 < i1; w0 += wj) {
+        const int w1 = min(i1, w0 + wj);
+        __syncthreads();
+        for (int x = threadIdx.x; x < (w1 - w0) * q; x += kBigBlock) {
+            const int t = x / (w1 - w0), jj = x - t * (w1 - w0), j = w0 + jj;
+            bw[t * wj + jj] = wendland_r2(dist2(s_nd[0][t], s_nd[1][t], s_nd[2][t], sm.sx[j], sm.sy[j], sm.sz[j]));
+        }
+        __syncthreads();
+        if (i < i1) {
+            const int je = min(w1, i + 1);
+            for (int j = w0 + lane; j < je; j += 64) {
+                const double m = Mi[j];
+#pragma unroll
+                for (int t = 0; t < Q; ++t)
+                    if (t < q) acc[t] = fma(m, bw[t * wj + (j - w0)], acc[t]);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < Q; ++t) {
+        if (t < q) {
+            const double lt = wave_sum(acc[t]);
+            if (lane == 0 && i < i1) {
+                A.lam[(size_t)t * A.cap + i] = lt;   // column-major: the column kernel reads it coalesced
+                s_lam[wave][t] = lt;
+            }
+        }
+    }
+    for (int x = threadIdx.x; x < (i1 - i0) * q; x += kBigBlock) {
+        const int jj = x / q, t = x - jj * q, j = i0 + jj;
+        const double b = wendland_r2(dist2(s_nd[0][t], s_nd[1][t], s_nd[2][t], sm.sx[j], sm.sy[j], sm.sz[j]));
+        s_bw[jj][t][0] = b * sm.wx[j];
+        s_bw[jj][t][1] = b * sm.wy[j];
+        s_bw[jj][t][2] = b * sm.wz[j];
+    }
+    __syncthreads();
+    double* P = A.Pb + (size_t)blockIdx.x * kBlkPart;
+    for (int x = threadIdx.x; x < 3 * q + q * q; x += kBigBlock) {
+        double v = 0.0;
+        if (x < 3 * q) {
+            const int t = x / 3, c = x - 3 * t;
+            for (int jj = 0; jj < i1 - i0; ++jj) v += s_bw[jj][t][c];
+        } else {
+            const int y = x - 3 * q, t = y / q, u = y - t * q;
+            for (int r = 0; r < i1 - i0; ++r) v = fma(s_lam[r][t], s_lam[r][u], v);
+        }
+        P[blk_part_offset(x, q)] = v;
+    }
+}
+
+// Every block sums the partials over the chunks in chunk order; wave 0 forms C - Lambda^T Lambda, its Cholesky
+// factor L22 (pivots checked), L22^-1 and Z; then one wave per column j of M: u = (M^T Lambda)_j from the
+// column-major copy, the new entries of rows n..n+q-1, and the W update.  Block 0 writes the diagonal block,
+// the new supports and their weights, and commits |S| = n + q.
+template <int Q>
+__global__ __launch_bounds__(kBigBlock) void k_factor_u_blk(FactorBlkArgs A) {
+    __shared__ double s_red[kBlkPart];
+    __shared__ double s_part[kBigBlock];
+    __shared__ double L[Q][Q], Li[Q][Q];
+    __shared__ double s_e[Q][3], s_y[Q][3], s_z[Q][3];
+    __shared__ double s_nd[6][Q];
+    __shared__ double s_dinv[Q];
+    __shared__ int32_t s_bad;
+    const int q = A.brec->q, n = A.brec->n;
+    if (q <= 0) return;
+    if (blockIdx.x > 0 && (int)blockIdx.x * kRowsL >= n) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const SupportMut sm = A.sm;
+    const int ncb = (n + kRowsL - 1) / kRowsL;
+    {
+        // the 3 q + q^2 needed sums over the chunks: thread (part, v) adds chunks part, part + parts, ... in order,
+        // then one thread per value adds the parts in order (a fixed order whatever the scheduling)
+        const int nval = 3 * q + q * q;
+        const int parts = kBigBlock / nval;
+        const int part = threadIdx.x / nval, v = threadIdx.x - part * nval;
+        if (part < parts) {
+            const int off = blk_part_offset(v, q);
+            double a = 0.0;
+#pragma unroll 4
+            for (int c = part; c < ncb; c += parts) a += A.Pb[(size_t)c * kBlkPart + off];
+            s_part[threadIdx.x] = a;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < nval) {
+            double r = 0.0;
+            for (int pp = 0; pp < parts; ++pp) r += s_part[pp * nval + threadIdx.x];
+            s_red[blk_part_offset(threadIdx.x, q)] = r;
+        }
+    }
+    if ((int)threadIdx.x < q) {
+        const int t = threadIdx.x;
+        s_nd[0][t] = A.brec->x[t];
+        s_nd[1][t] = A.brec->y[t];
+        s_nd[2][t] = A.brec->z[t];
+        s_nd[3][t] = A.brec->dx[t];
+        s_nd[4][t] = A.brec->dy[t];
+        s_nd[5][t] = A.brec->dz[t];
+    }
+    if (threadIdx.x == 0) s_bad = -1;
+    __syncthreads();
+    if (wave == 0) {
+        for (int x = lane; x < q * q; x += 64) {
+            const int t = x / q, u = x - t * q;
+            const double c = wendland_r2(dist2(s_nd[0][t], s_nd[1][t], s_nd[2][t], s_nd[0][u], s_nd[1][u], s_nd[2][u]));
+            L[t][u] = c - s_red[3 * kMaxPerIter + t * kMaxPerIter + u];
+        }
+        for (int x = lane; x < 3 * q; x += 64) {
+            const int t = x / 3, c = x - 3 * t;
+            s_e[t][c] = s_nd[3 + c][t] - s_red[3 * t + c];
+        }
+        wave_lds_sync();
+        // right-looking Cholesky of the Schur complement
+        int bad = -1;
+        for (int k = 0; k < q; ++k) {
+            const double piv = L[k][k];
+            if (!(piv > kSingularTol)) {
+                bad = k;
+                break;
+            }
+            const double rk = sqrt(piv), inv = 1.0 / rk;
+            wave_lds_sync();
+            if (lane > k && lane < q) L[lane][k] *= inv;
+            if (lane == k) L[k][k] = rk;
+            wave_lds_sync();
+            const int rem = q - k - 1;
+            for (int x = lane; x < rem * rem; x += 64) {
+                const int a = k + 1 + x / rem, b = k + 1 + x % rem;
+                if (b <= a) L[a][b] = fma(-L[a][k], L[b][k], L[a][b]);
+            }
+            wave_lds_sync();
+        }
+        if (bad >= 0) {
+            if (lane == 0) s_bad = bad;
+        } else {
+            if (lane < q) s_dinv[lane] = 1.0 / L[lane][lane];
+            wave_lds_sync();
+            // L22^-1 by forward substitution, lane c holding column c in registers
+            double col[Q];
+#pragma unroll
+            for (int r = 0; r < Q; ++r) {
+                double sacc = 0.0;
+#pragma unroll
+                for (int k = 0; k < r; ++k) sacc = fma(L[r][k], col[k], sacc);
+                col[r] = r < q ? ((r == lane ? 1.0 : 0.0) - sacc) * s_dinv[r < q ? r : 0] : 0.0;
+            }
+            if (lane < q) {
+#pragma unroll
+                for (int r = 0; r < Q; ++r)
+                    if (r < q) Li[r][lane] = col[r];
+            }
+            wave_lds_sync();
+            // Z = L22^-T (L22^-1 E)
+            if (lane < 3 * q) {
+                const int t = lane / 3, c = lane - 3 * t;
+                double y = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k)
+                    if (k <= t) y = fma(Li[t][k], s_e[k][c], y);
+                s_y[t][c] = y;
+            }
+            wave_lds_sync();
+            if (lane < 3 * q) {
+                const int t = lane / 3, c = lane - 3 * t;
+                double z = 0.0;
+#pragma unroll
+                for (int k = 0; k < Q; ++k)
+                    if (k >= t && k < q) z = fma(Li[k][t], s_y[k][c], z);
+                s_z[t][c] = z;
+            }
+        }
+    }
+    __syncthreads();
+    if (s_bad >= 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            A.st->done = 3;
+            A.st->singular_node = A.brec->orig[s_bad];
+        }
+        return;
+    }
+    const int j = blockIdx.x * kRowsL + wave;
+    if (j < n) {
+        double* col = A.Mc + (size_t)j * A.cap - (size_t)j * (j - 1) / 2;   // rows j.. of column j
+        double u[Q];
+#pragma unroll
+        for (int t = 0; t < Q; ++t) u[t] = 0.0;
+        for (int i = j + lane; i < n; i += 64) {
+            const double m = col[i - j];
+#pragma unroll
+            for (int t = 0; t < Q; ++t)
+                if (t < q) u[t] = fma(m, A.lam[(size_t)t * A.cap + i], u[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < Q; ++t)
+            if (t < q) u[t] = wave_sum(u[t]);
+        if (lane < q) {
+            double v = 0.0;
+#pragma unroll
+            for (int k = 0; k < Q; ++k)
+                if (k <= lane) v = fma(Li[lane][k], u[k], v);
+            const int r = n + lane;
+            sm.M[(size_t)r * (r + 1) / 2 + j] = -v;
+            col[r - j] = -v;
+        }
+        if (lane == 0) {
+            double wx = sm.wx[j], wy = sm.wy[j], wz = sm.wz[j];
+#pragma unroll
+            for (int t = 0; t < Q; ++t) {
+                if (t < q) {
+                    wx = fma(-u[t], s_z[t][0], wx);
+                    wy = fma(-u[t], s_z[t][1], wy);
+                    wz = fma(-u[t], s_z[t][2], wz);
+                }
+            }
+            sm.wx[j] = wx;
+            sm.wy[j] = wy;
+            sm.wz[j] = wz;
+        }
+    }
+    if (blockIdx.x == 0) {
+        for (int x = threadIdx.x; x < q * q; x += kBigBlock) {
+            const int t = x / q, u = x - t * q;
+            if (u <= t) {
+                const int r = n + t, c = n + u;
+                sm.M[(size_t)r * (r + 1) / 2 + c] = Li[t][u];
+                A.Mc[(size_t)c * A.cap - (size_t)c * (c - 1) / 2 + (r - c)] = Li[t][u];
+            }
+        }
+        if ((int)threadIdx.x < q) {
+            const int t = threadIdx.x;
+            sm.sx[n + t] = s_nd[0][t];
+            sm.sy[n + t] = s_nd[1][t];
+            sm.sz[n + t] = s_nd[2][t];
+            sm.wx[n + t] = s_z[t][0];
+            sm.wy[n + t] = s_z[t][1];
+            sm.wz[n + t] = s_z[t][2];
+            sm.orig[n + t] = A.brec->orig[t];
+            A.inS[A.brec->pos[t]] = 1;
+        }
+        if (threadIdx.x == 0) {
+            A.st->n = n + q;
+            A.st->pairs_append += (uint64_t)q * (uint64_t)n + (uint64_t)q * (uint64_t)(q - 1) / 2;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- batched iteration kernels (a10)
 // One launch advances every surface of a batch: block b belongs to surface s
 // with map.off[s] <= b < map.off[s+1]; the surface's arguments for this
@@ -1508,6 +2015,7 @@ SweepArgs make_sweep_args(const IterCtx& ic, int g) {
     A.sv = view(*ic.sp);
     A.nub = ic.sp->cap;
     A.rec = ic.srec;
+    A.ptop = 0;
     return A;
 }
 
@@ -1583,6 +2091,39 @@ int launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub, const hi
     GCB_LAUNCH(k_factor_u, dim3(grid), dim3(kBigBlock), s, make_factor_u_args(ic));
     if (marks) (void)hipEventRecord(marks[3], s);
     return A.T > 0;
+}
+
+template <int Q>
+static void launch_block_kernels(hipStream_t s, const FactorBlkArgs& F, dim3 grid) {
+    GCB_LAUNCH(k_factor_l_blk<Q>, grid, dim3(kBigBlock), s, F);
+    GCB_LAUNCH(k_factor_u_blk<Q>, grid, dim3(kBigBlock), s, F);
+}
+
+void launch_iteration_block(hipStream_t s, const IterCtx& ic, int g, int n_ub, int p) {
+    SweepArgs A = make_sweep_args(ic, g);
+    const bool lanes = A.T > 8192;
+    const int nblk = A.T > 0 ? (lanes ? sweep_lanes_blocks(A.T) : sweep_nblocks(A.T)) : 0;
+    const int cand = lanes ? kLaneTargets : (kBlock / A.lpt) * A.tpl;   // candidates one block holds
+    A.ptop = std::min(p, cand);
+    if (A.T > 0) {
+        if (lanes) GCB_LAUNCH(k_sweep_lanes_top, dim3(nblk), dim3(kBlock), s, A);
+        else if (A.tpl > 1) GCB_LAUNCH(k_sweep_wide_top, dim3(nblk), dim3(kBlock), s, A);
+        else GCB_LAUNCH(k_sweep_top, dim3(nblk), dim3(kBlock), s, A);
+    }
+    const Support& sp = *ic.sp;
+    FactorBlkArgs F;
+    F.st = ic.st; F.brec = ic.brec; F.sm = mut(*ic.sp); F.Mc = sp.Mc; F.cap = sp.cap; F.lam = ic.lam; F.Pb = ic.Pb;
+    F.inS = ic.bd->inS;
+    F.srec = ic.srec; F.nrec = nblk * A.ptop; F.ptop = p; F.m = ic.bd->m; F.g = g;
+    F.tol_abs = ic.tol_abs; F.nc_max = ic.nc_max;
+    F.log_group = ic.log_group; F.log_node = ic.log_node; F.log_err = ic.log_err; F.log_app = ic.log_app;
+    F.log_cap = ic.log_cap;
+    const dim3 grid((unsigned)factor_blocks(n_ub));
+    // kernels compiled for up to Q = 2, 4, 8, 16 nodes per iteration
+    if (p <= 2) launch_block_kernels<2>(s, F, grid);
+    else if (p <= 4) launch_block_kernels<4>(s, F, grid);
+    else if (p <= 8) launch_block_kernels<8>(s, F, grid);
+    else launch_block_kernels<16>(s, F, grid);
 }
 
 void launch_iteration_batch(hipStream_t s, const SweepArgs* sweep_tab, const FactorLArgs* fl_tab,

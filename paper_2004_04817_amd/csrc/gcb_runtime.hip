@@ -137,6 +137,21 @@ void ensure_fp32_copies(gcb_ctx* ctx) {
     dalloc(ctx, sp.fwx, sp.cap); dalloc(ctx, sp.fwy, sp.cap); dalloc(ctx, sp.fwz, sp.cap);
 }
 
+int per_iter(const gcb_ctx* ctx) { return std::max(1, ctx->params.per_iter); }
+
+// Partials of the append kernels for the current capacity (4 per 16-row chunk; kBlkPart with several nodes per
+// iteration), and the block variant's Lambda (cap x kMaxPerIter) and decision record.
+void ensure_append_buffers(gcb_ctx* ctx) {
+    const int64_t cap = ctx->sp.cap;
+    const int64_t nbl = (cap + kRowsL - 1) / kRowsL + 1;
+    const bool blk = per_iter(ctx) > 1;
+    dalloc_cap(ctx, ctx->Pb, ctx->Pb_cap, (decltype(ctx->Pb_cap))((blk ? kBlkPart : 4) * nbl));
+    if (blk) {
+        dalloc_cap(ctx, ctx->lam, ctx->lam_cap, (decltype(ctx->lam_cap))(cap * kMaxPerIter));
+        if (!ctx->brec) dalloc(ctx, ctx->brec, 1);
+    }
+}
+
 // (Re)allocate the support arrays for capacity `cap`, keeping the first n
 // supports and the first n rows of the factor (both copies).
 void grow_support(gcb_ctx* ctx, int64_t cap, int64_t n) {
@@ -172,8 +187,7 @@ void grow_support(gcb_ctx* ctx, int64_t cap, int64_t n) {
     }
     free_support(sp);
     sp = nw;
-    const int64_t nbl = (cap + kRowsL - 1) / kRowsL + 1;
-    dalloc_cap(ctx, ctx->Pb, ctx->Pb_cap, (decltype(ctx->Pb_cap))(4 * nbl));
+    ensure_append_buffers(ctx);
 }
 
 template <typename T>
@@ -208,6 +222,7 @@ void check_params(gcb_ctx* ctx) {
     if (p.precision != GCB_PREC_FP64 && p.precision != GCB_PREC_FP32_EVAL)
         fail(ctx, GCB_E_INVALID, "unknown precision");
     if (p.monitor_every < 0) fail(ctx, GCB_E_INVALID, "monitor_every must be >= 0");
+    if (p.per_iter < 0 || p.per_iter > GCB_MAX_PER_ITER) fail(ctx, GCB_E_INVALID, "per_iter must be in [0, 16]");
     if (p.use_init) {
         for (int t = 0; t < 3; ++t)
             if (p.init_idx[t] < 0 || p.init_idx[t] >= nb) fail(ctx, GCB_E_INVALID, "init_idx out of range");
@@ -259,7 +274,7 @@ void stage_boundary(gcb_ctx* ctx) {
 }
 
 int64_t n_upper(const gcb_ctx* ctx, int64_t n, int64_t iters) {
-    return std::min<int64_t>(ctx->params.nc_max, n + iters);
+    return std::min<int64_t>(ctx->params.nc_max, n + iters * per_iter(ctx));
 }
 
 IterCtx make_ic(gcb_ctx* ctx) {
@@ -278,6 +293,8 @@ IterCtx make_ic(gcb_ctx* ctx) {
     ic.log_node = ctx->log_node;
     ic.log_err = ctx->log_err;
     ic.log_app = ctx->log_app;
+    ic.lam = ctx->lam;
+    ic.brec = ctx->brec;
     return ic;
 }
 
@@ -360,7 +377,8 @@ void select_begin(gcb_ctx* ctx) {
         free_support(ctx->sp);
         grow_support(ctx, cap0, 0);
     }
-    const int64_t nrec = std::max<int64_t>(512, sweep_blocks(bd.gmax));
+    ensure_append_buffers(ctx);
+    const int64_t nrec = std::max<int64_t>(512, sweep_blocks(bd.gmax)) * per_iter(ctx);
     // the last record holds the three starting nodes
     dalloc_cap(ctx, ctx->argrec, ctx->argrec_cap, (decltype(ctx->argrec_cap))(nrec + 1));
     if (!ctx->state) dalloc(ctx, ctx->state, 1);
@@ -403,8 +421,9 @@ bool select_poll(gcb_ctx* ctx, int chunk) {
     if (h.done == 4) fail(ctx, GCB_E_DEVICE, "internal error: factor capacity exhausted inside a chunk");
     if (h.done != 0) return false;
     const gcb_params& p = ctx->params;
-    if (h.n + chunk > ctx->sp.cap && ctx->sp.cap < p.nc_max) {
-        const int64_t cap = std::min<int64_t>(p.nc_max, std::max<int64_t>(2 * ctx->sp.cap, h.n + chunk + 1));
+    const int64_t need = h.n + (int64_t)chunk * per_iter(ctx);
+    if (need > ctx->sp.cap && ctx->sp.cap < p.nc_max) {
+        const int64_t cap = std::min<int64_t>(p.nc_max, std::max<int64_t>(2 * ctx->sp.cap, need + 1));
         grow_support(ctx, cap, h.n);
     }
     if (h.log_len + chunk > ctx->log_cap) grow_log(ctx, h.log_len, std::max<int64_t>(2 * ctx->log_cap, h.log_len + chunk));
@@ -430,7 +449,7 @@ void select_end(gcb_ctx* ctx, gcb_select_info* info) {
     inf.pairs_append = h.pairs_append;
     // FP64 certificate over all boundary nodes
     ensure_red(ctx);
-    const bool ktime = ctx->ktime_on && ctx->ktime_ev.size() >= 2;
+    const bool ktime = ctx->ktime_on && per_iter(ctx) == 1 && ctx->ktime_ev.size() >= 2;
     if (ktime) HIPCHK(ctx, hipEventRecord(ctx->ktime_ev[ctx->ktime_ev.size() - 2], ctx->stream));
     launch_certify(ctx->stream, bd, ctx->sp, h.n, ctx->red, ctx->red + ctx->red_cap - 2);
     HIPCHK(ctx, hipGetLastError());
@@ -494,7 +513,7 @@ void launch_chunk(gcb_ctx* ctx, int chunk) {
     std::memcpy(&tol_bits, &p.tol_abs, sizeof(tol_bits));
     // everything else the captured launches baked in: capacities, buffers, parameters
     const std::vector<int64_t> key = {m, chunk, ctx->sp.cap, ctx->log_cap, p.nc_max, tol_bits,
-                                      (int64_t)ctx->alloc_gen, (int64_t)(intptr_t)ctx->stream};
+                                      (int64_t)ctx->alloc_gen, (int64_t)(intptr_t)ctx->stream, per_iter(ctx)};
     if (ctx->chunk_key != key) {
         clear_chunk_graphs(ctx);
         ctx->chunk_key = key;
@@ -508,7 +527,11 @@ void launch_chunk(gcb_ctx* ctx, int chunk) {
         hipGraph_t graph;
         HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
         const int n_ub = (int)std::min<int64_t>(p.nc_max, ctx->sp.cap);
-        for (int it = 0; it < chunk; ++it) launch_iteration(ctx->cap_stream, ic, (int)((k + it) % m), n_ub);
+        const int pi = per_iter(ctx);
+        for (int it = 0; it < chunk; ++it) {
+            if (pi > 1) launch_iteration_block(ctx->cap_stream, ic, (int)((k + it) % m), n_ub, pi);
+            else launch_iteration(ctx->cap_stream, ic, (int)((k + it) % m), n_ub);
+        }
         HIPCHK(ctx, hipStreamEndCapture(ctx->cap_stream, &graph));
         hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
@@ -552,7 +575,8 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     // same phase of k mod m every time and is captured once into a graph.
     const int m = p.m;
     const int every = p.monitor_every;
-    const bool ktime = ctx->ktime_on;
+    const int pi = per_iter(ctx);
+    const bool ktime = ctx->ktime_on && pi == 1;   // kernel timing covers Algorithm 1's three kernels
     const int gchunk = (every > 0 || ktime) ? 0 : graph_chunk(ctx);
     const int chunk = gchunk > 0 ? gchunk : 64;
     const int64_t k0 = ctx->k_host;   // loop start (3, or |S0| for a warm start)
@@ -570,9 +594,13 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
             const IterCtx ic = make_ic(ctx);
             for (int it = 0; it < chunk; ++it) {
                 const int n_ub = (int)n_upper(ctx, ctx->state_h.n, it + 1);
-                const int sw = launch_iteration(ctx->stream, ic, (int)((k + it) % m), n_ub,
-                                                ktime ? &ctx->ktime_ev[4 * it] : nullptr);
-                if (ktime) swept[it] = sw;
+                if (pi > 1) {
+                    launch_iteration_block(ctx->stream, ic, (int)((k + it) % m), (int)n_ub, pi);
+                } else {
+                    const int sw = launch_iteration(ctx->stream, ic, (int)((k + it) % m), n_ub,
+                                                    ktime ? &ctx->ktime_ev[4 * it] : nullptr);
+                    if (ktime) swept[it] = sw;
+                }
                 const int64_t done_iters = k + it + 1 - k0;   // loop iterations launched so far
                 if (every > 0 && done_iters % every == 0) {
                     const int64_t s = done_iters / every - 1;
@@ -621,6 +649,7 @@ size_t ctx_device_bytes(const gcb_ctx* ctx) {
     if (sp.fsx) b += 6 * sizeof(float) * (size_t)sp.cap;   // FP32 evaluation copies
     if (sp.qx) b += 4 * sizeof(double) * (size_t)sp.cap;   // volume table
     b += sizeof(double) * (size_t)ctx->Pb_cap + sizeof(ArgRec) * (size_t)ctx->argrec_cap;
+    b += sizeof(double) * (size_t)ctx->lam_cap + (ctx->brec ? sizeof(BlockRec) : 0);
     b += (size_t)ctx->log_cap * (2 * sizeof(int32_t) + 3 * sizeof(double) + 1);   // log and monitor samples
     b += sizeof(double) * (size_t)ctx->red_cap + ctx->tmp_cap + sizeof(GState) + sizeof(IterRec);
     return b;
@@ -711,6 +740,7 @@ int32_t batch_step(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, int32_t it
     BHIPCHK(b, hipSetDevice(b->device));
     for (int32_t i = 0; i < count; ++i) {
         attach(b, ctxs[i]);
+        if (ctxs[i]->params.per_iter > 1) bfail(b, GCB_E_INVALID, "per_iter > 1 is not available in batches");
         if (ctxs[i]->in_progress)
             HIPCHK(ctxs[i], hipMemcpyAsync(ctxs[i]->state_pin, ctxs[i]->state, sizeof(GState), hipMemcpyDeviceToHost,
                                            b->stream));
@@ -870,6 +900,7 @@ int gcb_batch_begin(gcb_batch* b, gcb_ctx* ctx) {
     return bguard(b, [&] {
         BHIPCHK(b, hipSetDevice(b->device));
         if (ctx && ctx->params.monitor_every > 0) bfail(b, GCB_E_INVALID, "monitor samples are not taken in batches");
+        if (ctx && ctx->params.per_iter > 1) bfail(b, GCB_E_INVALID, "per_iter > 1 is not available in batches");
         attach(b, ctx);
         return guard(ctx, [&] {
             select_begin(ctx);
@@ -1018,6 +1049,7 @@ void gcb_destroy(gcb_ctx* ctx) {
     free_boundary(ctx->bd);
     free_support(ctx->sp);
     dfree(ctx->state); dfree(ctx->argrec); dfree(ctx->red); dfree(ctx->irec); dfree(ctx->Pb);
+    dfree(ctx->lam); dfree(ctx->brec);
     dfree(ctx->log_group); dfree(ctx->log_node); dfree(ctx->log_err); dfree(ctx->log_app); dfree(ctx->mon);
     if (ctx->tmp) (void)hipFree(ctx->tmp);
     clear_chunk_graphs(ctx);
@@ -1107,6 +1139,8 @@ int gcb_set_displacement(gcb_ctx* ctx, const double* disp, int mem) {
 int gcb_set_params(gcb_ctx* ctx, const gcb_params* p) {
     return guard(ctx, [&] {
         if (!p) fail(ctx, GCB_E_INVALID, "params is NULL");
+        if (p->per_iter < 0 || p->per_iter > GCB_MAX_PER_ITER) fail(ctx, GCB_E_INVALID, "per_iter must be in [0, 16]");
+        if (p->per_iter > 1 && p->warm_start) fail(ctx, GCB_E_INVALID, "per_iter > 1 is not available with warm starts");
         ctx->params = *p;
         ctx->have_params = true;
         ctx->selected = false;
