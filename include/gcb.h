@@ -82,6 +82,13 @@ typedef struct {
                           * with no such node is quiet, and the stopping rule is unchanged.  The
                           * log's appended[] then holds the count.  Not with warm starts, batches
                           * or the server (GCB_E_INVALID) */
+    int32_t cull_volume; /* 1: gcb_deform's FP64 evaluation of Eq. (6) skips the (point, support)
+                          * pairs farther apart than R, whose phi is exactly zero (Eq. 2): the
+                          * points are evaluated in Morton order (a device radix sort), the
+                          * supports in Morton order in tiles of 32, and a wave of 64 points skips
+                          * every tile whose bounding box lies farther than R from theirs.  The
+                          * sum runs over the same non-zero terms in another order (the result
+                          * differs by rounding).  Device memory: 16 bytes per point.  0: off */
 } gcb_params;
 
 /* Largest per_iter of the several-nodes-per-iteration variant. */
@@ -196,6 +203,12 @@ int gcb_set_kernel_timing(gcb_ctx *ctx, int32_t on);
  * the event after it, so it includes that launch's dispatch on the device.
  * GCB_E_STATE if no selection ran with kernel timing on. */
 int gcb_get_kernel_times(gcb_ctx *ctx, double *ms, int64_t *launches);
+
+/* Pairs of the last culled deformation (params.cull_volume = 1): *evaluated
+ * (point, support) pairs the sweep computed, *dense = nv x nc (the pairs the
+ * plain sweep computes); either may be NULL.  Waits for the deformation.
+ * GCB_E_STATE if no culled deformation has run. */
+int gcb_get_deform_pairs(gcb_ctx *ctx, uint64_t *evaluated, uint64_t *dense);
 
 /* Largest support count gcb_deform_noalloc accepts. */
 #define GCB_NOALLOC_MAX_SUPPORTS 8192

@@ -36,7 +36,7 @@ EXPORTS = ["gcb_version", "gcb_partition", "gcb_create", "gcb_destroy", "gcb_las
            "gcb_server_clock", "gcb_server_create", "gcb_server_destroy", "gcb_server_last_error",
            "gcb_server_submit", "gcb_server_progress", "gcb_server_result", "gcb_server_forget",
            "gcb_server_memory", "gcb_deform_time", "gcb_deform_noalloc",
-           "gcb_set_kernel_timing", "gcb_get_kernel_times"]
+           "gcb_set_kernel_timing", "gcb_get_kernel_times", "gcb_get_deform_pairs"]
 
 GCB_NOALLOC_MAX_SUPPORTS = 8192
 GCB_MAX_PER_ITER = 16
@@ -52,7 +52,7 @@ class Params(C.Structure):
     _fields_ = [("radius", C.c_double), ("m", C.c_int32), ("seed", C.c_uint64), ("tol_abs", C.c_double),
                 ("nc_max", C.c_int64), ("precision", C.c_int32), ("use_init", C.c_int32),
                 ("init_idx", C.c_int64 * 3), ("warm_start", C.c_int32), ("monitor_every", C.c_int32),
-                ("per_iter", C.c_int32)]
+                ("per_iter", C.c_int32), ("cull_volume", C.c_int32)]
 
 
 class SelectInfo(C.Structure):
@@ -122,6 +122,7 @@ def lib():
         L.gcb_deform.argtypes = [vp, i64, vp, C.c_int, vp, C.c_int, C.c_int]
         L.gcb_deform_noalloc.argtypes = [vp, i64, vp, C.c_int, vp, C.c_int]
         L.gcb_set_kernel_timing.argtypes = [vp, i32]
+        L.gcb_get_deform_pairs.argtypes = [vp, vp, vp]
         L.gcb_get_kernel_times.argtypes = [vp, vp, vp]
         L.gcb_deform_multi.argtypes = [vp, i32, vp, i64, vp, C.c_int, vp, C.c_int, C.c_int]
         L.gcb_certify.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -271,11 +272,12 @@ class Context:
 
     def set_params(self, radius: float, m: int, tol_abs: float, nc_max: int | None = None, seed: int = 0,
                    precision: int = GCB_PREC_FP64, init_idx=None, warm_start: bool = False, monitor_every: int = 0,
-                   per_iter: int = 0):
+                   per_iter: int = 0, cull_volume: bool = False):
         """warm_start: start from the support set of the last finished selection (same
         boundary, radius, m and seed; new displacements via set_displacement).
         per_iter > 1: the several-nodes-per-iteration variant (up to per_iter nodes appended
-        per iteration; the log's appended entries are counts)."""
+        per iteration; the log's appended entries are counts).
+        cull_volume: FP64 deformations skip (point, support) pairs farther apart than R."""
         p = Params()
         p.radius = float(radius)
         p.m = int(m)
@@ -290,6 +292,7 @@ class Context:
         p.warm_start = 1 if warm_start else 0
         p.monitor_every = int(monitor_every)
         p.per_iter = int(per_iter)
+        p.cull_volume = 1 if cull_volume else 0
         self._check(lib().gcb_set_params(self._h, C.byref(p)))
 
     def set_groups(self, group_of):
@@ -376,6 +379,13 @@ class Context:
         self.use_current_stream(kx)
         self._check(lib().gcb_deform_noalloc(self._h, int(kx.shape[0]), px, in_dt, po, out_dt))
         return out
+
+    def deform_pairs(self) -> tuple:
+        """(evaluated, dense) (point, support) pairs of the last culled deformation."""
+        ev = C.c_uint64()
+        dn = C.c_uint64()
+        self._check(lib().gcb_get_deform_pairs(self._h, C.byref(ev), C.byref(dn)))
+        return int(ev.value), int(dn.value)
 
     def set_kernel_timing(self, on: bool):
         """Record HIP events between the greedy kernels of later selections (slower, same results)."""

@@ -7,7 +7,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["gcb_kernels.hip", "gcb_multi.hip", "gcb_runtime.hip", "gcb_server.hip", "gcb_dense.hip"]
+SOURCES = ["gcb_kernels.hip", "gcb_multi.hip", "gcb_runtime.hip", "gcb_server.hip", "gcb_dense.hip", "gcb_sort.hip"]
 LIB = os.path.join(HERE, "libgcb.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

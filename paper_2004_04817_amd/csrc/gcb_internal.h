@@ -175,6 +175,19 @@ struct gcb_ctx {
     int32_t warm_m = 0;
     uint64_t warm_seed = 0;
     int64_t warm_n = 0;
+    // compact-support culling of Eq. (6): Morton keys and point order, sorted supports and tile boxes
+    uint32_t *ck_in = nullptr, *ck_out = nullptr;
+    int32_t *ci_in = nullptr, *ci_out = nullptr;
+    int64_t cull_cap = 0;
+    double *cs = nullptr;              // 7 x cs_n sorted support entries, then 6 per tile
+    int64_t cs_cap = 0;
+    uint64_t *cull_ev = nullptr;       // evaluated pairs per block of the last culled sweep
+    int64_t cull_ev_cap = 0;
+    int64_t cull_nblk = 0;
+    uint64_t cull_dense = 0;
+    bool cull_valid = false;
+    void *sort_tmp = nullptr;
+    size_t sort_tmp_cap = 0;
     // scratch for certificate / volume
     double *red = nullptr;
     int64_t red_cap = 0;

@@ -198,6 +198,27 @@ void launch_volume32(hipStream_t s, int64_t nv, const void* xyz, int in_f64, dou
 // FP64 Eq. (6); the volume table is refreshed first (sp.qx..qq must hold sp.cap doubles).
 void launch_volume(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp, int n,
                    void* out, int out_f64);
+// Compact-support culling of Eq. (6): the frame of the points' Morton keys (in the volume table's units) and the
+// supports sorted in Morton order with the bounding box of every tile of 32.
+struct CullFrame {
+    double lox, loy, loz, sc;
+};
+struct CullSupports {
+    const double *qx, *qy, *qz, *qq, *wx, *wy, *wz;
+    const double* box;   // 6 per tile: min x, y, z, max x, y, z
+};
+constexpr int kCullTileHost = 32;
+void launch_cull_keys(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const double c0[3],
+                      const CullFrame& f, uint32_t* keys, int32_t* idx);
+void launch_volume_cull(hipStream_t s, int64_t nv, const void* xyz, int in_f64, const int32_t* order, double inv_r,
+                        const double c0[3], const CullSupports& cs, int n, void* out, int out_f64,
+                        uint64_t* evaluated);
+int cull_blocks(int64_t nv);
+// The FP64 volume table of the first n supports (scaled by 1/(2R), centred at the first support).
+void launch_volume_table(hipStream_t s, const Support& sp, int n);
+hipError_t sort_pairs_u32(void* temp, size_t* temp_bytes, const uint32_t* keys_in, uint32_t* keys_out,
+                          const int32_t* vals_in, int32_t* vals_out, int64_t n, int bits, hipStream_t s);
+
 // Allocation-free Eq. (6): the refreshed support table (FP64) or support copies (FP32 evaluation) go
 // into the module's static scratch array at scratch_ptr (n <= GCB_NOALLOC_MAX_SUPPORTS).
 void launch_volume_noalloc(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const Support& sp,

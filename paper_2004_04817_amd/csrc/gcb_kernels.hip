@@ -2207,6 +2207,166 @@ void launch_volume(hipStream_t s, int64_t nv, const void* xyz, int in_f64, doubl
     volume64_into(s, nv, xyz, in_f64, inv_r, view(sp), vtable(sp), n, out, out_f64);
 }
 
+// ---------------------------------------------------------------- compact-support culling of Eq. (6)
+// phi is exactly zero beyond R (Eq. 2), so a (target, support) pair farther apart adds nothing.  Points are
+// evaluated in Morton order of their cells (a sorted index list), supports in Morton order in tiles of
+// kCullTile with bounding boxes; a wave skips every tile whose box lies farther than R from the box of its 64
+// points.  Distances are in the volume table's units (1/(2R)), so R is 0.5; the test keeps a relative margin of
+// 1e-9, far above the rounding of the evaluated distance, so every skipped pair would have evaluated to zero.
+constexpr int kCullTile = 32;
+constexpr double kCullGap2 = 0.25 * (1.0 + 1e-9);
+
+__device__ __forceinline__ double wave_min(double v) {
+    v = fmin(v, dpp_f64<kDppXor1>(v));
+    v = fmin(v, dpp_f64<kDppXor2>(v));
+    v = fmin(v, dpp_f64<kDppHalfMirror>(v));
+    v = fmin(v, dpp_f64<kDppMirror>(v));
+    double lo, hi;
+    swap_rows_f64<false>(v, lo, hi);
+    v = fmin(lo, hi);
+    swap_rows_f64<true>(v, lo, hi);
+    return fmin(lo, hi);
+}
+
+__device__ __forceinline__ double wave_max(double v) { return -wave_min(-v); }
+
+__device__ __forceinline__ uint32_t spread10(uint32_t x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000FFu;
+    x = (x | (x << 8)) & 0x0300F00Fu;
+    x = (x | (x << 4)) & 0x030C30C3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+// Morton key of a point in the culling frame: 10 bits per axis over [lo, lo + 1023 / sc]; points outside the
+// frame (farther than R from every support along some axis) are clamped to it and get bit 30, so they sort after
+// the others, still in spatial order.
+__device__ __forceinline__ uint32_t cull_key(double ux, double uy, double uz, const CullFrame& f) {
+    const double qx = (ux - f.lox) * f.sc, qy = (uy - f.loy) * f.sc, qz = (uz - f.loz) * f.sc;
+    const bool in = qx >= 0.0 && qy >= 0.0 && qz >= 0.0 && qx <= 1023.0 && qy <= 1023.0 && qz <= 1023.0;
+    const uint32_t ix = (uint32_t)fmin(fmax(qx, 0.0), 1023.0), iy = (uint32_t)fmin(fmax(qy, 0.0), 1023.0),
+                   iz = (uint32_t)fmin(fmax(qz, 0.0), 1023.0);
+    return (in ? 0u : (1u << 30)) | spread10(ix) | (spread10(iy) << 1) | (spread10(iz) << 2);
+}
+
+template <typename TIn>
+__global__ __launch_bounds__(kBlock) void k_cull_keys(int64_t nv, const TIn* __restrict__ xyz, double h, double c0x,
+                                                      double c0y, double c0z, CullFrame f, uint32_t* __restrict__ keys,
+                                                      int32_t* __restrict__ idx) {
+    const int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (t >= nv) return;
+    const double ux = fma((double)xyz[3 * t], h, -c0x), uy = fma((double)xyz[3 * t + 1], h, -c0y),
+                 uz = fma((double)xyz[3 * t + 2], h, -c0z);
+    keys[t] = cull_key(ux, uy, uz, f);
+    idx[t] = (int32_t)t;
+}
+
+template <typename TIn, typename TOut>
+__global__ __launch_bounds__(kBlock) void k_volume64_cull(int64_t nv, const TIn* __restrict__ xyz,
+                                                          const int32_t* __restrict__ order, double h, double c0x,
+                                                          double c0y, double c0z, CullSupports cs, int n,
+                                                          TOut* __restrict__ out, uint64_t* __restrict__ evaluated) {
+    __shared__ uint64_t s_ev[kBlock / 64];
+    const int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    const bool live = t < nv;
+    const int64_t src = order[live ? t : nv - 1];
+    const double ux = fma((double)xyz[3 * src], h, -c0x), uy = fma((double)xyz[3 * src + 1], h, -c0y),
+                 uz = fma((double)xyz[3 * src + 2], h, -c0z);
+    const double mx = -2.0 * ux, my = -2.0 * uy, mz = -2.0 * uz, uu = fma(uz, uz, fma(uy, uy, ux * ux));
+    const double lox = wave_min(ux), loy = wave_min(uy), loz = wave_min(uz);
+    const double hix = wave_max(ux), hiy = wave_max(uy), hiz = wave_max(uz);
+    const double* __restrict__ qx = cs.qx;
+    const double* __restrict__ qy = cs.qy;
+    const double* __restrict__ qz = cs.qz;
+    const double* __restrict__ qq = cs.qq;
+    const double* __restrict__ wx = cs.wx;
+    const double* __restrict__ wy = cs.wy;
+    const double* __restrict__ wz = cs.wz;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    uint32_t evals = 0;
+    const int ntiles = (n + kCullTile - 1) / kCullTile;
+#pragma unroll 1
+    for (int k = 0; k < ntiles; ++k) {
+        const double* b = cs.box + 6 * k;   // min x, y, z, max x, y, z of the tile's supports
+        const double gx = fmax(0.0, fmax(b[0] - hix, lox - b[3]));
+        const double gy = fmax(0.0, fmax(b[1] - hiy, loy - b[4]));
+        const double gz = fmax(0.0, fmax(b[2] - hiz, loz - b[5]));
+        if (fma(gz, gz, fma(gy, gy, gx * gx)) > kCullGap2) continue;
+        const int j0 = k * kCullTile, j1 = min(n, j0 + kCullTile);
+        int j = j0;
+#pragma unroll 1
+        for (; j + 8 <= j1; j += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const double d = fma(mx, qx[j + u], fma(my, qy[j + u], fma(mz, qz[j + u], uu + qq[j + u])));
+                const double phi = wendland_quarter(d);
+                ax = fma(wx[j + u], phi, ax);
+                ay = fma(wy[j + u], phi, ay);
+                az = fma(wz[j + u], phi, az);
+            }
+        }
+#pragma unroll 1
+        for (; j < j1; ++j) {
+            const double d = fma(mx, qx[j], fma(my, qy[j], fma(mz, qz[j], uu + qq[j])));
+            const double phi = wendland_quarter(d);
+            ax = fma(wx[j], phi, ax);
+            ay = fma(wy[j], phi, ay);
+            az = fma(wz[j], phi, az);
+        }
+        evals += (uint32_t)(j1 - j0);
+    }
+    if (live) {
+        out[3 * src] = (TOut)ax;
+        out[3 * src + 1] = (TOut)ay;
+        out[3 * src + 2] = (TOut)az;
+    }
+    // pairs evaluated: the wave's evaluated supports times its live points
+    const int32_t nlive = wave_isum(live ? 1 : 0);
+    if ((threadIdx.x & 63) == 0) s_ev[threadIdx.x >> 6] = (uint64_t)evals * (uint64_t)nlive;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t sum = 0;
+        for (int w = 0; w < kBlock / 64; ++w) sum += s_ev[w];
+        evaluated[blockIdx.x] = sum;
+    }
+}
+
+void launch_cull_keys(hipStream_t s, int64_t nv, const void* xyz, int in_f64, double inv_r, const double c0[3],
+                      const CullFrame& f, uint32_t* keys, int32_t* idx) {
+    const unsigned g = (unsigned)((nv + kBlock - 1) / kBlock);
+    const double h = 0.5 * inv_r;
+    if (in_f64) GCB_LAUNCH(k_cull_keys<double>, dim3(g), dim3(kBlock), s, nv, (const double*)xyz, h, c0[0], c0[1],
+                           c0[2], f, keys, idx);
+    else GCB_LAUNCH(k_cull_keys<float>, dim3(g), dim3(kBlock), s, nv, (const float*)xyz, h, c0[0], c0[1], c0[2], f,
+                    keys, idx);
+}
+
+template <typename TIn, typename TOut>
+static void vol_cull(hipStream_t s, int64_t nv, const void* xyz, const int32_t* order, double h, const double c0[3],
+                     const CullSupports& cs, int n, void* out, uint64_t* evaluated) {
+    const unsigned g = (unsigned)((nv + kBlock - 1) / kBlock);
+    GCB_LAUNCH((k_volume64_cull<TIn, TOut>), dim3(g), dim3(kBlock), s, nv, (const TIn*)xyz, order, h, c0[0], c0[1],
+               c0[2], cs, n, (TOut*)out, evaluated);
+}
+
+void launch_volume_cull(hipStream_t s, int64_t nv, const void* xyz, int in_f64, const int32_t* order, double inv_r,
+                        const double c0[3], const CullSupports& cs, int n, void* out, int out_f64,
+                        uint64_t* evaluated) {
+    const double h = 0.5 * inv_r;
+    if (in_f64 && out_f64) vol_cull<double, double>(s, nv, xyz, order, h, c0, cs, n, out, evaluated);
+    else if (in_f64) vol_cull<double, float>(s, nv, xyz, order, h, c0, cs, n, out, evaluated);
+    else if (out_f64) vol_cull<float, double>(s, nv, xyz, order, h, c0, cs, n, out, evaluated);
+    else vol_cull<float, float>(s, nv, xyz, order, h, c0, cs, n, out, evaluated);
+}
+
+int cull_blocks(int64_t nv) { return (int)((nv + kBlock - 1) / kBlock); }
+
+void launch_volume_table(hipStream_t s, const Support& sp, int n) {
+    if (n > 0) GCB_LAUNCH(k_volume_table, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), s, n, view(sp),
+                          vtable(sp));
+}
+
 // ---------------------------------------------------------------- allocation-free deformation
 // The support table of the FP64 sweep (four arrays of kNoAllocSupports doubles) or the FP32 copies
 // of the supports (six arrays of kNoAllocSupports floats) live in this static array instead of in

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <cstdlib>
+#include <limits>
 #include <new>
 
 #include "gcb_internal.h"
@@ -826,6 +827,108 @@ int32_t batch_step(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, int32_t it
 namespace {
 
 // Events around the kernels of a deformation (not recorded while the stream is being captured).
+// Morton interleave of three 10-bit cell indices (supports' order for the culled sweep).
+uint32_t morton10(uint32_t x, uint32_t y, uint32_t z) {
+    auto spread = [](uint32_t v) {
+        v &= 0x3ffu;
+        v = (v | (v << 16)) & 0x030000FFu;
+        v = (v | (v << 8)) & 0x0300F00Fu;
+        v = (v | (v << 4)) & 0x030C30C3u;
+        v = (v | (v << 2)) & 0x09249249u;
+        return v;
+    };
+    return spread(x) | (spread(y) << 1) | (spread(z) << 2);
+}
+
+// Eq. (6) with compact-support culling (params.cull_volume, FP64): the volume table is formed on the device and
+// read back with the weights (7 doubles per support); the host orders the supports in Morton order, forms the
+// bounding box of every tile of kCullTileHost and uploads them; the points' Morton keys are sorted on the device
+// (radix sort of (key, index) pairs), and the culled sweep evaluates the points in that order.
+void deform_culled(gcb_ctx* ctx, int64_t nv, const void* din, bool in_f64, void* dout, bool out_f64) {
+    Support& sp = ctx->sp;
+    const int n = (int)ctx->info.nc;
+    ensure_volume_table(ctx);
+    launch_volume_table(ctx->stream, sp, n);
+    HIPCHK(ctx, hipGetLastError());
+    std::vector<double> h(7 * (size_t)n + 3);
+    const double* src[7] = {sp.qx, sp.qy, sp.qz, sp.qq, sp.wx, sp.wy, sp.wz};
+    for (int a = 0; a < 7; ++a)
+        HIPCHK(ctx, hipMemcpyAsync(h.data() + (size_t)a * n, src[a], sizeof(double) * n, hipMemcpyDeviceToHost,
+                                   ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(h.data() + 7 * (size_t)n, sp.sx, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(h.data() + 7 * (size_t)n + 1, sp.sy, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(h.data() + 7 * (size_t)n + 2, sp.sz, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    const double* q[3] = {h.data(), h.data() + n, h.data() + 2 * (size_t)n};
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = *std::min_element(q[a], q[a] + n);
+        hi[a] = *std::max_element(q[a], q[a] + n);
+    }
+    // frame: the supports' box grown by R (0.5 in these units) on every side, cubic cells
+    const double ext = std::max({hi[0] - lo[0], hi[1] - lo[1], hi[2] - lo[2]}) + 1.0;
+    CullFrame f{lo[0] - 0.5, lo[1] - 0.5, lo[2] - 0.5, 1023.0 / ext};
+    std::vector<std::pair<uint32_t, int>> key((size_t)n);
+    for (int j = 0; j < n; ++j) {
+        uint32_t c[3];
+        const double fl[3] = {f.lox, f.loy, f.loz};
+        for (int a = 0; a < 3; ++a)
+            c[a] = (uint32_t)std::min(1023.0, std::max(0.0, (q[a][j] - fl[a]) * f.sc));
+        key[(size_t)j] = {morton10(c[0], c[1], c[2]), j};
+    }
+    std::stable_sort(key.begin(), key.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    const int ntiles = (n + kCullTileHost - 1) / kCullTileHost;
+    std::vector<double> hs(7 * (size_t)n + 6 * (size_t)ntiles);
+    for (int j = 0; j < n; ++j)
+        for (int a = 0; a < 7; ++a) hs[(size_t)a * n + j] = h[(size_t)a * n + key[(size_t)j].second];
+    for (int k = 0; k < ntiles; ++k) {
+        double* b = hs.data() + 7 * (size_t)n + 6 * (size_t)k;
+        for (int a = 0; a < 3; ++a) {
+            b[a] = std::numeric_limits<double>::infinity();
+            b[3 + a] = -std::numeric_limits<double>::infinity();
+        }
+        for (int j = k * kCullTileHost; j < std::min(n, (k + 1) * kCullTileHost); ++j)
+            for (int a = 0; a < 3; ++a) {
+                b[a] = std::min(b[a], hs[(size_t)a * n + j]);
+                b[3 + a] = std::max(b[3 + a], hs[(size_t)a * n + j]);
+            }
+    }
+    dalloc_cap(ctx, ctx->cs, ctx->cs_cap, (decltype(ctx->cs_cap))hs.size());
+    HIPCHK(ctx, hipMemcpyAsync(ctx->cs, hs.data(), sizeof(double) * hs.size(), hipMemcpyHostToDevice, ctx->stream));
+    CullSupports cs{ctx->cs, ctx->cs + n, ctx->cs + 2 * (size_t)n, ctx->cs + 3 * (size_t)n, ctx->cs + 4 * (size_t)n,
+                    ctx->cs + 5 * (size_t)n, ctx->cs + 6 * (size_t)n, ctx->cs + 7 * (size_t)n};
+    // the points' Morton order
+    if (ctx->cull_cap < nv) {
+        ctx->cull_cap = 0;
+        dalloc(ctx, ctx->ck_in, (size_t)nv); dalloc(ctx, ctx->ck_out, (size_t)nv);
+        dalloc(ctx, ctx->ci_in, (size_t)nv); dalloc(ctx, ctx->ci_out, (size_t)nv);
+        ctx->cull_cap = nv;
+    }
+    const double c0[3] = {0.5 * h[7 * (size_t)n], 0.5 * h[7 * (size_t)n + 1], 0.5 * h[7 * (size_t)n + 2]};
+    launch_cull_keys(ctx->stream, nv, din, in_f64, ctx->bd.inv_r, c0, f, ctx->ck_in, ctx->ci_in);
+    HIPCHK(ctx, hipGetLastError());
+    size_t tb = 0;
+    HIPCHK(ctx, sort_pairs_u32(nullptr, &tb, ctx->ck_in, ctx->ck_out, ctx->ci_in, ctx->ci_out, nv, 31, ctx->stream));
+    if (ctx->sort_tmp_cap < tb) {
+        if (ctx->sort_tmp) (void)hipFree(ctx->sort_tmp);
+        ctx->sort_tmp = nullptr;
+        ctx->sort_tmp_cap = 0;
+        HIPCHK(ctx, hipMalloc(&ctx->sort_tmp, tb));
+        ctx->sort_tmp_cap = tb;
+    }
+    HIPCHK(ctx, sort_pairs_u32(ctx->sort_tmp, &tb, ctx->ck_in, ctx->ck_out, ctx->ci_in, ctx->ci_out, nv, 31,
+                               ctx->stream));
+    const int64_t nblk = cull_blocks(nv);
+    dalloc_cap(ctx, ctx->cull_ev, ctx->cull_ev_cap, (decltype(ctx->cull_ev_cap))nblk);
+    launch_volume_cull(ctx->stream, nv, din, in_f64, ctx->ci_out, ctx->bd.inv_r, c0, cs, n, dout, out_f64,
+                       ctx->cull_ev);
+    HIPCHK(ctx, hipGetLastError());
+    ctx->cull_nblk = nblk;
+    ctx->cull_dense = (uint64_t)nv * (uint64_t)n;
+    ctx->cull_valid = true;
+    sync(ctx);   // the host copies of the sorted supports go out of scope
+}
+
 bool deform_timing_begin(gcb_ctx* ctx) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     HIPCHK(ctx, hipStreamIsCapturing(ctx->stream, &cs));
@@ -1050,6 +1153,8 @@ void gcb_destroy(gcb_ctx* ctx) {
     free_support(ctx->sp);
     dfree(ctx->state); dfree(ctx->argrec); dfree(ctx->red); dfree(ctx->irec); dfree(ctx->Pb);
     dfree(ctx->lam); dfree(ctx->brec);
+    dfree(ctx->ck_in); dfree(ctx->ck_out); dfree(ctx->ci_in); dfree(ctx->ci_out); dfree(ctx->cs); dfree(ctx->cull_ev);
+    if (ctx->sort_tmp) (void)hipFree(ctx->sort_tmp);
     dfree(ctx->log_group); dfree(ctx->log_node); dfree(ctx->log_err); dfree(ctx->log_app); dfree(ctx->mon);
     if (ctx->tmp) (void)hipFree(ctx->tmp);
     clear_chunk_graphs(ctx);
@@ -1287,6 +1392,8 @@ int gcb_deform(gcb_ctx* ctx, int64_t nv, const void* xyz, int in_dtype, void* ou
             ensure_fp32_copies(ctx);
             launch_volume32(ctx->stream, nv, din, in_dtype == GCB_F64, ctx->bd.inv_r, sp, (int)ctx->info.nc, dout,
                             out_dtype == GCB_F64);
+        } else if (ctx->params.cull_volume) {
+            deform_culled(ctx, nv, din, in_dtype == GCB_F64, dout, out_dtype == GCB_F64);
         } else {
             ensure_volume_table(ctx);
             launch_volume(ctx->stream, nv, din, in_dtype == GCB_F64, ctx->bd.inv_r, ctx->sp, (int)ctx->info.nc, dout,
@@ -1322,6 +1429,22 @@ int gcb_deform_noalloc(gcb_ctx* ctx, int64_t nv, const void* xyz, int in_dtype, 
         launch_volume_noalloc(ctx->stream, nv, xyz, in_dtype == GCB_F64, ctx->bd.inv_r, ctx->sp, (int)n, out,
                               out_dtype == GCB_F64, ctx->params.precision == GCB_PREC_FP32_EVAL, scr);
         HIPCHK(ctx, hipGetLastError());
+        return GCB_OK;
+    });
+}
+
+int gcb_get_deform_pairs(gcb_ctx* ctx, uint64_t* evaluated, uint64_t* dense) {
+    return guard(ctx, [&] {
+        if (!ctx->cull_valid) fail(ctx, GCB_E_STATE, "no culled deformation has run");
+        HIPCHK(ctx, hipSetDevice(ctx->device));
+        std::vector<uint64_t> ev((size_t)ctx->cull_nblk);
+        HIPCHK(ctx, hipMemcpyAsync(ev.data(), ctx->cull_ev, sizeof(uint64_t) * ev.size(), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        sync(ctx);
+        uint64_t sum = 0;
+        for (uint64_t v : ev) sum += v;
+        if (evaluated) *evaluated = sum;
+        if (dense) *dense = ctx->cull_dense;
         return GCB_OK;
     });
 }
