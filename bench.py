@@ -446,7 +446,8 @@ def step_record(p, nv, run, steps):
         "accuracy": {"final_max_err": info["final_max_err"], "final_rms_err": info["final_rms_err"],
                      "converged": bool(info["converged"])},
         "greedy_iteration": {"bound": "latency", "kernels_per_iteration": 3,
-                             "us_per_iteration": 1e3 * sel_ms / info["iterations"]},
+                             "us_per_iteration": 1e3 * sel_ms / info["iterations"],
+                             "iterations_completed_by_probe": info["probed_iterations"]},
     }
 
 
@@ -742,6 +743,7 @@ def per_iter_section(ctx, p, ps, check_oracle):
         inf = ctx.select()
         row = {"p": pp, "nc": inf["nc"], "iterations": inf["iterations"], "select_ms": inf["ms_select"],
                "us_per_iteration": 1e3 * inf["ms_select"] / max(inf["iterations"], 1),
+               "iterations_completed_by_probe": inf["probed_iterations"],
                "pairs_greedy": inf["pairs_group"] + inf["pairs_append"], "converged": bool(inf["converged"]),
                "final_max_err_rel": inf["final_max_err"] / p.max_disp}
         if check_oracle:

@@ -105,6 +105,11 @@ typedef struct {
     uint64_t pairs_append;   /* pair evaluations of the appended phi vectors: sum |S| */
     uint64_t pairs_cert;     /* nb * nc */
     double ms_select;        /* device wall time of the selection (hipEvents), ms */
+    int64_t probed_iterations; /* of `iterations`, the trailing quiet ones that the convergence probe
+                                * completed: after a run of quiet iterations (W unchanged), one FP64
+                                * sweep of every group showed that each remaining iteration of
+                                * Algorithm 1 appends nothing; their log entries are that sweep's
+                                * group maxima.  0 when the loop ran to its end */
 } gcb_select_info;
 
 /* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to

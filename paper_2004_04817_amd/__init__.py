@@ -58,7 +58,8 @@ class Params(C.Structure):
 class SelectInfo(C.Structure):
     _fields_ = [("nc", C.c_int64), ("iterations", C.c_int64), ("status", C.c_int32), ("converged", C.c_int32),
                 ("final_max_err", C.c_double), ("final_rms_err", C.c_double), ("pairs_group", C.c_uint64),
-                ("pairs_append", C.c_uint64), ("pairs_cert", C.c_uint64), ("ms_select", C.c_double)]
+                ("pairs_append", C.c_uint64), ("pairs_cert", C.c_uint64), ("ms_select", C.c_double),
+                ("probed_iterations", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}

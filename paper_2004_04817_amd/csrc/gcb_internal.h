@@ -117,6 +117,7 @@ struct Support {
 struct Tuning {
     int sweep_lpt_max = 256;   // 64, 128 or 256 lanes sharing one target in the group sweep
     bool use_graph = true;     // replay chunks of iterations as captured hipGraphs
+    bool probe = true;         // convergence probe at chunk boundaries (GCB_PROBE=0 turns it off)
 };
 extern Tuning g_tuning;
 
@@ -188,6 +189,14 @@ struct gcb_ctx {
     bool cull_valid = false;
     void *sort_tmp = nullptr;
     size_t sort_tmp_cap = 0;
+    // convergence probe: per-node errors and per-group maxima
+    double *perr = nullptr;
+    int64_t perr_cap = 0;
+    void *gmax = nullptr;
+    int64_t gmax_cap = 0;
+    int64_t probes = 0, probe_skipped = 0;   // of the last selection: probes run, iterations they completed
+    bool probe_cert = false;                 // the successful probe left the certificate (max, sum of e^2)
+    double probe_cert_max = 0.0, probe_cert_sum = 0.0;
     // scratch for certificate / volume
     double *red = nullptr;
     int64_t red_cap = 0;

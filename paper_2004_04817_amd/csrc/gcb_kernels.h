@@ -189,6 +189,16 @@ void launch_transpose_factor(hipStream_t s, const double* Mr, double* Mc, int n,
 void launch_monitor(hipStream_t s, const Boundary& bd, const Support& sp, const GState* st, int64_t need,
                     double* red, double* out);
 void launch_certify(hipStream_t s, const Boundary& bd, const Support& sp, int n, double* red, double* out);
+// Convergence probe: per group, the largest squared error over the nodes not in S with the current W (ties to
+// the lowest original index) and their count; perr holds one double per boundary node.
+struct GroupMax {
+    double e2;       // -1: no node outside S
+    int32_t orig;
+    int32_t count;
+    double all_max;  // largest squared error over all the group's nodes (S included)
+    double all_sum;  // their sum, in thread order then waves in order
+};
+void launch_probe(hipStream_t s, const Boundary& bd, const Support& sp, int n, double* perr, GroupMax* out);
 // Blocks of the all-node sweeps (certificate, monitor): red needs 2 doubles per block.
 int64_t certify_blocks(int64_t nb);
 // FP32 evaluation of Eq. (6) (FP32 copies of the supports and weights are

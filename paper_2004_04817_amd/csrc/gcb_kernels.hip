@@ -234,6 +234,20 @@ __device__ __forceinline__ double wave_sum(double v) {
     return sum_rows_f64<true>(v);
 }
 
+__device__ __forceinline__ double wave_min(double v) {
+    v = fmin(v, dpp_f64<kDppXor1>(v));
+    v = fmin(v, dpp_f64<kDppXor2>(v));
+    v = fmin(v, dpp_f64<kDppHalfMirror>(v));
+    v = fmin(v, dpp_f64<kDppMirror>(v));
+    double lo, hi;
+    swap_rows_f64<false>(v, lo, hi);
+    v = fmin(lo, hi);
+    swap_rows_f64<true>(v, lo, hi);
+    return fmin(lo, hi);
+}
+
+__device__ __forceinline__ double wave_max(double v) { return -wave_min(-v); }
+
 template <int NT>
 __device__ double block_sum(double v) {
     __shared__ double sh[NT / 64];
@@ -1717,6 +1731,86 @@ __global__ __launch_bounds__(kBlock) void k_certify(int64_t nb, const double* __
     all_node_block(nb, px, py, pz, pdx, pdy, pdz, sv, n, red);
 }
 
+// Convergence probe: the FP64 error of every boundary node with the current W (the certificate's layout: one
+// target per lane, the supports split over the block's four waves), one value per node.
+__global__ __launch_bounds__(kBlock) void k_probe_err(int64_t nb, const double* __restrict__ px,
+                                                      const double* __restrict__ py, const double* __restrict__ pz,
+                                                      const double* __restrict__ pdx, const double* __restrict__ pdy,
+                                                      const double* __restrict__ pdz, SupportView sv, int n,
+                                                      double* __restrict__ perr) {
+    __shared__ double part[3][4][kCertTargets];
+    const int q = threadIdx.x / kCertTargets, tl = threadIdx.x % kCertTargets;
+    const int64_t t = blockIdx.x * (int64_t)kCertTargets + tl;
+    const bool live = t < nb;
+    const int64_t tt = live ? t : nb - 1;
+    const int s0 = (int)((int64_t)n * q / 4), s1 = (int)((int64_t)n * (q + 1) / 4);
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    accumulate64(px[tt], py[tt], pz[tt], s0, s1, sv.sx, sv.sy, sv.sz, sv.wx, sv.wy, sv.wz, ax, ay, az);
+    part[0][q][tl] = ax;
+    part[1][q][tl] = ay;
+    part[2][q][tl] = az;
+    __syncthreads();
+    if (q == 0 && live) {
+        const double fx = (part[0][0][tl] + part[0][1][tl]) + (part[0][2][tl] + part[0][3][tl]);
+        const double fy = (part[1][0][tl] + part[1][1][tl]) + (part[1][2][tl] + part[1][3][tl]);
+        const double fz = (part[2][0][tl] + part[2][1][tl]) + (part[2][2][tl] + part[2][3][tl]);
+        const double ex = fx - pdx[t], ey = fy - pdy[t], ez = fz - pdz[t];
+        perr[t] = fma(ez, ez, fma(ey, ey, ex * ex));
+    }
+}
+
+// Per group (one block each, groups contiguous in the permuted order): the largest squared error over the nodes
+// not in S, ties to the lowest original index, and the count of those nodes.
+__global__ __launch_bounds__(kBlock) void k_probe_groups(const int32_t* __restrict__ goff,
+                                                         const int32_t* __restrict__ perm,
+                                                         const uint8_t* __restrict__ inS,
+                                                         const double* __restrict__ perr, GroupMax* __restrict__ out) {
+    __shared__ int32_t s_cnt[kBlock / 64];
+    __shared__ double s_max[kBlock / 64];
+    const int g = blockIdx.x;
+    const int a = goff[g], b = goff[g + 1];
+    Best best{-1.0, 0x7fffffff, 0};
+    int32_t cnt = 0;
+    double amax = 0.0, asum = 0.0;
+    for (int p = a + (int)threadIdx.x; p < b; p += kBlock) {
+        const double e = perr[p];
+        amax = fmax(amax, e);
+        asum += e;
+        if (inS[p]) continue;
+        ++cnt;
+        const int32_t o = perm[p];
+        if (better(e, o, best.v, best.idx)) {
+            best.v = e;
+            best.idx = o;
+        }
+    }
+    best = block_best(best);
+    const double gsum = block_sum<kBlock>(asum);
+    cnt = wave_isum(cnt);
+    amax = wave_max(amax);
+    if ((threadIdx.x & 63) == 0) {
+        s_cnt[threadIdx.x >> 6] = cnt;
+        s_max[threadIdx.x >> 6] = amax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t total = 0;
+        double gmx = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            total += s_cnt[w];
+            gmx = fmax(gmx, s_max[w]);
+        }
+        out[g] = GroupMax{best.v, best.idx, total, gmx, gsum};
+    }
+}
+
+void launch_probe(hipStream_t s, const Boundary& bd, const Support& sp, int n, double* perr, GroupMax* out) {
+    const unsigned g = (unsigned)certify_blocks(bd.nb);
+    GCB_LAUNCH(k_probe_err, dim3(g), dim3(kBlock), s, bd.nb, bd.px, bd.py, bd.pz, bd.pdx, bd.pdy, bd.pdz, view(sp), n,
+               perr);
+    GCB_LAUNCH(k_probe_groups, dim3((unsigned)bd.m), dim3(kBlock), s, bd.goff, bd.perm, bd.inS, perr, out);
+}
+
 __global__ __launch_bounds__(kBlock) void k_certify_final(int nblk, const double* __restrict__ red,
                                                           double* __restrict__ out) {
     // fixed order: each thread sums a contiguous stretch, then the block in thread order
@@ -2215,20 +2309,6 @@ void launch_volume(hipStream_t s, int64_t nv, const void* xyz, int in_f64, doubl
 // 1e-9, far above the rounding of the evaluated distance, so every skipped pair would have evaluated to zero.
 constexpr int kCullTile = 32;
 constexpr double kCullGap2 = 0.25 * (1.0 + 1e-9);
-
-__device__ __forceinline__ double wave_min(double v) {
-    v = fmin(v, dpp_f64<kDppXor1>(v));
-    v = fmin(v, dpp_f64<kDppXor2>(v));
-    v = fmin(v, dpp_f64<kDppHalfMirror>(v));
-    v = fmin(v, dpp_f64<kDppMirror>(v));
-    double lo, hi;
-    swap_rows_f64<false>(v, lo, hi);
-    v = fmin(lo, hi);
-    swap_rows_f64<true>(v, lo, hi);
-    return fmin(lo, hi);
-}
-
-__device__ __forceinline__ double wave_max(double v) { return -wave_min(-v); }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t x) {
     x &= 0x3ffu;

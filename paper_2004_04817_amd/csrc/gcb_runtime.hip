@@ -363,6 +363,9 @@ void select_begin(gcb_ctx* ctx) {
         ctx->ktime_n[q] = 0;
     }
     ctx->ktime_valid = false;
+    ctx->probes = 0;
+    ctx->probe_skipped = 0;
+    ctx->probe_cert = false;
     if (ctx->params.warm_start) {
         warm_begin(ctx);
         return;
@@ -451,13 +454,20 @@ void select_end(gcb_ctx* ctx, gcb_select_info* info) {
     // FP64 certificate over all boundary nodes
     ensure_red(ctx);
     const bool ktime = ctx->ktime_on && per_iter(ctx) == 1 && ctx->ktime_ev.size() >= 2;
-    if (ktime) HIPCHK(ctx, hipEventRecord(ctx->ktime_ev[ctx->ktime_ev.size() - 2], ctx->stream));
-    launch_certify(ctx->stream, bd, ctx->sp, h.n, ctx->red, ctx->red + ctx->red_cap - 2);
-    HIPCHK(ctx, hipGetLastError());
-    if (ktime) HIPCHK(ctx, hipEventRecord(ctx->ktime_ev.back(), ctx->stream));
     double mr[2];
-    HIPCHK(ctx, hipMemcpyAsync(mr, ctx->red + ctx->red_cap - 2, sizeof(mr), hipMemcpyDeviceToHost, ctx->stream));
-    sync(ctx);
+    if (ctx->probe_cert) {
+        // the convergence probe already swept every node with the final W
+        sync(ctx);   // (the selection's end event)
+        mr[0] = ctx->probe_cert_max;
+        mr[1] = ctx->probe_cert_sum;
+    } else {
+        if (ktime) HIPCHK(ctx, hipEventRecord(ctx->ktime_ev[ctx->ktime_ev.size() - 2], ctx->stream));
+        launch_certify(ctx->stream, bd, ctx->sp, h.n, ctx->red, ctx->red + ctx->red_cap - 2);
+        HIPCHK(ctx, hipGetLastError());
+        if (ktime) HIPCHK(ctx, hipEventRecord(ctx->ktime_ev.back(), ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(mr, ctx->red + ctx->red_cap - 2, sizeof(mr), hipMemcpyDeviceToHost, ctx->stream));
+        sync(ctx);
+    }
     if (ktime) {
         float t = 0.f;
         HIPCHK(ctx, hipEventElapsedTime(&t, ctx->ktime_ev[ctx->ktime_ev.size() - 2], ctx->ktime_ev.back()));
@@ -472,6 +482,7 @@ void select_end(gcb_ctx* ctx, gcb_select_info* info) {
     inf.final_rms_err = std::sqrt(mr[1] / (double)bd.nb);
     inf.converged = inf.final_max_err <= p.tol_abs;
     inf.pairs_cert = (uint64_t)bd.nb * (uint64_t)h.n;
+    inf.probed_iterations = ctx->probe_skipped;
     ctx->info = inf;
     ctx->selected = true;
     ctx->warm_ok = true;
@@ -568,6 +579,86 @@ void ktime_collect(gcb_ctx* ctx, int chunk, const std::vector<int>& swept) {
     }
 }
 
+// Convergence probe (at a chunk boundary, after `quiet` iterations without an append): W has not changed during
+// them, so Algorithm 1's next m - quiet iterations are all quiet exactly when every group they visit has no node
+// outside S with an error above E*.  One FP64 sweep of all nodes gives every group's maximum; if none exceeds
+// E*, the remaining iterations are completed here with the log entries they would write (group, its argmax node
+// or -1, its error, nothing appended) and the counters they would add, and the selection ends as converged.
+// Returns true if it ended the selection.
+bool probe_converged(gcb_ctx* ctx) {
+    const gcb_params& p = ctx->params;
+    Boundary& bd = ctx->bd;
+    const GState h = ctx->state_h;
+    const int m = p.m;
+    const int rem = m - h.quiet;
+    // (no captured graph reads these buffers, so growing them does not invalidate one)
+    if (ctx->perr_cap < bd.nb) {
+        ctx->perr_cap = 0;
+        if (ctx->perr) (void)hipFree(ctx->perr);
+        ctx->perr = nullptr;
+        HIPCHK(ctx, hipMalloc(reinterpret_cast<void**>(&ctx->perr), sizeof(double) * (size_t)bd.nb));
+        ctx->perr_cap = bd.nb;
+    }
+    if (ctx->gmax_cap < m) {
+        ctx->gmax_cap = 0;
+        if (ctx->gmax) (void)hipFree(ctx->gmax);
+        ctx->gmax = nullptr;
+        HIPCHK(ctx, hipMalloc(&ctx->gmax, sizeof(GroupMax) * (size_t)m));
+        ctx->gmax_cap = m;
+    }
+    launch_probe(ctx->stream, bd, ctx->sp, h.n, ctx->perr, static_cast<GroupMax*>(ctx->gmax));
+    HIPCHK(ctx, hipGetLastError());
+    std::vector<GroupMax> g((size_t)m);
+    HIPCHK(ctx, hipMemcpyAsync(g.data(), ctx->gmax, sizeof(GroupMax) * (size_t)m, hipMemcpyDeviceToHost, ctx->stream));
+    sync(ctx);
+    ctx->probes += 1;
+    const int64_t k = ctx->k_host;
+    for (int i = 0; i < rem; ++i) {
+        const GroupMax& r = g[(size_t)((k + i) % m)];
+        if (r.count > 0 && std::sqrt(r.e2) > p.tol_abs) return false;
+    }
+    if (h.log_len + rem > ctx->log_cap) grow_log(ctx, h.log_len, std::max<int64_t>(2 * ctx->log_cap, h.log_len + rem));
+    std::vector<int32_t> lg((size_t)rem), ln((size_t)rem);
+    std::vector<double> le((size_t)rem);
+    std::vector<int8_t> la((size_t)rem, 0);
+    uint64_t pairs = 0;
+    for (int i = 0; i < rem; ++i) {
+        const int gi = (int)((k + i) % m);
+        const GroupMax& r = g[(size_t)gi];
+        lg[(size_t)i] = gi;
+        ln[(size_t)i] = r.count > 0 ? r.orig : -1;
+        le[(size_t)i] = r.count > 0 ? std::sqrt(r.e2) : 0.0;
+        pairs += (uint64_t)r.count * (uint64_t)h.n;
+    }
+    GState st = h;
+    st.k = h.k + rem;
+    st.quiet = m;
+    st.done = 1;
+    st.log_len = h.log_len + rem;
+    st.pairs_group = h.pairs_group + pairs;
+    const int64_t o = h.log_len;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->log_group + o, lg.data(), sizeof(int32_t) * rem, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->log_node + o, ln.data(), sizeof(int32_t) * rem, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->log_err + o, le.data(), sizeof(double) * rem, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->log_app + o, la.data(), sizeof(int8_t) * rem, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->state, &st, sizeof(GState), hipMemcpyHostToDevice, ctx->stream));
+    sync(ctx);   // the host vectors go out of scope
+    ctx->state_h = st;
+    ctx->k_host = k + rem;
+    ctx->probe_skipped = rem;
+    // W stays as the probe saw it, so its errors are the certificate's (the same per-node arithmetic): the
+    // largest, and the sum in group order
+    double mx = 0.0, sum = 0.0;
+    for (int gi = 0; gi < m; ++gi) {
+        mx = std::max(mx, g[(size_t)gi].all_max);
+        sum += g[(size_t)gi].all_sum;
+    }
+    ctx->probe_cert = true;
+    ctx->probe_cert_max = mx;
+    ctx->probe_cert_sum = sum;
+    return true;
+}
+
 void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     select_begin(ctx);
     const gcb_params& p = ctx->params;
@@ -584,10 +675,19 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     if (every > 0) ensure_red(ctx);
     std::vector<int> swept(ktime ? chunk : 0, 0);
     if (ktime) ktime_events(ctx, chunk);
+    // the probe runs once per run of quiet iterations (W changes with every append), after max(8, m / 8) of them
+    const bool probe = g_tuning.probe && every == 0 && !ktime;
+    const int probe_after = std::max(8, m / 8);
+    int64_t probed_n = -1;
     for (;;) {
         HIPCHK(ctx, hipMemcpyAsync(ctx->state_pin, ctx->state, sizeof(GState), hipMemcpyDeviceToHost, ctx->stream));
         sync(ctx);
         if (!select_poll(ctx, chunk)) break;
+        const GState& hs = ctx->state_h;
+        if (probe && hs.quiet >= probe_after && m - hs.quiet >= 8 && hs.n != probed_n) {
+            probed_n = hs.n;
+            if (probe_converged(ctx)) break;
+        }
         if (gchunk > 0) {
             launch_chunk(ctx, chunk);
         } else {
@@ -1114,6 +1214,7 @@ int gcb_create(gcb_ctx** out, int device, void* hip_stream) {
         if (v == 64 || v == 128 || v == 256) g_tuning.sweep_lpt_max = v;
     }
     if (const char* e = std::getenv("GCB_GRAPH")) g_tuning.use_graph = std::atoi(e) != 0;
+    if (const char* e = std::getenv("GCB_PROBE")) g_tuning.probe = std::atoi(e) != 0;
     *out = nullptr;
     gcb_ctx* ctx = new (std::nothrow) gcb_ctx();
     if (!ctx) return GCB_E_NOMEM;
@@ -1153,6 +1254,8 @@ void gcb_destroy(gcb_ctx* ctx) {
     free_support(ctx->sp);
     dfree(ctx->state); dfree(ctx->argrec); dfree(ctx->red); dfree(ctx->irec); dfree(ctx->Pb);
     dfree(ctx->lam); dfree(ctx->brec);
+    if (ctx->perr) (void)hipFree(ctx->perr);
+    if (ctx->gmax) (void)hipFree(ctx->gmax);
     dfree(ctx->ck_in); dfree(ctx->ck_out); dfree(ctx->ci_in); dfree(ctx->ci_out); dfree(ctx->cs); dfree(ctx->cull_ev);
     if (ctx->sort_tmp) (void)hipFree(ctx->sort_tmp);
     dfree(ctx->log_group); dfree(ctx->log_node); dfree(ctx->log_err); dfree(ctx->log_app); dfree(ctx->mon);

@@ -245,3 +245,34 @@ def test_kernel_timing_keeps_the_selection():
         fresh.kernel_times()
     fresh.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("case", ["wing80k", "ellipsoid", "wing_m300"])
+def test_convergence_probe_completes_the_same_run(case, monkeypatch):
+    """The convergence probe ends the final run of quiet iterations early, writing the log entries those
+    iterations would write: the same support sequence, weights and iteration count as with the probe off, the
+    same groups, appended flags and argmax nodes, errors within 1e-12 max|d|; and against the oracle."""
+    if case == "wing80k":
+        p = synth.config_wing(with_volume=False)
+    elif case == "ellipsoid":
+        p = synth.config_small_ellipsoid(with_volume=False)
+    else:
+        p = synth.config_wing(with_volume=False, m=300)
+    ctx, info, S, W, log = gpu_select(p)
+    monkeypatch.setenv("GCB_PROBE", "0")
+    c0, i0, S0, W0, l0 = gpu_select(p)
+    monkeypatch.setenv("GCB_PROBE", "1")
+    print(f"{case}: iterations {info['iterations']}, probe completed {info['probed_iterations']}; "
+          f"select {info['ms_select']:.2f} ms vs {i0['ms_select']:.2f} ms without", flush=True)
+    assert i0["probed_iterations"] == 0
+    assert np.array_equal(S, S0) and np.array_equal(W, W0)
+    assert info["iterations"] == i0["iterations"] and info["nc"] == i0["nc"]
+    assert np.array_equal(log.group, l0.group) and np.array_equal(log.appended, l0.appended)
+    assert np.array_equal(log.node, l0.node)
+    assert np.abs(log.err - l0.err).max() <= 1e-12 * p.max_disp
+    assert info["pairs_group"] == i0["pairs_group"] and info["pairs_append"] == i0["pairs_append"]
+    assert info["final_max_err"] == i0["final_max_err"]
+    r = oracle_select(p)
+    assert_same_run(p, info, S, W, log, r, p.tol_abs, p.m)
+    ctx.close()
+    c0.close()
