@@ -731,6 +731,22 @@ def m_sweep_section(ctx, p, ms_list):
             f"history_m{p.m}": history}
 
 
+def refactor_scaling(ctx, p, ncs):
+    """Dense refactorisation of larger support systems: fixed-Nc selections (E* = 0, Nc^max = Nc) of the
+    workload, then the blocked Cholesky + inverse timed warm (second of two)."""
+    rows = []
+    for nc in ncs:
+        ctx.set_params(p.radius, p.m, 0.0, nc_max=nc, seed=p.seed)
+        ctx.select()
+        ctx.refactor()
+        drift, rinfo = ctx.refactor()
+        rows.append({"nc": rinfo["nc"], "ms": rinfo["ms_select"], "drift": drift,
+                     "tflops": 2.0 * rinfo["nc"] ** 3 / 3.0 / (rinfo["ms_select"] * 1e-3) / 1e12})
+    ctx.set_params(p.radius, p.m, p.tol_abs, seed=p.seed)
+    ctx.select()
+    return rows
+
+
 def per_iter_section(ctx, p, ps, check_oracle):
     """The several-nodes-per-iteration variant (the block form of the peak-selection idea cited in Section 1):
     per p, the warm selection time (second of two runs), iterations, Nc and the certificate; with check_oracle
@@ -797,6 +813,7 @@ def wing80k_section(a, dev, stream):
     rec["volume_fp32_eval"]["speedup_vs_fp64"] = rec["phases_ms"]["volume"] / rec["volume_fp32_eval"]["ms"]
     rec["volume_culled"] = cull_section(ctx, p, vol, out, rec["phases_ms"]["volume"], ref)
     rec["refactor"] = refactor_section(ctx, p)
+    rec["refactor"]["scaling"] = refactor_scaling(ctx, p, [2000, 4000])
     if a.modes > 0:
         rec["modes"] = modes_section(ctx, p, xyz, vol, a.modes, not a.no_cpu_baseline, stream)
     if a.m_sweep:

@@ -1,19 +1,26 @@
-// Dense FP64 refactorisation of the support system: Phi_S = L L^T (blocked
-// right-looking Cholesky) and, in the same block steps, M = L^-1, with the
-// block products on the FP64 matrix cores (v_mfma_f64_16x16x4f64).  Used to
-// rebuild the inverse factor of a given support set, and to re-certify the
-// incrementally grown factor against rounding drift.
+// Dense FP64 refactorisation of the support system: Phi_S = L L^T and M = L^-1
+// (the inverse factor), by recursive halving, with the block products on the
+// FP64 matrix cores (v_mfma_f64_16x16x4f64).  Used to rebuild the inverse
+// factor of a given support set, and to re-certify the incrementally grown
+// factor against rounding drift.
 //
-// The inverse follows from L M = I by blocks: M_kk = L_kk^-1 and, for j < k,
-// M_kj = -M_kk T_kj with T_kj = sum_{l=j}^{k-1} L_kl M_lj.  Step k of the
-// Cholesky produces the panel L_{.,k}; the same step's update adds
-// L_ik M_kj to T_ij for every i > k and j <= k, so T_kj is complete when
-// step k starts and the inverse costs no launches of its own.
+// For Phi = [[A11, A21^T], [A21, A22]] split at a multiple of 64:
+//   (L11, M11) from A11 (recursively);
+//   L21 = A21 L11^-T = A21 M11^T (refined once against L11 for large A11);
+//   S = A22 - L21 L21^T = L22 L22^T, and (L22, M22) from S (recursively);
+//   M21 = -M22 L21 M11, formed as X = L21 M11, then M21 = -M22 X.
+// Nearly all flops sit in the four products, whose depth is the size of the
+// split (a few thousand at the top), so they run near the matrix cores' rate;
+// only the 64 x 64 leaves are factored one workgroup at a time.
 //
-// Matrices are dense row-major np x np with np = n rounded up to kDB; the
-// padding is the identity, so every block step is full-sized:
+// Matrices are dense row-major np x np with np = n rounded up to 64; the
+// padding is the identity, so every leaf is full-sized:
 // chol([[Phi, 0], [0, I]]) = [[L, 0], [0, I]] and its inverse is [[M, 0], [0, I]].
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <initializer_list>
+#include <vector>
 
 #include "gcb_device.h"
 #include "gcb_internal.h"
@@ -24,7 +31,9 @@ namespace gcb {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-constexpr int kDB = 32;   // block size of the blocked algorithms
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+constexpr int kLeaf = 64;   // leaf size of the recursion and tile size of the products
 
 // A = Phi_S (lower triangle, zero above) in the np x np padded layout.
 __global__ __launch_bounds__(kBlock) void k_assemble(int n, int np, const double* __restrict__ sx,
@@ -49,174 +58,344 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
     return __hiloint2double(hi, lo);
 }
 
-// Step k0 of the Cholesky factorisation.  Wave 0 factors the diagonal block
-// (already updated by the earlier steps) in registers, one row per lane, with
-// the column entries broadcast across lanes; the factored block goes to LDS.
-// A's diagonal block is only read in this launch and never written, so no
-// workgroup overwrites what another still reads.  In workgroup 0, 32 lanes of
-// wave 1 then form M_kk = L_kk^-1 (lane c: column c by forward substitution)
-// into Md.  Each workgroup solves kBlock rows of the panel below:
-// x L_kk^T = a.
-__global__ __launch_bounds__(kBlock) void k_chol_step(int np, int k0, double* __restrict__ A,
-                                                      double* __restrict__ Md, int32_t* __restrict__ bad) {
-    __shared__ double D[kDB][kDB + 1];
-    __shared__ double Rd[kDB];
-    const int tid = threadIdx.x;
-    if (tid < 64) {
-        const int lane = tid;
-        const int row = lane < kDB ? lane : kDB - 1;
-        double a[kDB];
-        const double* Ar = A + (size_t)(k0 + row) * np + k0;
+// One wave factors a 32 x 32 SPD block and inverts its factor in the same
+// column loop.  On entry lane i < 32 holds row i of the block (entries t <= i,
+// zero above) and lane 32 + t holds column t of the identity.  On exit lane i
+// holds row i of L in its entries t <= i (the entries above are left with
+// values that are never read) and lane 32 + t column t of L^-1.
+// Column c (right-looking): every lane scales its entry c by 1 / sqrt(a_cc)
+// (L_ic below the diagonal; in the upper half row c of the inverse,
+// R_c / L_cc, final once the earlier columns are applied), then for k > c
+// every lane takes a_k -= a_c L_kc: the lower half's a_ik -= L_ic L_kc and
+// the upper half's R_k -= L_kc M_c, one broadcast of L_kc serving both.
+__device__ __forceinline__ void chol_inv32(double (&a)[32], int& sing) {
 #pragma unroll
-        for (int c = 0; c < kDB; ++c) a[c] = (c <= lane && lane < kDB) ? Ar[c] : 0.0;
-        int sing = 0;
-#pragma unroll
-        for (int c = 0; c < kDB; ++c) {
-            double d = readlane_f64(a[c], c);
-            if (!(d > kSingularTol)) {
-                sing = 1;
-                d = 1.0;
-            }
-            // 1/sqrt(d) by two Newton steps on the hardware estimate; L_cc = d / sqrt(d)
-            double rs = __builtin_amdgcn_rsq(d);
-            rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
-            rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
-            if (lane == c) a[c] = d * rs;
-            if (lane > c) a[c] *= rs;
-#pragma unroll
-            for (int j = c + 1; j < kDB; ++j) {
-                const double ljc = readlane_f64(a[c], j);
-                if (lane >= j) a[j] = fma(-a[c], ljc, a[j]);
-            }
+    for (int c = 0; c < 32; ++c) {
+        double d = readlane_f64(a[c], c);
+        if (!(d > kSingularTol)) {
+            sing = 1;
+            d = 1.0;
+            a[c] = 1.0;
         }
-        if (lane < kDB) {
+        // 1/sqrt(d) by two Newton steps on the hardware estimate
+        double rs = __builtin_amdgcn_rsq(d);
+        rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
+        rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
+        a[c] *= rs;
 #pragma unroll
-            for (int c = 0; c < kDB; ++c) D[lane][c] = c <= lane ? a[c] : 0.0;
+        for (int k = c + 1; k < 32; ++k) a[k] = fma(-a[c], readlane_f64(a[c], k), a[k]);
+    }
+}
+
+// D (16 x 16 tile of one wave, d4 layout: row lk + 4 r, column li) += X Y over depth 32, both from LDS:
+// X[i][k] at x[(xr + i) * xs + xc + k]; Y[k][j] at y[(yk + k) * ys + yc + j] or, transposed
+// (Y given as rows j), at y[(yc + j) * ys + yk + k].
+template <bool YT>
+__device__ __forceinline__ d4 mm16x32(d4 acc, double sgn, const double* x, int xs, int xr, int xc, const double* y,
+                                      int ys, int yk, int yc, int li, int lk) {
+#pragma unroll
+    for (int s = 0; s < 32; s += 4) {
+        const double av = sgn * x[(xr + li) * xs + xc + s + lk];
+        const double bv = YT ? y[(yc + li) * ys + yk + s + lk] : y[(yk + s + lk) * ys + yc + li];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Leaf: the 64 x 64 diagonal block at (o, o) of A (lower triangle, already
+// reduced by the earlier blocks) gives the same block of L (into Tb) and of
+// Md = L^-1, both with zeros above the diagonal, by one halving step inside
+// the workgroup: two 32-wide factorisations with inverse (wave 0) and the
+// products between them on the matrix cores (all four waves).
+constexpr int kLs = kLeaf + 1;   // LDS row strides
+constexpr int kHs = 33;
+
+__global__ __launch_bounds__(kBlock) void k_leaf64(int np, int o, const double* __restrict__ A,
+                                                   double* __restrict__ Md, double* __restrict__ Lt,
+                                                   int32_t* __restrict__ bad) {
+    __shared__ double sA[kLeaf * kLs], sLb[kLeaf * kLs];
+    __shared__ double sM1[32 * kHs], sM2[32 * kHs], sL[32 * kHs], sX[32 * kHs];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    for (int x = tid; x < kLeaf * kLeaf; x += kBlock) sA[(x >> 6) * kLs + (x & 63)] = A[(size_t)(o + (x >> 6)) * np + o + (x & 63)];
+    __syncthreads();
+    int sing = 0;
+    if (wave == 0) {
+        double a[32];
+        const int i = lane & 31;
+#pragma unroll
+        for (int t = 0; t < 32; ++t) a[t] = lane < 32 ? (t <= i ? sA[i * kLs + t] : 0.0) : (t == i ? 1.0 : 0.0);
+        chol_inv32(a, sing);
+        if (lane >= 32)   // column i of M11
+#pragma unroll
+            for (int t = 0; t < 32; ++t) sM1[t * kHs + i] = a[t];
+        else   // row i of L11 and the zeros beside it
+#pragma unroll
+            for (int t = 0; t < 32; ++t) {
+                sLb[i * kLs + t] = t <= i ? a[t] : 0.0;
+                sLb[i * kLs + 32 + t] = 0.0;
+            }
+    }
+    __syncthreads();
+    const int wi = wave >> 1, wj = wave & 1;
+    {   // L21 = A21 M11^T
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        acc = mm16x32<true>(acc, 1.0, sA, kLs, 32 + 16 * wi, 0, sM1, kHs, 0, 16 * wj, li, lk);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            sL[(16 * wi + lk + 4 * r) * kHs + 16 * wj + li] = acc[r];
+            sLb[(32 + 16 * wi + lk + 4 * r) * kLs + 16 * wj + li] = acc[r];
         }
+    }
+    __syncthreads();
+    // S = A22 - L21 L21^T (lower tiles 0..2) and X = L21 M11 (tiles 3..6)
+    for (int job = wave; job < 7; job += 4) {
+        if (job < 3) {
+            const int ti = job == 0 ? 0 : 1, tj = job == 2 ? 1 : 0;
+            double* s = sA + (32 + 16 * ti) * kLs + 32 + 16 * tj;
+            d4 acc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = s[(lk + 4 * r) * kLs + li];
+            acc = mm16x32<true>(acc, -1.0, sL, kHs, 16 * ti, 0, sL, kHs, 0, 16 * tj, li, lk);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) s[(lk + 4 * r) * kLs + li] = acc[r];
+        } else {
+            const int ti = (job - 3) >> 1, tj = (job - 3) & 1;
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+            acc = mm16x32<false>(acc, 1.0, sL, kHs, 16 * ti, 0, sM1, kHs, 0, 16 * tj, li, lk);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sX[(16 * ti + lk + 4 * r) * kHs + 16 * tj + li] = acc[r];
+        }
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double a[32];
+        const int i = lane & 31;
+#pragma unroll
+        for (int t = 0; t < 32; ++t)
+            a[t] = lane < 32 ? (t <= i ? sA[(32 + i) * kLs + 32 + t] : 0.0) : (t == i ? 1.0 : 0.0);
+        chol_inv32(a, sing);
+        if (lane >= 32)   // column i of M22
+#pragma unroll
+            for (int t = 0; t < 32; ++t) sM2[t * kHs + i] = a[t];
+        else   // row i of L22
+#pragma unroll
+            for (int t = 0; t < 32; ++t) sLb[(32 + i) * kLs + 32 + t] = t <= i ? a[t] : 0.0;
         if (lane == 0 && sing) bad[0] = 1;
     }
     __syncthreads();
-    if (tid < kDB) Rd[tid] = 1.0 / D[tid][tid];
-    __syncthreads();
-    if (blockIdx.x == 0 && tid >= 64 && tid < 64 + kDB) {
-        const int c = tid - 64;
-        double x[kDB];
+    {   // M21 = -M22 X
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        acc = mm16x32<false>(acc, -1.0, sM2, kHs, 16 * wi, 0, sX, kHs, 0, 16 * wj, li, lk);
 #pragma unroll
-        for (int i = 0; i < kDB; ++i) x[i] = i == c ? 1.0 : 0.0;
-        // L_kk x = e_c, right-looking: x_t is final once the earlier columns are applied
-#pragma unroll
-        for (int t = 0; t < kDB; ++t) {
-            x[t] *= Rd[t];
-#pragma unroll
-            for (int i = t + 1; i < kDB; ++i) x[i] = fma(-D[i][t], x[t], x[i]);
+        for (int r = 0; r < 4; ++r) Md[(size_t)(o + 32 + 16 * wi + lk + 4 * r) * np + o + 16 * wj + li] = acc[r];
+    }
+    for (int x = tid; x < 64 * 32; x += kBlock) {
+        const int r = x >> 5, c = x & 31;
+        if (r < 32) {   // M11 and the zero block beside it
+            Md[(size_t)(o + r) * np + o + c] = sM1[r * kHs + c];
+            Md[(size_t)(o + r) * np + o + 32 + c] = 0.0;
+        } else {
+            Md[(size_t)(o + r) * np + o + 32 + c] = sM2[(r - 32) * kHs + c];
         }
-#pragma unroll
-        for (int i = 0; i < kDB; ++i) Md[(size_t)(k0 + i) * np + k0 + c] = x[i];
     }
-    const int r = k0 + kDB + blockIdx.x * kBlock + tid;
-    if (r >= np) return;
-    double* Ar = A + (size_t)r * np + k0;
-    double x[kDB];
-#pragma unroll
-    for (int c = 0; c < kDB; ++c) x[c] = Ar[c];
-    // right-looking: once x_c is known, every later entry is updated (independent FMAs)
-#pragma unroll
-    for (int c = 0; c < kDB; ++c) {
-        x[c] *= Rd[c];
-#pragma unroll
-        for (int t = c + 1; t < kDB; ++t) x[t] = fma(-x[c], D[t][c], x[t]);
-    }
-#pragma unroll
-    for (int c = 0; c < kDB; ++c) Ar[c] = x[c];
+    for (int x = tid; x < kLeaf * kLeaf; x += kBlock) Lt[(size_t)(o + (x >> 6)) * np + o + (x & 63)] = sLb[(x >> 6) * kLs + (x & 63)];
 }
 
-// lower block index pair (ti >= tj) of linear index b
-__device__ __forceinline__ void tri_index(int b, int& ti, int& tj) {
-    int i = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= b) ++i;
-    while (i * (i + 1) / 2 > b) --i;
-    ti = i;
-    tj = b - i * (i + 1) / 2;
-}
+// ---------------------------------------------------------------------------
+// Block products C (m x n) = alpha X Y (+ C), all matrices row-major with the
+// leading dimension np.  X[i][k] at X + i np + k; Y[k][j] at Y + k np + j, or
+// (y_rows) Y given by its rows j: Y[k][j] at Y + j np + k.  Output tiles of
+// 64 x 64 (four waves of 32 x 32); a tile's depth range may be split into
+// slices, one workgroup each (the work items of a launch, built on the host),
+// so that tiles of very different depth (triangular factors) spread evenly
+// over the chip and small products still fill it.  Slice 0 writes C itself
+// (alpha p_0, plus C for accumulate), slice s > 0 writes alpha p_s to a
+// partial buffer, and a second launch adds the partials to C in slice order,
+// so a plan always gives the same bits.
+//
+// Depth in chunks of 32 staged in LDS (two stages), with the global loads of
+// the next two chunks in flight in two register sets while a chunk is
+// multiplied; operands stored in LDS depth-major so that each wave reads its
+// matrix-core operands as 16 consecutive doubles.
+struct GemmSide {
+    const double* X;
+    const double* Y;
+    double* C;
+    double alpha;
+    int accumulate;  // C = alpha X Y + C
+    int y_rows;      // Y given by its rows j (Y^T row-major)
+};
+struct GemmItem {
+    int32_t ti, tj;  // output tile
+    int32_t kb, ke;  // depth slice (multiples of 64)
+    int32_t s;       // slice index
+    int32_t part;    // partial slot of this slice (s > 0)
+    int32_t side;    // 0 or 1: which product of the launch
+    int32_t pad;
+};
+struct GemmReduce {   // a sliced tile: C += partials part .. part + P - 2, in order
+    int32_t ti, tj, side, P, part, pad[3];
+};
+struct GemmLaunch {
+    GemmSide side[2];
+    const GemmItem* items;
+    int total;
+    int np;
+    double* part;
+};
+struct ReduceLaunch {
+    double* C[2];
+    const GemmReduce* tiles;
+    int np;
+    const double* part;
+};
 
-// M_kj = -M_kk T_kj (j < k) or M_kk (j = k) into Ms, one 16 x 16 quarter per
-// wave (K = kDB on the matrix cores); block row k starts at k0.
-__device__ __forceinline__ void inverse_row_block(int np, int k0, int jb, const double* __restrict__ Tb,
-                                                  const double* __restrict__ Md, double (*Ms)[kDB + 1]) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int qi = wave >> 1, qj = wave & 1, li = lane & 15, lk = lane >> 4;
-    if (jb * kDB == k0) {
-        for (int x = threadIdx.x; x < kDB * kDB; x += kBlock) Ms[x / kDB][x % kDB] = Md[(size_t)(k0 + x / kDB) * np + k0 + x % kDB];
-        return;
-    }
-    const double* Mkk = Md + (size_t)(k0 + 16 * qi + li) * np + k0;
-    const double* Tkj = Tb + (size_t)k0 * np + kDB * jb + 16 * qj + li;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int s = 0; s < kDB; s += 4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Mkk[s + lk], Tkj[(size_t)(s + lk) * np], acc, 0, 0, 0);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) Ms[16 * qi + lk + 4 * r][16 * qj + li] = -acc[r];
-}
+constexpr int kKc = 32;            // depth chunk
+constexpr int kTile = kLeaf * kLeaf;   // doubles per partial slot
 
-// Update after step k0 (k1 = k0 + kDB), one workgroup per kDB x kDB block,
-// one wave per 16 x 16 quarter, K = kDB on the matrix cores:
-//   blocks [0, nA): A[k1:, k1:] -= P P^T (lower blocks), P = A[k1:, k0:k1];
-//   blocks [nA, ...): T_ij += L_ik M_kj for block rows i > k and columns
-//   j <= k, with M_kj formed from T_kj first; the blocks of row k + 1 also
-//   store M_kj into Md (T_kj is read by other blocks of this launch, so M
-//   lives apart from T).
-__global__ __launch_bounds__(kBlock) void k_chol_update(int np, int k0, int nA, double* __restrict__ A,
-                                                        double* __restrict__ Tb, double* __restrict__ Md) {
-    const int k1 = k0 + kDB;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int li = lane & 15, lk = lane >> 4;
-    if ((int)blockIdx.x >= nA) {
-        __shared__ double Ms[kDB][kDB + 1];
-        const int kb = k0 / kDB;
-        const int b = (int)blockIdx.x - nA;
-        const int ti = b / (kb + 1), jb = b % (kb + 1);
-        inverse_row_block(np, k0, jb, Tb, Md, Ms);
+// One chunk's global loads of one thread (TL / 16 d2 of each operand): X rows rr + 16 u, depth rk, rk + 1; Y
+// likewise, or depth-major: depth ck + (512 / TL) u, columns cj, cj + 1.
+template <int TL>
+struct ChunkRegs {
+    d2 x[TL / 16], y[TL / 16];
+};
+
+// TL x TL output tiles (TL = 64 or 32); each wave computes a (TL / 2) x (TL / 2) quadrant of TW x TW matrix-core
+// tiles of 16 x 16.
+template <int TL>
+__global__ __launch_bounds__(kBlock) void k_gemm(GemmLaunch g) {
+    constexpr int TW = TL / 32, NU = TL / 16, kTs = TL + 2, CW = TL / 2;
+    __shared__ __align__(16) double sX[2][kKc * kTs];
+    __shared__ __align__(16) double sY[2][kKc * kTs];
+    // consecutive items on one XCD (workgroups are dealt to the 8 XCDs in turn), so that items sharing a row
+    // panel share its L2
+    const int b = blockIdx.x, T = g.total;
+    const int xcd = b & 7, q = T >> 3, rem = T & 7;
+    const GemmItem it = g.items[xcd * q + min(xcd, rem) + (b >> 3)];
+    const GemmSide& op = it.side ? g.side[1] : g.side[0];
+    const double* __restrict__ X = op.X;
+    const double* __restrict__ Y = op.Y;
+    const int y_rows = op.y_rows;
+    const int i0 = it.ti * TL, j0 = it.tj * TL, np = g.np, kb = it.kb, ke = it.ke;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4, qi = wave >> 1, qj = wave & 1;
+    // staging: a row-major chunk (TL rows x 32 depth): thread -> rows rr + 16 u, depth rk, rk + 1; a depth-major
+    // one (32 depth x TL columns): thread -> depth ck + (512 / TL) u, columns cj, cj + 1
+    const int rr = tid >> 4, rk = (tid & 15) * 2;
+    const int ck = tid / CW, cj = (tid % CW) * 2;
+    const double* Xp = X + (size_t)(i0 + rr) * np + rk;
+    const double* Yp = y_rows ? Y + (size_t)(j0 + rr) * np + rk : Y + (size_t)ck * np + j0 + cj;
+    auto load = [&](ChunkRegs<TL>& R, int kc) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) R.x[u] = *reinterpret_cast<const d2*>(Xp + (size_t)(16 * u) * np + kc);
+        if (y_rows) {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) R.y[u] = *reinterpret_cast<const d2*>(Yp + (size_t)(16 * u) * np + kc);
+        } else {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) R.y[u] = *reinterpret_cast<const d2*>(Yp + (size_t)(kc + (512 / TL) * u) * np);
+        }
+    };
+    auto store = [&](const ChunkRegs<TL>& R, int buf) {
+        double* x = sX[buf];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            x[rk * kTs + rr + 16 * u] = R.x[u].x;
+            x[(rk + 1) * kTs + rr + 16 * u] = R.x[u].y;
+        }
+        double* y = sY[buf];
+        if (y_rows) {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                y[rk * kTs + rr + 16 * u] = R.y[u].x;
+                y[(rk + 1) * kTs + rr + 16 * u] = R.y[u].y;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) *reinterpret_cast<d2*>(y + (ck + (512 / TL) * u) * kTs + cj) = R.y[u];
+        }
+    };
+    d4 acc[TW][TW];
+#pragma unroll
+    for (int a = 0; a < TW; ++a)
+#pragma unroll
+        for (int c = 0; c < TW; ++c) acc[a][c] = d4{0.0, 0.0, 0.0, 0.0};
+    auto compute = [&](int buf) {
+        const double* x = sX[buf];
+        const double* y = sY[buf];
+#pragma unroll
+        for (int s = 0; s < kKc; s += 4) {
+            double av[TW], bv[TW];
+#pragma unroll
+            for (int a = 0; a < TW; ++a) av[a] = x[(s + lk) * kTs + CW * qi + 16 * a + li];
+#pragma unroll
+            for (int c = 0; c < TW; ++c) bv[c] = y[(s + lk) * kTs + CW * qj + 16 * c + li];
+#pragma unroll
+            for (int a = 0; a < TW; ++a)
+#pragma unroll
+                for (int c = 0; c < TW; ++c)
+                    acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[c], acc[a][c], 0, 0, 0);
+        }
+    };
+    if (kb < ke) {
+        ChunkRegs<TL> RA, RB;
+        load(RA, kb);
+        if (kb + kKc < ke) load(RB, kb + kKc);
+        store(RA, 0);
         __syncthreads();
-        if (ti == 0 && jb < kb)
-            for (int x = threadIdx.x; x < kDB * kDB; x += kBlock)
-                Md[(size_t)(k0 + x / kDB) * np + kDB * jb + x % kDB] = Ms[x / kDB][x % kDB];
-        const int qi = wave >> 1, qj = wave & 1;
-        const int R0 = k1 + kDB * ti + 16 * qi, C0 = kDB * jb + 16 * qj;
-        d4 acc;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = Tb[(size_t)(R0 + lk + 4 * r) * np + C0 + li];
-        const double* Lik = A + (size_t)(R0 + li) * np + k0;
-#pragma unroll
-        for (int s = 0; s < kDB; s += 4)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Lik[s + lk], Ms[s + lk][16 * qj + li], acc, 0, 0, 0);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Tb[(size_t)(R0 + lk + 4 * r) * np + C0 + li] = acc[r];
-        return;
+        // stage 0 holds chunk kc (from RA), RB holds chunk kc + 32; the loop body handles two chunks so that the
+        // register sets keep fixed names (depth ranges are multiples of 64)
+        for (int kc = kb;; kc += 2 * kKc) {
+            if (kc + 2 * kKc < ke) load(RA, kc + 2 * kKc);
+            compute(0);
+            if (kc + kKc >= ke) break;
+            store(RB, 1);
+            __syncthreads();
+            if (kc + 3 * kKc < ke) load(RB, kc + 3 * kKc);
+            compute(1);
+            if (kc + 2 * kKc >= ke) break;
+            store(RA, 0);
+            __syncthreads();
+        }
     }
-    int ti, tj;
-    tri_index(blockIdx.x, ti, tj);
-    const int R0 = k1 + kDB * ti + 16 * (wave >> 1);
-    const int C0 = k1 + kDB * tj + 16 * (wave & 1);
-    if (ti == tj && (wave >> 1) < (wave & 1)) return;   // strictly upper quarter of a diagonal block
-    const double* Pa = A + (size_t)(R0 + li) * np + k0;
-    const double* Pb = A + (size_t)(C0 + li) * np + k0;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    double* C = op.C;
+    const double alpha = op.alpha;
+    if (it.s == 0) {
+        const int accumulate = op.accumulate;
 #pragma unroll
-    for (int s = 0; s < kDB; s += 4) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Pa[s + lk], Pb[s + lk], acc, 0, 0, 0);
+        for (int a = 0; a < TW; ++a)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) A[(size_t)(R0 + lk + 4 * r) * np + C0 + li] -= acc[r];
+            for (int c = 0; c < TW; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    double* p = C + (size_t)(i0 + CW * qi + 16 * a + lk + 4 * r) * np + j0 + CW * qj + 16 * c + li;
+                    const double v = alpha * acc[a][c][r];
+                    *p = accumulate ? *p + v : v;
+                }
+    } else {
+        double* pp = g.part + (size_t)it.part * kTile;
+#pragma unroll
+        for (int a = 0; a < TW; ++a)
+#pragma unroll
+            for (int c = 0; c < TW; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    pp[(CW * qi + 16 * a + lk + 4 * r) * TL + CW * qj + 16 * c + li] = alpha * acc[a][c][r];
+    }
 }
 
-// The last block row of M (no update follows the last step): M_kj for j < k.
-__global__ __launch_bounds__(kBlock) void k_inverse_last_row(int np, int k0, const double* __restrict__ Tb,
-                                                             double* __restrict__ Md) {
-    __shared__ double Ms[kDB][kDB + 1];
-    const int jb = blockIdx.x;
-    inverse_row_block(np, k0, jb, Tb, Md, Ms);
-    __syncthreads();
-    for (int x = threadIdx.x; x < kDB * kDB; x += kBlock)
-        Md[(size_t)(k0 + x / kDB) * np + kDB * jb + x % kDB] = Ms[x / kDB][x % kDB];
+// C += the partials of each sliced tile, in slice order (one element per thread; TL x TL tiles).
+template <int TL>
+__global__ __launch_bounds__(kBlock) void k_gemm_reduce(ReduceLaunch g) {
+    constexpr int per = TL * TL / kBlock;   // workgroups per tile
+    const GemmReduce t = g.tiles[blockIdx.x / per];
+    double* C = t.side ? g.C[1] : g.C[0];
+    const int x = (blockIdx.x % per) * kBlock + threadIdx.x;
+    double* p = C + (size_t)(t.ti * TL + x / TL) * g.np + t.tj * TL + x % TL;
+    double v = *p;
+    for (int sl = 0; sl < t.P - 1; ++sl) v += g.part[(size_t)(t.part + sl) * kTile + x];
+    *p = v;
 }
 
 // Packed rows of the first n rows (row i at i(i+1)/2), and the largest
@@ -269,7 +448,200 @@ __global__ __launch_bounds__(kBlock) void k_gather_support(int n, const int32_t*
     sz[j] = xyz0[3 * (size_t)o + 2] * inv_r;
 }
 
+// One product of the recursion: shape, depth rule and operands (offsets into A, Md, Tb).
+enum DenseBuf { kA = 0, kM = 1, kT = 2 };
+struct ProdSpec {
+    int m, n, k;
+    int krule;   // depth range of tile (ti, tj): 0 all; 1 k < 64 (tj + 1) (Y^T lower); 2 k >= 64 tj (Y lower);
+                 // 3 k < 64 (ti + 1) (X lower)
+    int lower;   // only the tiles with tj <= ti
+    int xb, yb, cb;
+    size_t xo, yo, co;
+    double alpha;
+    int accumulate, y_rows;
+};
+
 }  // namespace
+
+// The launches of a refactorisation of one padded size: leaves and products in
+// order, each product's work items (tile, depth slice) in a device table.
+struct DensePlan {
+    struct Step {
+        int leaf;       // >= 0: leaf at this offset; else a product launch
+        int nspec;
+        ProdSpec spec[2];
+        int64_t item0;  // first work item
+        int total;      // work items
+        int64_t red0;   // first sliced tile
+        int nred;       // sliced tiles (a reduction launch follows when > 0)
+        int tl;         // output tile size of the product launch (64, or 32 for small products)
+    };
+    int np = 0;
+    std::vector<Step> steps;
+    GemmItem* items = nullptr;
+    GemmReduce* red = nullptr;
+    double* part = nullptr;
+    int64_t nitems = 0, nred = 0, npart = 0;
+};
+
+namespace {
+
+// Multiplying by the explicit inverse M11 gives L21 with an error that grows like kappa(L11)^2 u; one step of
+// refinement against L11 itself brings it back to the level of a triangular solve.  Below this size the diagonal
+// blocks are small enough that the product alone is as accurate.
+constexpr int kRefineFrom = 256;
+
+void plan_rec(std::vector<DensePlan::Step>& steps, int np, int o, int nl) {
+    if (nl == 1) {
+        DensePlan::Step st{};
+        st.leaf = o * kLeaf;
+        steps.push_back(st);
+        return;
+    }
+    const int h = (nl + 1) / 2;
+    plan_rec(steps, np, o, h);
+    const int o1 = o * kLeaf, n1 = h * kLeaf, o2 = (o + h) * kLeaf, n2 = (nl - h) * kLeaf;
+    const size_t p11 = (size_t)o1 * np + o1, p21 = (size_t)o2 * np + o1, p22 = (size_t)o2 * np + o2;
+    auto step = [&](std::initializer_list<ProdSpec> sp) {
+        DensePlan::Step st{};
+        st.leaf = -1;
+        for (const ProdSpec& x : sp) st.spec[st.nspec++] = x;
+        steps.push_back(st);
+    };
+    // L21 = A21 M11^T into Tb
+    step({ProdSpec{n2, n1, n1, 1, 0, kA, kM, kT, p21, p11, p21, 1.0, 0, 1}});
+    if (n1 >= kRefineFrom) {
+        // one refinement step: R = A21 - L21 L11^T into A21's place, then L21 += R M11^T
+        step({ProdSpec{n2, n1, n1, 1, 0, kT, kT, kA, p21, p11, p21, -1.0, 1, 1}});
+        step({ProdSpec{n2, n1, n1, 1, 0, kA, kM, kT, p21, p11, p21, 1.0, 1, 1}});
+    }
+    // S = A22 - L21 L21^T (lower tiles) and X = L21 M11 into A21's place
+    step({ProdSpec{n2, n2, n1, 0, 1, kT, kT, kA, p21, p21, p22, -1.0, 1, 1},
+          ProdSpec{n2, n1, n1, 2, 0, kT, kM, kA, p21, p11, p21, 1.0, 0, 0}});
+    plan_rec(steps, np, o + h, nl - h);
+    // M21 = -M22 X
+    step({ProdSpec{n2, n1, n2, 3, 0, kM, kA, kM, p22, p21, p21, -1.0, 0, 0}});
+}
+
+// Depth range of output tile (ti, tj) of size tl, in multiples of 64 (the products' chunk loop takes 64 at a time):
+// the triangular rules hold per element and the leaves store exact zeros above the diagonal, so a range that also
+// covers some of those zeros gives the same sums.
+void depth_range(const ProdSpec& p, int tl, int ti, int tj, int& kb, int& ke) {
+    kb = 0;
+    ke = p.k;
+    const int cj = tj * tl / kLeaf * kLeaf, ci = ti * tl / kLeaf * kLeaf;   // 64-block of the tile's first column / row
+    if (p.krule == 1) ke = std::min(p.k, cj + kLeaf);
+    else if (p.krule == 2) kb = cj;
+    else if (p.krule == 3) ke = std::min(p.k, ci + kLeaf);
+}
+
+// Work items of one launch: tiles of 64, or of 32 when there are fewer than 128 tiles of 64 (so that a small
+// product still spreads over many CUs); the slice depth (a multiple of 64) is chosen so that the launch has about
+// two items per workgroup slot of the chip (2 per CU with 64-tiles, 4 with 32-tiles at their LDS use), and is at
+// least 256: a shallower tile gains less from splitting than the reduction launch costs.
+void plan_items(DensePlan::Step& st, std::vector<GemmItem>& items, std::vector<GemmReduce>& red, int64_t& npart) {
+    int64_t tiles64 = 0;
+    for (int q = 0; q < st.nspec; ++q) {
+        const ProdSpec& p = st.spec[q];
+        const int64_t mt = p.m / kLeaf, nt = p.n / kLeaf;
+        tiles64 += p.lower ? mt * (mt + 1) / 2 : mt * nt;
+    }
+    const int tl = tiles64 < 128 ? 32 : kLeaf;
+    st.tl = tl;
+    int64_t depth = 0;
+    for (int q = 0; q < st.nspec; ++q) {
+        const ProdSpec& p = st.spec[q];
+        for (int ti = 0; ti < p.m / tl; ++ti)
+            for (int tj = 0; tj < p.n / tl; ++tj) {
+                if (p.lower && tj * tl / kLeaf > ti * tl / kLeaf) continue;
+                int kb, ke;
+                depth_range(p, tl, ti, tj, kb, ke);
+                depth += std::max(0, ke - kb);
+            }
+    }
+    const int64_t target = 2 * (tl == kLeaf ? 2 : 4) * 256;
+    int ks = (int)std::min<int64_t>(1 << 20, (depth + target - 1) / target);
+    ks = std::max(4 * kLeaf, (ks + kLeaf - 1) / kLeaf * kLeaf);
+    int32_t part = 0;
+    for (int q = 0; q < st.nspec; ++q) {
+        const ProdSpec& p = st.spec[q];
+        for (int ti = 0; ti < p.m / tl; ++ti)
+            for (int tj = 0; tj < p.n / tl; ++tj) {
+                if (p.lower && tj * tl / kLeaf > ti * tl / kLeaf) continue;
+                int kb, ke;
+                depth_range(p, tl, ti, tj, kb, ke);
+                const int P = std::max(1, (ke - kb + ks - 1) / ks);
+                for (int sl = 0; sl < P; ++sl) {
+                    GemmItem it{};
+                    it.ti = ti;
+                    it.tj = tj;
+                    it.kb = kb + sl * ks;
+                    it.ke = std::min(ke, kb + (sl + 1) * ks);
+                    it.s = sl;
+                    it.part = sl > 0 ? part + sl - 1 : 0;
+                    it.side = q;
+                    items.push_back(it);
+                }
+                if (P > 1) {
+                    red.push_back(GemmReduce{ti, tj, q, P, part, {0, 0, 0}});
+                    part += P - 1;
+                }
+            }
+    }
+    npart = std::max<int64_t>(npart, part);
+}
+
+}  // namespace
+
+void free_dense_plan(DensePlan* p) {
+    if (!p) return;
+    if (p->items) (void)hipFree(p->items);
+    if (p->red) (void)hipFree(p->red);
+    if (p->part) (void)hipFree(p->part);
+    delete p;
+}
+
+size_t dense_plan_bytes(const DensePlan* p) {
+    if (!p) return 0;
+    return sizeof(GemmItem) * (size_t)p->nitems + sizeof(GemmReduce) * (size_t)p->nred +
+           sizeof(double) * kTile * (size_t)p->npart;
+}
+
+hipError_t dense_plan_for(DensePlan*& plan, int n, hipStream_t s) {
+    const int np = dense_padded(n);
+    if (plan && plan->np == np) return hipSuccess;
+    free_dense_plan(plan);
+    plan = nullptr;
+    DensePlan* p = new DensePlan();
+    p->np = np;
+    plan_rec(p->steps, np, 0, np / kLeaf);
+    std::vector<GemmItem> items;
+    std::vector<GemmReduce> red;
+    for (DensePlan::Step& st : p->steps) {
+        if (st.leaf >= 0) continue;
+        st.item0 = (int64_t)items.size();
+        st.red0 = (int64_t)red.size();
+        plan_items(st, items, red, p->npart);
+        st.total = (int)((int64_t)items.size() - st.item0);
+        st.nred = (int)((int64_t)red.size() - st.red0);
+    }
+    p->nitems = (int64_t)items.size();
+    p->nred = (int64_t)red.size();
+    hipError_t e = hipMalloc(&p->items, sizeof(GemmItem) * std::max<size_t>(1, items.size()));
+    if (e == hipSuccess) e = hipMalloc(&p->red, sizeof(GemmReduce) * std::max<size_t>(1, red.size()));
+    if (e == hipSuccess && p->npart > 0) e = hipMalloc(&p->part, sizeof(double) * kTile * (size_t)p->npart);
+    if (e == hipSuccess && !items.empty())
+        e = hipMemcpyAsync(p->items, items.data(), sizeof(GemmItem) * items.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !red.empty())
+        e = hipMemcpyAsync(p->red, red.data(), sizeof(GemmReduce) * red.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);   // the host tables go out of scope
+    if (e != hipSuccess) {
+        free_dense_plan(p);
+        return e;
+    }
+    plan = p;
+    return hipSuccess;
+}
 
 void launch_gather_support(hipStream_t s, Support& sp, int n, const double* xyz0, double inv_r) {
     if (n <= 0) return;
@@ -277,31 +649,44 @@ void launch_gather_support(hipStream_t s, Support& sp, int n, const double* xyz0
                        xyz0, inv_r, sp.sx, sp.sy, sp.sz);
 }
 
-int dense_padded(int n) { return (n + kDB - 1) / kDB * kDB; }
+int dense_padded(int n) { return (n + kLeaf - 1) / kLeaf * kLeaf; }
 
 int dense_pack_blocks() { return 256; }
 
-void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, double* Tb,
-                           int32_t* bad) {
-    const int np = dense_padded(n);
-    const int nbk = np / kDB;
+void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, double* Tb, int32_t* bad,
+                           const DensePlan* plan) {
+    const int np = plan->np;
     const int64_t cnt = (int64_t)np * np;
     hipLaunchKernelGGL(k_assemble, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, np, sp.sx,
                        sp.sy, sp.sz, A);
-    for (int kb = 0; kb < nbk; ++kb) {
-        const int k0 = kb * kDB;
-        const int rows = np - k0 - kDB;
-        const unsigned g = (unsigned)std::max(1, (rows + kBlock - 1) / kBlock);
-        hipLaunchKernelGGL(k_chol_step, dim3(g), dim3(kBlock), 0, s, np, k0, A, Md, bad);
-        const int nt = nbk - kb - 1;
-        if (nt > 0) {
-            const int nA = nt * (nt + 1) / 2, nT = nt * (kb + 1);
-            hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(nA + nT)), dim3(kBlock), 0, s, np, k0, nA, A, Tb, Md);
+    double* bufs[3] = {A, Md, Tb};
+    for (const DensePlan::Step& st : plan->steps) {
+        if (st.leaf >= 0) {
+            hipLaunchKernelGGL(k_leaf64, dim3(1), dim3(kBlock), 0, s, np, st.leaf, A, Md, Tb, bad);
+            continue;
+        }
+        GemmLaunch g{};
+        ReduceLaunch r{};
+        for (int q = 0; q < st.nspec; ++q) {
+            const ProdSpec& p = st.spec[q];
+            g.side[q] = GemmSide{bufs[p.xb] + p.xo, bufs[p.yb] + p.yo, bufs[p.cb] + p.co, p.alpha, p.accumulate, p.y_rows};
+            r.C[q] = bufs[p.cb] + p.co;
+        }
+        g.items = plan->items + st.item0;
+        g.total = st.total;
+        g.np = np;
+        g.part = plan->part;
+        if (st.tl == kLeaf) hipLaunchKernelGGL(k_gemm<kLeaf>, dim3((unsigned)st.total), dim3(kBlock), 0, s, g);
+        else hipLaunchKernelGGL(k_gemm<32>, dim3((unsigned)st.total), dim3(kBlock), 0, s, g);
+        if (st.nred > 0) {
+            r.tiles = plan->red + st.red0;
+            r.np = np;
+            r.part = plan->part;
+            const unsigned per = (unsigned)(st.tl * st.tl / kBlock);
+            if (st.tl == kLeaf) hipLaunchKernelGGL(k_gemm_reduce<kLeaf>, dim3((unsigned)st.nred * per), dim3(kBlock), 0, s, r);
+            else hipLaunchKernelGGL(k_gemm_reduce<32>, dim3((unsigned)st.nred * per), dim3(kBlock), 0, s, r);
         }
     }
-    if (nbk > 1)
-        hipLaunchKernelGGL(k_inverse_last_row, dim3((unsigned)(nbk - 1)), dim3(kBlock), 0, s, np, (nbk - 1) * kDB,
-                           Tb, Md);
 }
 
 void launch_pack_factor(hipStream_t s, int n, const double* Md, double* Mp, const double* old, double* red) {

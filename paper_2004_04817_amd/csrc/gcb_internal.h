@@ -121,6 +121,8 @@ struct Tuning {
 };
 extern Tuning g_tuning;
 
+struct DensePlan;   // dense refactorisation launches (gcb_dense.hip)
+
 }  // namespace gcb
 
 struct gcb_ctx {
@@ -202,6 +204,7 @@ struct gcb_ctx {
     int64_t red_cap = 0;
     void *tmp = nullptr;
     size_t tmp_cap = 0;
+    gcb::DensePlan* dplan = nullptr;   // launches of the dense refactorisation for the last padded size
 };
 
 namespace gcb {

@@ -168,14 +168,20 @@ bool launch_support_weights(hipStream_t s, Support& sp, int n, const double* dis
 void launch_mark_support(hipStream_t s, const Boundary& bd, const Support& sp, int n);
 
 // Dense FP64 refactorisation (matrix cores): A, Md, Tb hold dense_padded(n)^2
-// doubles each, Tb zero on entry; on return the strictly lower blocks of A hold L (Cholesky of
-// Phi_S) below the diagonal blocks, the lower triangle of Md holds L^-1 (its
-// blocks above the diagonal are not written), Tb is scratch, and *bad = 1
-// (set, never cleared) if a pivot was not above kSingularTol.
+// doubles each; on return the lower triangle of Md holds L^-1 and that of Tb
+// holds L (their 64 x 64 blocks above the diagonal are not written), A is
+// scratch, and *bad = 1 (set, never cleared) if a pivot was not above
+// kSingularTol.
 int dense_padded(int n);
 int dense_pack_blocks();
+// The launch sequence of the refactorisation for one padded size (host steps, device work-item table, tile
+// counters and partial buffers); rebuilt when the padded size of n changes.
+struct DensePlan;
+hipError_t dense_plan_for(DensePlan*& plan, int n, hipStream_t s);
+void free_dense_plan(DensePlan* plan);
+size_t dense_plan_bytes(const DensePlan* plan);
 void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, double* Tb,
-                           int32_t* bad);
+                           int32_t* bad, const DensePlan* plan);
 // Packed rows of Md into Mp (may equal old); with old, red[2b], red[2b+1]
 // get per-block max |new - old| and max |old| (dense_pack_blocks() blocks).
 void launch_pack_factor(hipStream_t s, int n, const double* Md, double* Mp, const double* old, double* red);

@@ -753,6 +753,7 @@ size_t ctx_device_bytes(const gcb_ctx* ctx) {
     b += sizeof(double) * (size_t)ctx->lam_cap + (ctx->brec ? sizeof(BlockRec) : 0);
     b += (size_t)ctx->log_cap * (2 * sizeof(int32_t) + 3 * sizeof(double) + 1);   // log and monitor samples
     b += sizeof(double) * (size_t)ctx->red_cap + ctx->tmp_cap + sizeof(GState) + sizeof(IterRec);
+    b += dense_plan_bytes(ctx->dplan);
     return b;
 }
 }  // namespace gcb
@@ -1260,6 +1261,7 @@ void gcb_destroy(gcb_ctx* ctx) {
     if (ctx->sort_tmp) (void)hipFree(ctx->sort_tmp);
     dfree(ctx->log_group); dfree(ctx->log_node); dfree(ctx->log_err); dfree(ctx->log_app); dfree(ctx->mon);
     if (ctx->tmp) (void)hipFree(ctx->tmp);
+    free_dense_plan(ctx->dplan);
     clear_chunk_graphs(ctx);
     for (hipEvent_t e : ctx->ktime_ev) (void)hipEventDestroy(e);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
@@ -1656,8 +1658,8 @@ void rebuild_factor(gcb_ctx* ctx, int n, bool compare, double* drift) {
     ensure_red(ctx);
     HIPCHK(ctx, hipMemsetAsync(bad, 0, sizeof(int32_t), ctx->stream));
     HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    HIPCHK(ctx, hipMemsetAsync(Tb, 0, dense_b, ctx->stream));   // the inverse's block sums start at zero
-    launch_inverse_factor(ctx->stream, sp, n, A, Md, Tb, bad);
+    HIPCHK(ctx, dense_plan_for(ctx->dplan, n, ctx->stream));
+    launch_inverse_factor(ctx->stream, sp, n, A, Md, Tb, bad, ctx->dplan);
     HIPCHK(ctx, hipGetLastError());
     int32_t hbad = 0;
     HIPCHK(ctx, hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, ctx->stream));

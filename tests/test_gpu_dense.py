@@ -1,5 +1,6 @@
-"""Dense FP64 refactorisation on the matrix cores (blocked Cholesky and
-triangular inverse) against the oracle's inverse factor and RC solve."""
+"""Dense FP64 refactorisation on the matrix cores (Cholesky factor and its
+inverse by recursive halving, 64 x 64 leaves) against the oracle's inverse
+factor and RC solve."""
 import numpy as np
 import pytest
 import torch
@@ -37,6 +38,56 @@ def test_set_support_matches_oracle_factor(n):
     if n is None:   # the full selected set meets E*: same certificate as the oracle's run
         assert info["converged"]
         assert info["final_max_err"] == pytest.approx(r.final_max_err, rel=1e-6)
+    c.close()
+
+
+@pytest.mark.parametrize("n", [511, 512, 513, 700, None])
+def test_set_support_recursion_sizes(n):
+    """Sizes around a 64-boundary of the padding and an uneven split (700 -> 11 leaves: 6 + 5): the wing's support
+    set (Nc = 1,135) and prefixes of it, against the oracle's inverse factor (within 1e-8 relative: about
+    n kappa(L) u on this ill-conditioned system, reading R22) and the interpolant of the oracle's weights at
+    2,000 boundary nodes (1e-9 max|d|)."""
+    p = synth.config_wing(with_volume=False)
+    r = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed, nthreads=0)
+    S = r.S if n is None else r.S[:n]
+    c = ctx_for(p)
+    info = c.set_support(S)
+    assert info["nc"] == len(S)
+    M = c.get_factor()
+    Mo = oracle.inverse_factor(p.xyz, S, p.radius)
+    assert np.abs(M - Mo).max() <= 1e-8 * np.abs(Mo).max()
+    Wo = oracle.solve_on_support(p.xyz, S, p.radius, p.disp)
+    idx = np.unique(np.linspace(0, p.nb - 1, 2000).astype(np.int64))
+    got = c.deform(np.ascontiguousarray(p.xyz[idx]))
+    want = oracle.interpolate(p.xyz[S], Wo, p.radius, p.xyz[idx])
+    assert np.abs(got - want).max() <= 1e-9 * p.max_disp
+    if n is None:
+        assert info["converged"]
+        assert info["final_max_err"] == pytest.approx(r.final_max_err, rel=1e-6)
+    c.close()
+
+
+def test_set_support_2000_spread_nodes():
+    """2,000 supports (every 40th wing node, kappa(Phi_S) = 1.1e9): five levels of halving, products on 32- and
+    64-wide tiles, with the deepest tiles split over several workgroups; against the oracle's inverse factor
+    (1e-8 relative, reading R22: n kappa(L) u = 7e-9 here) and the oracle's weights through the interpolant."""
+    p = synth.config_wing(with_volume=False)
+    S = np.arange(0, p.nb, 40)
+    c = ctx_for(p)
+    c.set_params(p.radius, p.m, p.tol_abs, nc_max=len(S), seed=p.seed)
+    info = c.set_support(S)
+    assert info["nc"] == len(S)
+    M = c.get_factor()
+    Mo = oracle.inverse_factor(p.xyz, S, p.radius)
+    assert np.abs(M - Mo).max() <= 1e-8 * np.abs(Mo).max()
+    Wo = oracle.solve_on_support(p.xyz, S, p.radius, p.disp)
+    idx = np.unique(np.linspace(0, p.nb - 1, 2000).astype(np.int64))
+    got = c.deform(np.ascontiguousarray(p.xyz[idx]))
+    want = oracle.interpolate(p.xyz[S], Wo, p.radius, p.xyz[idx])
+    assert np.abs(got - want).max() <= 1e-9 * p.max_disp
+    # the same inputs give the same bits (fixed plan, fixed summation order)
+    drift, _ = c.refactor()
+    assert drift == 0.0
     c.close()
 
 
