@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <initializer_list>
 #include <vector>
 
@@ -68,22 +69,30 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 // R_c / L_cc, final once the earlier columns are applied), then for k > c
 // every lane takes a_k -= a_c L_kc: the lower half's a_ik -= L_ic L_kc and
 // the upper half's R_k -= L_kc M_c, one broadcast of L_kc serving both.
+// The broadcasts are read in groups of eight into separate registers before
+// their products, so that their latency overlaps (also across columns).
 __device__ __forceinline__ void chol_inv32(double (&a)[32], int& sing) {
 #pragma unroll
     for (int c = 0; c < 32; ++c) {
-        double d = readlane_f64(a[c], c);
-        if (!(d > kSingularTol)) {
-            sing = 1;
-            d = 1.0;
-            a[c] = 1.0;
-        }
-        // 1/sqrt(d) by two Newton steps on the hardware estimate
+        const double d0 = readlane_f64(a[c], c);
+        const bool ok = d0 > kSingularTol;
+        sing |= ok ? 0 : 1;
+        const double d = ok ? d0 : 1.0;
+        // 1/sqrt(d) by two Newton steps on the hardware estimate (good to about 2^-24)
         double rs = __builtin_amdgcn_rsq(d);
         rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
         rs = fma(0.5 * rs, fma(-d * rs, rs, 1.0), rs);
         a[c] *= rs;
 #pragma unroll
-        for (int k = c + 1; k < 32; ++k) a[k] = fma(-a[c], readlane_f64(a[c], k), a[k]);
+        for (int k0 = c + 1; k0 < 32; k0 += 8) {
+            double b[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + u < 32) b[u] = readlane_f64(a[c], k0 + u);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + u < 32) a[k0 + u] = fma(-a[c], b[u], a[k0 + u]);
+        }
     }
 }
 
@@ -124,7 +133,10 @@ __global__ __launch_bounds__(kBlock) void k_leaf64(int np, int o, const double* 
         double a[32];
         const int i = lane & 31;
 #pragma unroll
-        for (int t = 0; t < 32; ++t) a[t] = lane < 32 ? (t <= i ? sA[i * kLs + t] : 0.0) : (t == i ? 1.0 : 0.0);
+        for (int t = 0; t < 32; ++t) {   // every lane reads (in bounds); v * keep + one is exact: no branch
+            const double v = sA[i * kLs + t];
+            a[t] = fma(v, (lane < 32 && t <= i) ? 1.0 : 0.0, (lane >= 32 && t == i) ? 1.0 : 0.0);
+        }
         chol_inv32(a, sing);
         if (lane >= 32)   // column i of M11
 #pragma unroll
@@ -172,8 +184,10 @@ __global__ __launch_bounds__(kBlock) void k_leaf64(int np, int o, const double* 
         double a[32];
         const int i = lane & 31;
 #pragma unroll
-        for (int t = 0; t < 32; ++t)
-            a[t] = lane < 32 ? (t <= i ? sA[(32 + i) * kLs + 32 + t] : 0.0) : (t == i ? 1.0 : 0.0);
+        for (int t = 0; t < 32; ++t) {
+            const double v = sA[(32 + i) * kLs + 32 + t];
+            a[t] = fma(v, (lane < 32 && t <= i) ? 1.0 : 0.0, (lane >= 32 && t == i) ? 1.0 : 0.0);
+        }
         chol_inv32(a, sing);
         if (lane >= 32)   // column i of M22
 #pragma unroll
@@ -338,7 +352,23 @@ __global__ __launch_bounds__(kBlock) void k_gemm(GemmLaunch g) {
                     acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[c], acc[a][c], 0, 0, 0);
         }
     };
-    if (kb < ke) {
+    if (kb < ke && TL == 128) {
+        // one chunk's products outlast a load, so one register set in flight is enough (and keeps the
+        // accumulators in registers)
+        ChunkRegs<TL> R;
+        load(R, kb);
+        store(R, 0);
+        __syncthreads();
+        int cur = 0;
+        for (int kc = kb; kc < ke; kc += kKc) {
+            const bool more = kc + kKc < ke;
+            if (more) load(R, kc + kKc);
+            compute(cur);
+            if (more) store(R, cur ^ 1);
+            __syncthreads();
+            cur ^= 1;
+        }
+    } else if (kb < ke) {
         ChunkRegs<TL> RA, RB;
         load(RA, kb);
         if (kb + kKc < ke) load(RB, kb + kKc);
@@ -482,6 +512,10 @@ struct DensePlan {
     GemmReduce* red = nullptr;
     double* part = nullptr;
     int64_t nitems = 0, nred = 0, npart = 0;
+    // the whole sequence captured once for one set of buffers (key), then replayed
+    std::vector<const void*> key;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
 };
 
 namespace {
@@ -515,7 +549,7 @@ void plan_rec(std::vector<DensePlan::Step>& steps, int np, int o, int nl) {
         step({ProdSpec{n2, n1, n1, 1, 0, kT, kT, kA, p21, p11, p21, -1.0, 1, 1}});
         step({ProdSpec{n2, n1, n1, 1, 0, kA, kM, kT, p21, p11, p21, 1.0, 1, 1}});
     }
-    // S = A22 - L21 L21^T (lower tiles) and X = L21 M11 into A21's place
+    // S = A22 - L21 L21^T (lower tiles) and X = L21 M11 into A21's place, in one launch
     step({ProdSpec{n2, n2, n1, 0, 1, kT, kT, kA, p21, p21, p22, -1.0, 1, 1},
           ProdSpec{n2, n1, n1, 2, 0, kT, kM, kA, p21, p11, p21, 1.0, 0, 0}});
     plan_rec(steps, np, o + h, nl - h);
@@ -595,6 +629,8 @@ void plan_items(DensePlan::Step& st, std::vector<GemmItem>& items, std::vector<G
 
 void free_dense_plan(DensePlan* p) {
     if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
     if (p->items) (void)hipFree(p->items);
     if (p->red) (void)hipFree(p->red);
     if (p->part) (void)hipFree(p->part);
@@ -627,6 +663,7 @@ hipError_t dense_plan_for(DensePlan*& plan, int n, hipStream_t s) {
     }
     p->nitems = (int64_t)items.size();
     p->nred = (int64_t)red.size();
+
     hipError_t e = hipMalloc(&p->items, sizeof(GemmItem) * std::max<size_t>(1, items.size()));
     if (e == hipSuccess) e = hipMalloc(&p->red, sizeof(GemmReduce) * std::max<size_t>(1, red.size()));
     if (e == hipSuccess && p->npart > 0) e = hipMalloc(&p->part, sizeof(double) * kTile * (size_t)p->npart);
@@ -653,8 +690,11 @@ int dense_padded(int n) { return (n + kLeaf - 1) / kLeaf * kLeaf; }
 
 int dense_pack_blocks() { return 256; }
 
-void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, double* Tb, int32_t* bad,
-                           const DensePlan* plan) {
+namespace {
+
+// The plan's launches on stream s.
+void issue_plan(hipStream_t s, const Support& sp, int n, double* A, double* Md, double* Tb, int32_t* bad,
+                const DensePlan* plan) {
     const int np = plan->np;
     const int64_t cnt = (int64_t)np * np;
     hipLaunchKernelGGL(k_assemble, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, np, sp.sx,
@@ -667,10 +707,10 @@ void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, d
         }
         GemmLaunch g{};
         ReduceLaunch r{};
-        for (int q = 0; q < st.nspec; ++q) {
-            const ProdSpec& p = st.spec[q];
-            g.side[q] = GemmSide{bufs[p.xb] + p.xo, bufs[p.yb] + p.yo, bufs[p.cb] + p.co, p.alpha, p.accumulate, p.y_rows};
-            r.C[q] = bufs[p.cb] + p.co;
+        for (int k = 0; k < st.nspec; ++k) {
+            const ProdSpec& p = st.spec[k];
+            g.side[k] = GemmSide{bufs[p.xb] + p.xo, bufs[p.yb] + p.yo, bufs[p.cb] + p.co, p.alpha, p.accumulate, p.y_rows};
+            r.C[k] = bufs[p.cb] + p.co;
         }
         g.items = plan->items + st.item0;
         g.total = st.total;
@@ -687,6 +727,35 @@ void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, d
             else hipLaunchKernelGGL(k_gemm_reduce<32>, dim3((unsigned)st.nred * per), dim3(kBlock), 0, s, r);
         }
     }
+}
+
+}  // namespace
+
+hipError_t launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, double* Tb,
+                                 int32_t* bad, DensePlan* plan) {
+    const std::vector<const void*> key = {A, Md, Tb, bad, sp.sx, sp.sy, sp.sz, reinterpret_cast<const void*>((intptr_t)n)};
+    if (!plan->exec || plan->key != key) {
+        if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+        plan->exec = nullptr;
+        plan->key.clear();
+        hipError_t e = hipSuccess;
+        if (!plan->cap) e = hipStreamCreateWithFlags(&plan->cap, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        hipGraph_t graph = nullptr;
+        e = hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        issue_plan(plan->cap, sp, n, A, Md, Tb, bad, plan);
+        e = hipStreamEndCapture(plan->cap, &graph);
+        if (e != hipSuccess) return e;
+        e = hipGraphInstantiate(&plan->exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            plan->exec = nullptr;
+            return e;
+        }
+        plan->key = key;
+    }
+    return hipGraphLaunch(plan->exec, s);
 }
 
 void launch_pack_factor(hipStream_t s, int n, const double* Md, double* Mp, const double* old, double* red) {

@@ -180,8 +180,9 @@ struct DensePlan;
 hipError_t dense_plan_for(DensePlan*& plan, int n, hipStream_t s);
 void free_dense_plan(DensePlan* plan);
 size_t dense_plan_bytes(const DensePlan* plan);
-void launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, double* Tb,
-                           int32_t* bad, const DensePlan* plan);
+// The whole sequence is captured once per buffer set into a graph and replayed on s.
+hipError_t launch_inverse_factor(hipStream_t s, const Support& sp, int n, double* A, double* Md, double* Tb,
+                                 int32_t* bad, DensePlan* plan);
 // Packed rows of Md into Mp (may equal old); with old, red[2b], red[2b+1]
 // get per-block max |new - old| and max |old| (dense_pack_blocks() blocks).
 void launch_pack_factor(hipStream_t s, int n, const double* Md, double* Mp, const double* old, double* red);

@@ -1659,7 +1659,7 @@ void rebuild_factor(gcb_ctx* ctx, int n, bool compare, double* drift) {
     HIPCHK(ctx, hipMemsetAsync(bad, 0, sizeof(int32_t), ctx->stream));
     HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
     HIPCHK(ctx, dense_plan_for(ctx->dplan, n, ctx->stream));
-    launch_inverse_factor(ctx->stream, sp, n, A, Md, Tb, bad, ctx->dplan);
+    HIPCHK(ctx, launch_inverse_factor(ctx->stream, sp, n, A, Md, Tb, bad, ctx->dplan));
     HIPCHK(ctx, hipGetLastError());
     int32_t hbad = 0;
     HIPCHK(ctx, hipMemcpyAsync(&hbad, bad, sizeof(hbad), hipMemcpyDeviceToHost, ctx->stream));
