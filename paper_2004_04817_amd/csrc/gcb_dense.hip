@@ -19,7 +19,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <cstdlib>
 #include <initializer_list>
 #include <vector>
 
@@ -220,7 +219,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf64(int np, int o, const double* 
 // Block products C (m x n) = alpha X Y (+ C), all matrices row-major with the
 // leading dimension np.  X[i][k] at X + i np + k; Y[k][j] at Y + k np + j, or
 // (y_rows) Y given by its rows j: Y[k][j] at Y + j np + k.  Output tiles of
-// 64 x 64 (four waves of 32 x 32); a tile's depth range may be split into
+// TL x TL (64, or 32 for small products; four waves of TL/2 x TL/2); a tile's
+// depth range may be split into
 // slices, one workgroup each (the work items of a launch, built on the host),
 // so that tiles of very different depth (triangular factors) spread evenly
 // over the chip and small products still fill it.  Slice 0 writes C itself
@@ -352,23 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_gemm(GemmLaunch g) {
                     acc[a][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[c], acc[a][c], 0, 0, 0);
         }
     };
-    if (kb < ke && TL == 128) {
-        // one chunk's products outlast a load, so one register set in flight is enough (and keeps the
-        // accumulators in registers)
-        ChunkRegs<TL> R;
-        load(R, kb);
-        store(R, 0);
-        __syncthreads();
-        int cur = 0;
-        for (int kc = kb; kc < ke; kc += kKc) {
-            const bool more = kc + kKc < ke;
-            if (more) load(R, kc + kKc);
-            compute(cur);
-            if (more) store(R, cur ^ 1);
-            __syncthreads();
-            cur ^= 1;
-        }
-    } else if (kb < ke) {
+    if (kb < ke) {
         ChunkRegs<TL> RA, RB;
         load(RA, kb);
         if (kb + kKc < ke) load(RB, kb + kKc);
