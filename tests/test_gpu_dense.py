@@ -133,6 +133,27 @@ def test_refactor_wing_drift_and_same_result():
     c.close()
 
 
+@pytest.mark.parametrize("pos", [100, 150])
+def test_set_support_singular_in_a_later_leaf(pos):
+    """A node that duplicates one already in the set, placed where its pivot is only reached after earlier
+    leaves and the products between them (pos 100: second half of the second leaf; 150: third leaf): the
+    Schur complement pivot is about -4e-16 (NumPy), below 64 eps, so the call fails with GCB_E_SINGULAR."""
+    p = synth.tiny_problem(nb=400, seed=11, m=2)
+    xyz = np.concatenate([p.xyz, p.xyz[40:41]])
+    disp = np.concatenate([p.disp, p.disp[40:41]])
+    c = gcb.Context(0)
+    c.set_boundary(xyz, disp)
+    c.set_params(p.radius, 2, 0.0, seed=p.seed)
+    S = list(range(0, pos)) + [400] + list(range(pos, 200))
+    with pytest.raises(gcb.GcbError) as e:
+        c.set_support(S)
+    assert e.value.code == gcb.GCB_E_SINGULAR
+    # the same set without the duplicate is fine
+    info = c.set_support(list(range(0, 200)))
+    assert info["nc"] == 200
+    c.close()
+
+
 def test_set_support_errors():
     p = synth.tiny_problem(nb=30, seed=4, m=2)
     xyz = np.concatenate([p.xyz, p.xyz[:1]])
