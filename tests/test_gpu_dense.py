@@ -91,6 +91,32 @@ def test_set_support_2000_spread_nodes():
     c.close()
 
 
+def test_set_support_4000_spread_nodes():
+    """4,000 supports (every 20th wing node, kappa(Phi_S) = 6.9e9): the size the benchmark's refactorisation
+    scaling reports, against the oracle's inverse factor within n kappa(L) u (reading R22; at least 1e-8), here
+    3.7e-8 (LAPACK's Cholesky and triangular solve differ from the oracle by 1.9e-8 on this set); bitwise
+    repeatable."""
+    from oracle import brute
+    p = synth.config_wing(with_volume=False)
+    S = np.arange(0, p.nb, 20)
+    n = len(S)
+    c = ctx_for(p)
+    c.set_params(p.radius, p.m, p.tol_abs, nc_max=n, seed=p.seed)
+    info = c.set_support(S)
+    assert info["nc"] == n
+    M = c.get_factor()
+    print("GPU factor done; oracle inverse factor (about 20 s)", flush=True)
+    Mo = oracle.inverse_factor(p.xyz, S, p.radius)
+    ev = np.linalg.eigvalsh(brute.rbf_matrix(p.xyz[S], p.xyz[S], p.radius))
+    bar = max(1e-8, n * np.sqrt(ev[-1] / ev[0]) * np.finfo(np.float64).eps / 2)
+    err = np.abs(M - Mo).max() / np.abs(Mo).max()
+    print(f"kappa {ev[-1] / ev[0]:.2e}: |M - M_oracle| / |M_oracle| = {err:.2e} (bar {bar:.2e})", flush=True)
+    assert err <= bar
+    drift, _ = c.refactor()
+    assert drift == 0.0
+    c.close()
+
+
 def test_set_support_then_deform_and_warm_start():
     p = synth.config_small_ellipsoid(nv=5000)
     r = oracle.select(p.xyz, p.disp, p.radius, p.m, p.tol_abs, seed=p.seed)
