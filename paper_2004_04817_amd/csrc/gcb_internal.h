@@ -118,6 +118,7 @@ struct Tuning {
     int sweep_lpt_max = 256;   // 64, 128 or 256 lanes sharing one target in the group sweep
     bool use_graph = true;     // replay chunks of iterations as captured hipGraphs
     bool probe = true;         // convergence probe at chunk boundaries (GCB_PROBE=0 turns it off)
+    int probe_div = 16;        // ... after max(8, m / probe_div) quiet iterations (GCB_PROBE_DIV)
 };
 extern Tuning g_tuning;
 

@@ -675,9 +675,9 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     if (every > 0) ensure_red(ctx);
     std::vector<int> swept(ktime ? chunk : 0, 0);
     if (ktime) ktime_events(ctx, chunk);
-    // the probe runs once per run of quiet iterations (W changes with every append), after max(8, m / 8) of them
+    // the probe runs once per run of quiet iterations (W changes with every append), after max(8, m / 16) of them
     const bool probe = g_tuning.probe && every == 0 && !ktime;
-    const int probe_after = std::max(8, m / 8);
+    const int probe_after = std::max(8, m / g_tuning.probe_div);
     int64_t probed_n = -1;
     for (;;) {
         HIPCHK(ctx, hipMemcpyAsync(ctx->state_pin, ctx->state, sizeof(GState), hipMemcpyDeviceToHost, ctx->stream));
@@ -1216,6 +1216,10 @@ int gcb_create(gcb_ctx** out, int device, void* hip_stream) {
     }
     if (const char* e = std::getenv("GCB_GRAPH")) g_tuning.use_graph = std::atoi(e) != 0;
     if (const char* e = std::getenv("GCB_PROBE")) g_tuning.probe = std::atoi(e) != 0;
+    if (const char* e = std::getenv("GCB_PROBE_DIV")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 1024) g_tuning.probe_div = v;
+    }
     *out = nullptr;
     gcb_ctx* ctx = new (std::nothrow) gcb_ctx();
     if (!ctx) return GCB_E_NOMEM;
