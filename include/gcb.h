@@ -252,8 +252,9 @@ int gcb_deform_multi(gcb_ctx *ctx, int32_t k_modes, const double *disp_modes, in
 /* Give the context a support set instead of selecting one: idx[0..n) are
  * distinct boundary indices (host or device memory per mem), 3 <= n <=
  * nc_max.  The support system Phi_S (Eqs. 4-5 restricted to S, in this
- * order) is factored from scratch in FP64 (blocked Cholesky and triangular
- * inverse on the matrix cores, M = L^-1), W = M^T (M Delta_S) for the current
+ * order) is factored from scratch in FP64 (Cholesky factor and its inverse
+ * M = L^-1 by recursive halving, the block products on the matrix cores;
+ * Section 2: Phi is SPD), W = M^T (M Delta_S) for the current
  * displacements, and the FP64 all-node certificate fills *info (may be
  * NULL; iterations = 0).  Afterwards the context is as after a finished
  * selection: gcb_deform, gcb_get_support and warm starts work.  Returns
