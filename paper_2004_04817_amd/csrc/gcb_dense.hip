@@ -231,7 +231,10 @@ __global__ __launch_bounds__(kBlock) void k_leaf64(int np, int o, const double* 
 // Depth in chunks of 32 staged in LDS (two stages), with the global loads of
 // the next two chunks in flight in two register sets while a chunk is
 // multiplied; operands stored in LDS depth-major so that each wave reads its
-// matrix-core operands as 16 consecutive doubles.
+// matrix-core operands as 16 consecutive doubles.  Rows of the staged chunk
+// are not padded; instead the column index is XOR-ed with a function of the
+// depth row (lds_swizzle), which keeps both the transposing stores and the
+// operand reads free of LDS bank conflicts.
 struct GemmSide {
     const double* X;
     const double* Y;
@@ -275,11 +278,19 @@ struct ChunkRegs {
     d2 x[TL / 16], y[TL / 16];
 };
 
+// Column swizzle of depth row k of a staged chunk (row length TL, a multiple of 32): bits 1-3 take bits 1-3 of k
+// and bit 4 takes the parity of k and of k / 16.  XOR with it permutes the columns within aligned blocks of 32
+// (so the 16 consecutive doubles of a matrix-core operand stay one permuted block of 16).  Operand reads: the two
+// rows a half-wave reads (k even, k + 1) fall in opposite halves of the banks.  Transposing stores: the 32 lanes
+// of a half-wave (two rows r, 16 depths 2m) land on 32 distinct double slots.  Pairs of columns (even, odd) stay
+// adjacent, so 16-byte stores of a depth-major chunk keep working.
+__device__ __forceinline__ int lds_swizzle(int k) { return (k & 14) | ((((k >> 4) ^ k) & 1) << 4); }
+
 // TL x TL output tiles (TL = 64 or 32); each wave computes a (TL / 2) x (TL / 2) quadrant of TW x TW matrix-core
 // tiles of 16 x 16.
 template <int TL>
 __global__ __launch_bounds__(kBlock) void k_gemm(GemmLaunch g) {
-    constexpr int TW = TL / 32, NU = TL / 16, kTs = TL + 2, CW = TL / 2;
+    constexpr int TW = TL / 32, NU = TL / 16, kTs = TL, CW = TL / 2;
     __shared__ __align__(16) double sX[2][kKc * kTs];
     __shared__ __align__(16) double sY[2][kKc * kTs];
     // consecutive items on one XCD (workgroups are dealt to the 8 XCDs in turn), so that items sharing a row
@@ -315,19 +326,22 @@ __global__ __launch_bounds__(kBlock) void k_gemm(GemmLaunch g) {
         double* x = sX[buf];
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
-            x[rk * kTs + rr + 16 * u] = R.x[u].x;
-            x[(rk + 1) * kTs + rr + 16 * u] = R.x[u].y;
+            x[rk * kTs + ((rr + 16 * u) ^ lds_swizzle(rk))] = R.x[u].x;
+            x[(rk + 1) * kTs + ((rr + 16 * u) ^ lds_swizzle(rk + 1))] = R.x[u].y;
         }
         double* y = sY[buf];
         if (y_rows) {
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
-                y[rk * kTs + rr + 16 * u] = R.y[u].x;
-                y[(rk + 1) * kTs + rr + 16 * u] = R.y[u].y;
+                y[rk * kTs + ((rr + 16 * u) ^ lds_swizzle(rk))] = R.y[u].x;
+                y[(rk + 1) * kTs + ((rr + 16 * u) ^ lds_swizzle(rk + 1))] = R.y[u].y;
             }
         } else {
 #pragma unroll
-            for (int u = 0; u < NU; ++u) *reinterpret_cast<d2*>(y + (ck + (512 / TL) * u) * kTs + cj) = R.y[u];
+            for (int u = 0; u < NU; ++u) {
+                const int k = ck + (512 / TL) * u;
+                *reinterpret_cast<d2*>(y + k * kTs + (cj ^ lds_swizzle(k))) = R.y[u];
+            }
         }
     };
     d4 acc[TW][TW];
@@ -342,9 +356,9 @@ __global__ __launch_bounds__(kBlock) void k_gemm(GemmLaunch g) {
         for (int s = 0; s < kKc; s += 4) {
             double av[TW], bv[TW];
 #pragma unroll
-            for (int a = 0; a < TW; ++a) av[a] = x[(s + lk) * kTs + CW * qi + 16 * a + li];
+            for (int a = 0; a < TW; ++a) av[a] = x[(s + lk) * kTs + ((CW * qi + 16 * a + li) ^ lds_swizzle(s + lk))];
 #pragma unroll
-            for (int c = 0; c < TW; ++c) bv[c] = y[(s + lk) * kTs + CW * qj + 16 * c + li];
+            for (int c = 0; c < TW; ++c) bv[c] = y[(s + lk) * kTs + ((CW * qj + 16 * c + li) ^ lds_swizzle(s + lk))];
 #pragma unroll
             for (int a = 0; a < TW; ++a)
 #pragma unroll
