@@ -198,6 +198,7 @@ struct gcb_ctx {
     void *gmax = nullptr;
     int64_t gmax_cap = 0;
     int64_t probes = 0, probe_skipped = 0;   // of the last selection: probes run, iterations they completed
+    int64_t probed_n = -1;                   // |S| at the last probe (one probe per run of quiet iterations)
     bool probe_cert = false;                 // the successful probe left the certificate (max, sum of e^2)
     double probe_cert_max = 0.0, probe_cert_sum = 0.0;
     // scratch for certificate / volume

@@ -366,6 +366,7 @@ void select_begin(gcb_ctx* ctx) {
     ctx->probes = 0;
     ctx->probe_skipped = 0;
     ctx->probe_cert = false;
+    ctx->probed_n = -1;
     if (ctx->params.warm_start) {
         warm_begin(ctx);
         return;
@@ -659,6 +660,18 @@ bool probe_converged(gcb_ctx* ctx) {
     return true;
 }
 
+// At a chunk or batch-step boundary, with the state just polled: run the probe once per run of quiet
+// iterations (W changes with every append), after max(8, m / 16) of them and while at least 8 remain.
+// True if it ended the selection.
+bool maybe_probe(gcb_ctx* ctx) {
+    const int m = ctx->params.m;
+    const GState& hs = ctx->state_h;
+    if (!g_tuning.probe || ctx->params.monitor_every > 0) return false;
+    if (hs.quiet < std::max(8, m / g_tuning.probe_div) || m - hs.quiet < 8 || hs.n == ctx->probed_n) return false;
+    ctx->probed_n = hs.n;
+    return probe_converged(ctx);
+}
+
 void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     select_begin(ctx);
     const gcb_params& p = ctx->params;
@@ -675,19 +688,11 @@ void run_select(gcb_ctx* ctx, gcb_select_info* info) {
     if (every > 0) ensure_red(ctx);
     std::vector<int> swept(ktime ? chunk : 0, 0);
     if (ktime) ktime_events(ctx, chunk);
-    // the probe runs once per run of quiet iterations (W changes with every append), after max(8, m / 16) of them
-    const bool probe = g_tuning.probe && every == 0 && !ktime;
-    const int probe_after = std::max(8, m / g_tuning.probe_div);
-    int64_t probed_n = -1;
     for (;;) {
         HIPCHK(ctx, hipMemcpyAsync(ctx->state_pin, ctx->state, sizeof(GState), hipMemcpyDeviceToHost, ctx->stream));
         sync(ctx);
         if (!select_poll(ctx, chunk)) break;
-        const GState& hs = ctx->state_h;
-        if (probe && hs.quiet >= probe_after && m - hs.quiet >= 8 && hs.n != probed_n) {
-            probed_n = hs.n;
-            if (probe_converged(ctx)) break;
-        }
+        if (!ktime && maybe_probe(ctx)) break;
         if (gchunk > 0) {
             launch_chunk(ctx, chunk);
         } else {
@@ -853,6 +858,7 @@ int32_t batch_step(gcb_batch* b, gcb_ctx* const* ctxs, int32_t count, int32_t it
         gcb_ctx* c = ctxs[i];
         bool r = false;
         if (c->in_progress) r = select_poll(c, iterations);
+        if (r && maybe_probe(c)) r = false;   // the probe completed the selection's quiet tail
         if (running) running[i] = r ? 1 : 0;
         if (r) run.push_back(c);
     }
