@@ -278,8 +278,8 @@ struct ChunkRegs {
     d2 x[TL / 16], y[TL / 16];
 };
 
-// Column swizzle of depth row k of a staged chunk (row length TL, a multiple of 32): bits 1-3 take bits 1-3 of k
-// and bit 4 takes the parity of k and of k / 16.  XOR with it permutes the columns within aligned blocks of 32
+// Column swizzle of depth row k of a staged chunk (row length TL, a multiple of 32): bits 1-3 are bits 1-3 of k
+// and bit 4 is bit 0 of k XOR bit 4 of k.  XOR with it permutes the columns within aligned blocks of 32
 // (so the 16 consecutive doubles of a matrix-core operand stay one permuted block of 16).  Operand reads: the two
 // rows a half-wave reads (k even, k + 1) fall in opposite halves of the banks.  Transposing stores: the 32 lanes
 // of a half-wave (two rows r, 16 depths 2m) land on 32 distinct double slots.  Pairs of columns (even, odd) stay
