@@ -88,6 +88,39 @@ def test_step_api_small_steps():
         c.close()
 
 
+def test_batch_probe_completes_the_same_run(monkeypatch):
+    """Batch steps of 8 iterations poll often enough for the convergence probe to end the 80,000-node wing's
+    final quiet run (m = 107) inside the batch: the run equals a single selection with the probe off (support
+    sequence, iteration count, groups, appended flags and argmax nodes; weights within 1e-12 relative, errors
+    within 1e-12 max|d|, the certificate within 1e-9 relative) and the oracle's."""
+    probs = [synth.config_wing(with_volume=False), synth.config_small_ellipsoid(with_volume=False)]
+    monkeypatch.setenv("GCB_PROBE", "0")
+    refs = [gpu_select(p) for p in probs]
+    monkeypatch.setenv("GCB_PROBE", "1")
+    ctxs = [make_ctx(p) for p in probs]
+    with gcb.Batch(0) as b:
+        for c in ctxs:
+            b.begin(c)
+        while b.step(ctxs, 8).sum() > 0:
+            pass
+        infos = [b.end(c) for c in ctxs]
+    assert infos[0]["probed_iterations"] > 0
+    for p, c, inf, (c0, i0, S0, W0, l0) in zip(probs, ctxs, infos, refs):
+        assert i0["probed_iterations"] == 0
+        S, W = c.get_support()
+        log = c.get_log()
+        assert np.array_equal(S, S0)
+        assert np.abs(W - W0).max() <= 1e-12 * max(1.0, np.abs(W0).max())
+        assert inf["iterations"] == i0["iterations"] and inf["nc"] == i0["nc"]
+        assert np.array_equal(log.group, l0.group) and np.array_equal(log.appended, l0.appended)
+        assert np.array_equal(log.node, l0.node)
+        assert np.abs(log.err - l0.err).max() <= 1e-12 * p.max_disp
+        assert inf["final_max_err"] == pytest.approx(i0["final_max_err"], rel=1e-9)
+        assert_same_run(p, inf, S, W, log, oracle_select(p), p.tol_abs, p.m)
+        c.close()
+        c0.close()
+
+
 def test_more_than_64_contexts():
     probs = [synth.tiny_problem(nb=16 + (j % 9), seed=100 + j, m=1 + j % 4, tol_rel=0.01) for j in range(70)]
     ctxs = [make_ctx(p) for p in probs]
