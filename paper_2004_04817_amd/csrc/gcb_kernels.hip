@@ -621,7 +621,8 @@ __device__ __forceinline__ void sweep_lanes_body(const SweepArgs& A) {
     const GState st = *A.st;
     if (st.done) return;
     const int n = st.n;
-    const int q = threadIdx.x >> 6, tl = threadIdx.x & 63;
+    // wave-uniform quarter of the supports (readfirstlane: scalar loads of the supports)
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), tl = threadIdx.x & 63;
     const int t = blockIdx.x * kLaneTargets + tl;   // target within the group
     const int p = A.t0 + min(t, A.T - 1);
     const int s0 = (int)((int64_t)n * q / 4), s1 = (int)((int64_t)n * (q + 1) / 4);
@@ -1694,7 +1695,9 @@ __device__ __forceinline__ void all_node_block(int64_t nb, const double* __restr
                                                const double* __restrict__ pdz, const SupportView& sv, int n,
                                                double* __restrict__ red) {
     __shared__ double part[3][4][kCertTargets];
-    const int q = threadIdx.x / kCertTargets, tl = threadIdx.x % kCertTargets;
+    // the quarter of the supports is wave-uniform; readfirstlane says so to the compiler, so the support loads
+    // become scalar loads (SGPR operands) rather than one vector load per lane of the same address
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kCertTargets), tl = threadIdx.x % kCertTargets;
     const int64_t t = blockIdx.x * (int64_t)kCertTargets + tl;
     const bool live = t < nb;
     const int64_t tt = live ? t : nb - 1;
@@ -1739,7 +1742,9 @@ __global__ __launch_bounds__(kBlock) void k_probe_err(int64_t nb, const double* 
                                                       const double* __restrict__ pdz, SupportView sv, int n,
                                                       double* __restrict__ perr) {
     __shared__ double part[3][4][kCertTargets];
-    const int q = threadIdx.x / kCertTargets, tl = threadIdx.x % kCertTargets;
+    // the quarter of the supports is wave-uniform; readfirstlane says so to the compiler, so the support loads
+    // become scalar loads (SGPR operands) rather than one vector load per lane of the same address
+    const int q = __builtin_amdgcn_readfirstlane(threadIdx.x / kCertTargets), tl = threadIdx.x % kCertTargets;
     const int64_t t = blockIdx.x * (int64_t)kCertTargets + tl;
     const bool live = t < nb;
     const int64_t tt = live ? t : nb - 1;
