@@ -91,6 +91,20 @@ def test_capacity_growth_and_cap():
     ctx.close()
 
 
+
+def test_selection_past_one_staging_window():
+    """E* = 0 with Nc^max = 2,000 on the 80,000-node wing: |S| passes the group sweep's 1,280-support staging
+    window (the next window is loaded into registers while one is evaluated), the factor kernels' 1,024-entry
+    prefetch of a row or column of M, and a capacity growth past 1,024; ends at the cap like the oracle."""
+    p = synth.config_wing(with_volume=False)
+    ctx, info, S, W, log = gpu_select(p, tol_abs=0.0, nc_max=2000)
+    r = oracle_select(p, tol_abs=0.0, nc_max=2000)
+    assert info["status"] == 1 and r.status == oracle.ORC_NOT_CONVERGED
+    assert len(S) == 2000 == r.nc
+    assert_same_run(p, info, S, W, log, r, 0.0, p.m, nc_max=2000)
+    ctx.close()
+
+
 def test_explicit_partition_and_start():
     p = synth.config_small_ellipsoid(nb=1500, with_volume=False)
     g = np.random.default_rng(3).integers(0, 7, p.nb).astype(np.int32)
