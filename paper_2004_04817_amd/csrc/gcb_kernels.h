@@ -162,9 +162,8 @@ int launch_iteration(hipStream_t s, const IterCtx& ic, int g, int n_ub, const hi
 void launch_iteration_block(hipStream_t s, const IterCtx& ic, int g, int n_ub, int p);
 int multi_padded_r(int rc);
 // Weights of the kept support set for the displacements disp (nb, 3):
-// W = M^T (M Delta_S) into sp.wx/wy/wz.  Buffers hold n * multi_padded_r(3) doubles each.
-bool launch_support_weights(hipStream_t s, Support& sp, int n, const double* disp, double* Dbuf, double* Ybuf,
-                            double* Wbuf);
+// W = M^T (M Delta_S) into sp.wx/wy/wz.  Dbuf and Ybuf hold 3 n doubles each.
+bool launch_support_weights(hipStream_t s, Support& sp, int n, const double* disp, double* Dbuf, double* Ybuf);
 void launch_mark_support(hipStream_t s, const Boundary& bd, const Support& sp, int n);
 
 // Dense FP64 refactorisation (matrix cores): A, Md, Tb hold dense_padded(n)^2

@@ -147,16 +147,6 @@ __global__ __launch_bounds__(kMWaves * 64) void k_volume_multi(int64_t nv, const
 
 int multi_padded_r(int rc) { return (rc + 15) / 16 * 16; }
 
-__global__ __launch_bounds__(kBlock) void k_scatter_w(int n, int R, const double* __restrict__ W,
-                                                      double* __restrict__ wx, double* __restrict__ wy,
-                                                      double* __restrict__ wz) {
-    const int j = blockIdx.x * kBlock + threadIdx.x;
-    if (j >= n) return;
-    wx[j] = W[(size_t)j * R];
-    wy[j] = W[(size_t)j * R + 1];
-    wz[j] = W[(size_t)j * R + 2];
-}
-
 bool launch_deform_multi(hipStream_t s, const Support& sp, int n, int rc, const double* modes_dev, double* Dbuf,
                          double* Ybuf, double* Wbuf, int64_t nv, const void* xyz, int in_f64, double inv_r, void* out,
                          int out_f64) {
@@ -184,11 +174,94 @@ bool launch_deform_multi(hipStream_t s, const Support& sp, int n, int rc, const 
     return true;
 }
 
-bool launch_support_weights(hipStream_t s, Support& sp, int n, const double* disp, double* Dbuf, double* Ybuf,
-                            double* Wbuf) {
-    if (!launch_deform_multi(s, sp, n, 3, disp, Dbuf, Ybuf, Wbuf, 0, nullptr, 1, 0.0, nullptr, 1)) return false;
-    hipLaunchKernelGGL(k_scatter_w, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n,
-                       multi_padded_r(3), Wbuf, sp.wx, sp.wy, sp.wz);
+// Sum over the 64 lanes of a wave (every lane active): a butterfly over the lane masks 32, 16, ..., 1; both
+// lanes of a pair add the same two values, so every lane ends with the same total.
+__device__ __forceinline__ double wave_total(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// The weights' three displacement columns (Eq. 4 for x, y and z): Y = M D with D = Delta_S (n x 3, row-major),
+// one wave per row of M (packed rows), the lanes over the row's entries with two partial sums per column, then a
+// wave tree.  Every row reads only its own entries of M and of D.
+__global__ __launch_bounds__(kBlock) void k_trmv3_lower(int n, const double* __restrict__ M,
+                                                        const double* __restrict__ D, double* __restrict__ Y) {
+    const int i = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (i >= n) return;   // the whole wave
+    const double* Mi = M + (size_t)i * (i + 1) / 2;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+    int j = lane;
+    for (; j + 64 <= i; j += 128) {
+        const double m0 = Mi[j], m1 = Mi[j + 64];
+        const double* d0 = D + 3 * (size_t)j;
+        const double* d1 = D + 3 * (size_t)(j + 64);
+        a0 = fma(m0, d0[0], a0);
+        a1 = fma(m0, d0[1], a1);
+        a2 = fma(m0, d0[2], a2);
+        b0 = fma(m1, d1[0], b0);
+        b1 = fma(m1, d1[1], b1);
+        b2 = fma(m1, d1[2], b2);
+    }
+    if (j <= i) {
+        const double m0 = Mi[j];
+        const double* d0 = D + 3 * (size_t)j;
+        a0 = fma(m0, d0[0], a0);
+        a1 = fma(m0, d0[1], a1);
+        a2 = fma(m0, d0[2], a2);
+    }
+    const double y0 = wave_total(a0 + b0), y1 = wave_total(a1 + b1), y2 = wave_total(a2 + b2);
+    if (lane == 0) {
+        Y[3 * (size_t)i] = y0;
+        Y[3 * (size_t)i + 1] = y1;
+        Y[3 * (size_t)i + 2] = y2;
+    }
+}
+
+// W = M^T Y for the same three columns, one wave per column j of M (the column-major copy: rows j.. of column j
+// at j cap - j (j - 1) / 2), written straight into the support's weight arrays.
+__global__ __launch_bounds__(kBlock) void k_trmv3_upper(int n, const double* __restrict__ Mc, int64_t cap,
+                                                        const double* __restrict__ Y, double* __restrict__ wx,
+                                                        double* __restrict__ wy, double* __restrict__ wz) {
+    const int j = blockIdx.x * (kBlock / 64) + (int)(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (j >= n) return;   // the whole wave
+    const double* col = Mc + (size_t)j * cap - (size_t)j * (j - 1) / 2;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, b0 = 0.0, b1 = 0.0, b2 = 0.0;
+    int i = j + lane;
+    for (; i + 64 < n; i += 128) {
+        const double m0 = col[i - j], m1 = col[i + 64 - j];
+        const double* y0 = Y + 3 * (size_t)i;
+        const double* y1 = Y + 3 * (size_t)(i + 64);
+        a0 = fma(m0, y0[0], a0);
+        a1 = fma(m0, y0[1], a1);
+        a2 = fma(m0, y0[2], a2);
+        b0 = fma(m1, y1[0], b0);
+        b1 = fma(m1, y1[1], b1);
+        b2 = fma(m1, y1[2], b2);
+    }
+    if (i < n) {
+        const double m0 = col[i - j];
+        const double* y0 = Y + 3 * (size_t)i;
+        a0 = fma(m0, y0[0], a0);
+        a1 = fma(m0, y0[1], a1);
+        a2 = fma(m0, y0[2], a2);
+    }
+    const double w0 = wave_total(a0 + b0), w1 = wave_total(a1 + b1), w2 = wave_total(a2 + b2);
+    if (lane == 0) {
+        wx[j] = w0;
+        wy[j] = w1;
+        wz[j] = w2;
+    }
+}
+
+bool launch_support_weights(hipStream_t s, Support& sp, int n, const double* disp, double* Dbuf, double* Ybuf) {
+    if (n <= 0) return false;
+    const int64_t cnt = 3 * (int64_t)n;
+    hipLaunchKernelGGL(k_gather_modes, dim3((unsigned)((cnt + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, n, 3, 3,
+                       sp.orig, disp, Dbuf);
+    const unsigned g = (unsigned)((n + kBlock / 64 - 1) / (kBlock / 64));
+    hipLaunchKernelGGL(k_trmv3_lower, dim3(g), dim3(kBlock), 0, s, n, sp.M, Dbuf, Ybuf);
+    hipLaunchKernelGGL(k_trmv3_upper, dim3(g), dim3(kBlock), 0, s, n, sp.Mc, sp.cap, Ybuf, sp.wx, sp.wy, sp.wz);
     return true;
 }
 

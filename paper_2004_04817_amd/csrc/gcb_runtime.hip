@@ -332,10 +332,9 @@ void warm_begin(gcb_ctx* ctx) {
     launch_mark_support(ctx->stream, bd, ctx->sp, (int)n);
     HIPCHK(ctx, hipMemsetAsync(ctx->irec, 0, sizeof(IterRec), ctx->stream));
     HIPCHK(ctx, hipEventRecord(ctx->ev0, ctx->stream));
-    const int R = multi_padded_r(3);
-    ensure_tmp(ctx, sizeof(double) * 3 * (size_t)n * R + 256);
+    ensure_tmp(ctx, sizeof(double) * 6 * (size_t)n + 256);
     double* D = static_cast<double*>(ctx->tmp);
-    if (!launch_support_weights(ctx->stream, ctx->sp, (int)n, bd.disp0, D, D + (size_t)n * R, D + 2 * (size_t)n * R))
+    if (!launch_support_weights(ctx->stream, ctx->sp, (int)n, bd.disp0, D, D + 3 * (size_t)n))
         fail(ctx, GCB_E_DEVICE, "internal error: weight recomputation rejected");
     ensure_red(ctx);
     launch_certify(ctx->stream, bd, ctx->sp, (int)n, ctx->red, ctx->red + ctx->red_cap - 2);
@@ -1653,9 +1652,8 @@ void rebuild_factor(gcb_ctx* ctx, int n, bool compare, double* drift) {
     Support& sp = ctx->sp;
     Boundary& bd = ctx->bd;
     const int np = dense_padded(n);
-    const int R = multi_padded_r(3);
     const size_t dense_b = sizeof(double) * (size_t)np * np;
-    const size_t w_b = sizeof(double) * 3 * (size_t)n * R;
+    const size_t w_b = sizeof(double) * 6 * (size_t)n;   // Delta_S and M Delta_S, three columns each
     ensure_tmp(ctx, 3 * dense_b + w_b + 1024);
     char* base = static_cast<char*>(ctx->tmp);
     double* A = reinterpret_cast<double*>(base);
@@ -1680,7 +1678,7 @@ void rebuild_factor(gcb_ctx* ctx, int n, bool compare, double* drift) {
     }
     launch_pack_factor(ctx->stream, n, Md, sp.M, compare ? sp.M : nullptr, ctx->red);
     launch_transpose_factor(ctx->stream, sp.M, sp.Mc, n, sp.cap);
-    if (!launch_support_weights(ctx->stream, sp, n, bd.disp0, Wb, Wb + (size_t)n * R, Wb + 2 * (size_t)n * R))
+    if (!launch_support_weights(ctx->stream, sp, n, bd.disp0, Wb, Wb + 3 * (size_t)n))
         fail(ctx, GCB_E_DEVICE, "internal error: weight recomputation rejected");
     HIPCHK(ctx, hipGetLastError());
     if (compare) {
