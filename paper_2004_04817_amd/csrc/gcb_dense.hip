@@ -428,29 +428,30 @@ __global__ __launch_bounds__(kBlock) void k_gemm_reduce(ReduceLaunch g) {
 
 // Packed rows of the first n rows (row i at i(i+1)/2), and the largest
 // |new - old| and |old| against a previous packed factor (per workgroup).
-__global__ __launch_bounds__(kBlock) void k_pack_rows(int n, int np, const double* __restrict__ Md,
-                                                      double* Mp, const double* old,   // Mp may be old
-                                                      double* __restrict__ red) {
-    __shared__ double sd[kBlock], so[kBlock];
-    const int64_t tri = (int64_t)n * (n + 1) / 2;
+// Workgroup b copies rows b, b + G, b + 2G, ... (G workgroups), its threads
+// along the row.
+__global__ __launch_bounds__(kBigBlock) void k_pack_rows(int n, int np, const double* __restrict__ Md,
+                                                         double* Mp, const double* old,   // Mp may be old
+                                                         double* __restrict__ red) {
+    __shared__ double sd[kBigBlock], so[kBigBlock];
     double dmax = 0.0, omax = 0.0;
-    for (int64_t x = blockIdx.x * (int64_t)kBlock + threadIdx.x; x < tri; x += (int64_t)gridDim.x * kBlock) {
-        int i = (int)((sqrt(8.0 * (double)x + 1.0) - 1.0) * 0.5);
-        while ((int64_t)(i + 1) * (i + 2) / 2 <= x) ++i;
-        while ((int64_t)i * (i + 1) / 2 > x) --i;
-        const int j = (int)(x - (int64_t)i * (i + 1) / 2);
-        const double v = Md[(size_t)i * np + j];
-        if (old) {
-            const double o = old[x];
-            dmax = fmax(dmax, fabs(v - o));
-            omax = fmax(omax, fabs(o));
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const double* src = Md + (size_t)i * np;
+        const size_t r0 = (size_t)i * (i + 1) / 2;
+        for (int j = threadIdx.x; j <= i; j += kBigBlock) {
+            const double v = src[j];
+            if (old) {
+                const double o = old[r0 + j];
+                dmax = fmax(dmax, fabs(v - o));
+                omax = fmax(omax, fabs(o));
+            }
+            Mp[r0 + j] = v;
         }
-        Mp[x] = v;
     }
     sd[threadIdx.x] = dmax;
     so[threadIdx.x] = omax;
     __syncthreads();
-    for (int h = kBlock / 2; h > 0; h >>= 1) {
+    for (int h = kBigBlock / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h) {
             sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + h]);
             so[threadIdx.x] = fmax(so[threadIdx.x], so[threadIdx.x + h]);
@@ -758,8 +759,8 @@ hipError_t launch_inverse_factor(hipStream_t s, const Support& sp, int n, double
 }
 
 void launch_pack_factor(hipStream_t s, int n, const double* Md, double* Mp, const double* old, double* red) {
-    hipLaunchKernelGGL(k_pack_rows, dim3((unsigned)dense_pack_blocks()), dim3(kBlock), 0, s, n, dense_padded(n), Md, Mp,
-                       old, red);
+    hipLaunchKernelGGL(k_pack_rows, dim3((unsigned)dense_pack_blocks()), dim3(kBigBlock), 0, s, n, dense_padded(n), Md,
+                       Mp, old, red);
 }
 
 }  // namespace gcb
