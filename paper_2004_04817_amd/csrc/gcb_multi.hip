@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kBlock) void k_trmm_upper(int n, int R, const doubl
 // of 4 supports a lane evaluates one phi (target l%16, support l/16): the A
 // operand of v_mfma_f64_16x16x4f64; B is W[support][16 t + l%16]; the
 // accumulator of tile t holds out[target (l/16) + 4 r][16 t + l%16].
-constexpr int kMWaves = 8;
+constexpr int kMWaves = 16;
 constexpr int kMChunk = 32;
 constexpr int kMaxR = 192;
 
